@@ -1,0 +1,155 @@
+/*
+ * gpspca.h -- C ABI of the MI355X (gfx950) implementation of the generalized
+ * power method for sparse PCA (GP-SPCA).
+ *
+ * The method (paper, Section 2 and Table 1): for a data matrix A in R^{p x n}
+ * (p samples in rows, n variables in columns a_i), find X on the unit sphere
+ * (m = 1) or on the Stiefel manifold {X in R^{p x m} : X^T X = I_m} (block
+ * forms, 1 <= m <= p) that maximizes one of the four reformulated objectives
+ * of Table 1:
+ *   SL1  F(x) = sum_i [ |a_i^T x| - gamma ]_+^2
+ *   SL0  F(x) = sum_i [ (a_i^T x)^2 - gamma ]_+
+ *   BL1  F(X) = sum_j sum_i [ mu_j |a_i^T x_j| - gamma ]_+^2
+ *   BL0  F(X) = sum_j sum_i [ (mu_j a_i^T x_j)^2 - gamma ]_+
+ * with t_+ = max(0, t).  Each iteration ("pass") computes the correlations
+ * y_ij = a_i^T x_j, thresholds them (soft for l1: s = sign(y)[mu|y| - gamma]_+,
+ * hard for l0: s = mu y where (mu y)^2 > gamma, else 0), forms the ascent
+ * direction G = A S N (N = Diag(mu)), and retracts: x = g / ||g|| (m = 1) or
+ * X = polar factor of G (block).  The sparse loadings of the original form
+ * (Table 1, left column) are Z = S with unit-norm columns.
+ *
+ * Conventions shared by every entry point:
+ *  - Device pointers are HIP device memory owned by the caller; host pointers
+ *    are ordinary host memory.  The library keeps no pointer after a call
+ *    returns.
+ *  - Matrices are column-major.  A is p x n with leading dimension lda >= p.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is stream-ordered; calls that return host results synchronize the
+ *    stream before returning.
+ *  - gamma is absolute and the same for every component; mu (block forms
+ *    only, host, m entries, NULL = all ones) must be positive and finite.
+ *  - The return value is a status: 0 OK, > 0 outputs valid but flagged,
+ *    < 0 error (outputs unspecified).  No exception or abort crosses the ABI.
+ *    gpspca_last_error() gives a message for the calling thread.
+ *  - Arguments are validated on the host before any HIP call.
+ *  - The solve path never allocates device memory: all scratch lives in a
+ *    caller-provided workspace of gpspca_workspace_bytes() bytes.
+ */
+#ifndef GPSPCA_H
+#define GPSPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Formulations (Table 1). */
+#define GPSPCA_SL1 0
+#define GPSPCA_SL0 1
+#define GPSPCA_BL1 2
+#define GPSPCA_BL0 3
+
+/* Storage types of A. */
+#define GPSPCA_F32 0
+#define GPSPCA_BF16 1     /* bfloat16, value = bf16 * col_scale[i] (scale optional) */
+#define GPSPCA_F8E4M3 2   /* OCP float8 e4m3fn, value = fp8 * col_scale[i] (scale required) */
+
+/* Status codes. */
+#define GPSPCA_OK 0
+#define GPSPCA_MAXITER 1      /* stopped at max_iter before the tolerance test held */
+#define GPSPCA_DEGENERATE 2   /* some component had an empty support (completed), or F = 0 */
+#define GPSPCA_EINVAL (-1)    /* invalid argument, or a rank-deficient starting point */
+#define GPSPCA_EDTYPE (-2)    /* unsupported storage type for this call */
+#define GPSPCA_ENOMEM (-3)    /* workspace (or server arena) too small */
+#define GPSPCA_EDEVICE (-4)   /* a HIP runtime error */
+#define GPSPCA_ENONFINITE (-5)/* the objective or the ascent direction became non-finite */
+
+/* Largest number of components handled by the block kernels. */
+#define GPSPCA_MAX_M 64
+
+/* A data matrix (Section 2: p samples x n variables). */
+typedef struct gpspca_matrix {
+    const void* data;        /* device, column-major p x n */
+    int64_t p;               /* rows (samples), >= 1 */
+    int64_t n;               /* columns (variables), >= 1 */
+    int64_t lda;             /* leading dimension in elements, >= p */
+    int32_t dtype;           /* GPSPCA_F32 | GPSPCA_BF16 | GPSPCA_F8E4M3 */
+    int32_t reserved;
+    const float* col_scale;  /* device, n FP32 per-column scales, or NULL (= 1) */
+} gpspca_matrix;
+
+/* Bytes of device workspace that gpspca_solve needs for this problem.
+ * Returns 0 if the arguments are invalid (see gpspca_last_error()). */
+size_t gpspca_workspace_bytes(const gpspca_matrix* A, int form, int m, int max_iter);
+
+/*
+ * Solve one GP-SPCA problem by the power iteration (Section 2, Table 1).
+ *
+ *  A          data matrix (F32, BF16 or F8E4M3 storage; FP32 arithmetic).
+ *  form       GPSPCA_SL1 | SL0 (then m must be 1) | BL1 | BL0 (1 <= m <= min(p, 64)).
+ *  gamma      absolute sparsity weight >= 0.
+ *  mu         host, m weights > 0 for block forms; NULL = all ones; ignored for SL*.
+ *  X0         device p x m starting point (leading dim p), or NULL for the default
+ *             start: the m columns of A with the largest norms (ties to the lower
+ *             index).  The start is projected onto the feasible set (normalized or
+ *             polar factor); a rank-deficient start returns GPSPCA_EINVAL.
+ *  tol        stop when |F_k - F_{k-1}| < tol * |F_{k-1}| (k >= 1); 0 = never.
+ *  max_iter   maximum number of passes (>= 1).
+ *  workspace  device, ws_bytes >= gpspca_workspace_bytes(A, form, m, max_iter),
+ *             256-byte aligned.
+ * Outputs (device unless noted; any except X may be NULL):
+ *  X          p x m (leading dim p): X_k, the iterate of the last pass.
+ *  Z          n x m (leading dim n): thresholded correlations of the last pass with
+ *             unit-norm columns (a column with empty support is all zeros).
+ *  support    ceil(n/32) x m uint32 words: bit (i % 32) of word (j * ceil(n/32) + i/32)
+ *             is set iff Z[i, j] != 0.
+ *  obj_trace  host, max_iter doubles: F_0 .. F_{n_iter-1}.
+ *  n_iter     host: number of passes made.
+ * The iteration stops at pass k when F_k = 0, when the tolerance test holds, or
+ * when k + 1 = max_iter.  Synchronizes `stream` before returning.
+ */
+int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
+                 const float* X0, double tol, int max_iter,
+                 void* workspace, size_t ws_bytes, void* stream,
+                 float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter);
+
+/*
+ * One pass of the iteration at a given feasible point X (device p x m, leading
+ * dim p, used as given: it is not re-projected).  For step-level checks.
+ * Outputs: S (device n x m, leading dim n): thresholded correlations;
+ * G (device p x m doubles, leading dim p): G = A S Diag(mu);
+ * f (host, m doubles): per-component objective terms (F = sum_j f_j);
+ * nnz (host, m int64): per-component support sizes.
+ * Uses the same workspace as gpspca_solve (max_iter = 1).  Synchronizes.
+ */
+int gpspca_step(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
+                const float* X, void* workspace, size_t ws_bytes, void* stream,
+                float* S, double* G, double* f, int64_t* nnz);
+
+/*
+ * Column norms ||a_i||_2 of A (FP64 accumulation) into device `norms` (n doubles).
+ * Stream-ordered; does not synchronize.
+ */
+int gpspca_column_norms(const gpspca_matrix* A, double* norms, void* stream);
+
+/* Message describing the last non-OK status returned on the calling thread. */
+const char* gpspca_last_error(void);
+
+/* Library version string. */
+const char* gpspca_version(void);
+
+/*
+ * Kernel timing for roofline reports.  While enabled, the solve path brackets
+ * every launch of its dominant (A-streaming) kernel with HIP events on the
+ * launch stream.  gpspca_profile_read returns the summed duration (ms), the
+ * launch count, and the name of the kernel, then resets the counters.
+ */
+int gpspca_profile_enable(int on);
+int gpspca_profile_read(double* total_ms, int64_t* launches, char* name, size_t name_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPSPCA_H */

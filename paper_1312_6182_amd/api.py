@@ -1,0 +1,183 @@
+"""Torch-facing wrappers of the GP-SPCA C ABI.
+
+PyTorch provides device memory and the stream; every computation runs in
+libgpspca.so.  A data matrix is a CUDA/HIP tensor ``A`` of shape (p, n) whose
+columns are contiguous (``A.stride(0) == 1``, ``A.stride(1) = lda >= p``), e.g.
+``At.t()`` for a contiguous (n, p) tensor ``At``.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.F32, torch.bfloat16: L.BF16, torch.float8_e4m3fn: L.F8E4M3}
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def matrix(A: torch.Tensor, col_scale: Optional[torch.Tensor] = None) -> L.Matrix:
+    """Describe a column-major device matrix (shape (p, n), stride (1, lda))."""
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D (p, n)")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    if A.dtype not in _DT:
+        raise ValueError(f"unsupported dtype {A.dtype}")
+    p, n = A.shape
+    if n > 1 and A.stride(0) != 1:
+        raise ValueError("columns of A must be contiguous (stride(0) == 1)")
+    lda = A.stride(1) if n > 1 else max(p, 1)
+    if p > 1 and A.stride(0) != 1:
+        raise ValueError("columns of A must be contiguous (stride(0) == 1)")
+    M = L.Matrix()
+    M.data = A.data_ptr()
+    M.p, M.n, M.lda = p, n, lda
+    M.dtype = _DT[A.dtype]
+    M.col_scale = None if col_scale is None else col_scale.data_ptr()
+    return M
+
+
+def column_major(A_rows_are_columns: torch.Tensor) -> torch.Tensor:
+    """View a contiguous (n, p) tensor (row i = column a_i) as the (p, n) matrix A."""
+    return A_rows_are_columns.t()
+
+
+def _mu_array(mu: Optional[Sequence[float]], m: int):
+    if mu is None:
+        return None
+    arr = (ctypes.c_double * m)(*[float(v) for v in mu])
+    if len(mu) != m:
+        raise ValueError("mu must have m entries")
+    return arr
+
+
+def workspace_bytes(A: torch.Tensor, form: int, m: int, max_iter: int,
+                    col_scale: Optional[torch.Tensor] = None) -> int:
+    M = matrix(A, col_scale)
+    nb = L.load().gpspca_workspace_bytes(ctypes.byref(M), form, m, max_iter)
+    if nb == 0:
+        raise L.GpspcaError(L.EINVAL, L.last_error())
+    return int(nb)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+@dataclass
+class SolveResult:
+    X: torch.Tensor          # (p, m) column-major view
+    Z: torch.Tensor          # (n, m) column-major view, unit-norm columns or 0
+    support: torch.Tensor    # (m, ceil(n/32)) int32 bit words
+    trace: list              # objective F_0 .. F_{n_iter-1}
+    n_iter: int
+    status: int
+
+    def support_mask(self) -> torch.Tensor:
+        """Boolean (n, m) support decoded from the bit words."""
+        m, nw = self.support.shape
+        n = self.Z.shape[0]
+        bits = torch.arange(32, device=self.support.device, dtype=torch.int32)
+        words = self.support.to(torch.int64) & 0xFFFFFFFF
+        mask = ((words[:, :, None] >> bits[None, None, :]) & 1).bool()
+        return mask.reshape(m, nw * 32)[:, :n].t()
+
+
+def solve(A: torch.Tensor, form: int, m: int = 1, gamma: float = 0.0,
+          mu: Optional[Sequence[float]] = None, X0: Optional[torch.Tensor] = None,
+          tol: float = 1e-4, max_iter: int = 1000, col_scale: Optional[torch.Tensor] = None,
+          stream: Optional[torch.cuda.Stream] = None,
+          workspace: Optional[torch.Tensor] = None) -> SolveResult:
+    """Run the GP-SPCA power iteration (gpspca_solve) on device tensor A (p, n)."""
+    lib = L.load()
+    M = matrix(A, col_scale)
+    p, n = A.shape
+    dev = A.device
+    nb = workspace_bytes(A, form, m, max_iter, col_scale)
+    ws = workspace if workspace is not None and workspace.numel() >= nb else _workspace(nb, dev)
+    Xt = torch.empty((m, p), dtype=torch.float32, device=dev)
+    Zt = torch.empty((m, n), dtype=torch.float32, device=dev)
+    nw = (n + 31) // 32
+    sup = torch.empty((m, nw), dtype=torch.int32, device=dev)
+    trace = (ctypes.c_double * max_iter)()
+    nit = ctypes.c_int(0)
+    x0p = None
+    if X0 is not None:
+        X0c = X0.t().contiguous() if X0.dim() == 2 else X0.reshape(1, -1).contiguous()
+        if X0c.shape != (m, p) or X0c.dtype != torch.float32:
+            raise ValueError("X0 must be a float32 (p, m) tensor")
+        x0p = X0c.data_ptr()
+    rc = lib.gpspca_solve(ctypes.byref(M), form, m, float(gamma), _mu_array(mu, m), x0p,
+                          float(tol), int(max_iter), ws.data_ptr(), ws.numel(), _stream_ptr(stream),
+                          Xt.data_ptr(), Zt.data_ptr(), sup.data_ptr(), trace, ctypes.byref(nit))
+    L.check(rc, "gpspca_solve")
+    k = nit.value
+    return SolveResult(X=Xt.t(), Z=Zt.t(), support=sup, trace=list(trace[:k]), n_iter=k,
+                       status=rc)
+
+
+@dataclass
+class StepResult:
+    S: torch.Tensor   # (n, m) thresholded correlations
+    G: torch.Tensor   # (p, m) float64 ascent direction A S Diag(mu)
+    f: list           # per-component objective terms
+    nnz: list         # per-component support sizes
+
+    @property
+    def F(self) -> float:
+        return float(sum(self.f))
+
+
+def step(A: torch.Tensor, form: int, X: torch.Tensor, gamma: float,
+         mu: Optional[Sequence[float]] = None, col_scale: Optional[torch.Tensor] = None,
+         stream: Optional[torch.cuda.Stream] = None) -> StepResult:
+    """One pass at the feasible point X (p, m) (gpspca_step)."""
+    lib = L.load()
+    M = matrix(A, col_scale)
+    p, n = A.shape
+    Xc = X.reshape(p, -1)
+    m = Xc.shape[1]
+    Xt = Xc.t().contiguous().to(torch.float32)
+    nb = workspace_bytes(A, form, m, 1, col_scale)
+    ws = _workspace(nb, A.device)
+    St = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    Gt = torch.empty((m, p), dtype=torch.float64, device=A.device)
+    f = (ctypes.c_double * m)()
+    nnz = (ctypes.c_int64 * m)()
+    rc = lib.gpspca_step(ctypes.byref(M), form, m, float(gamma), _mu_array(mu, m), Xt.data_ptr(),
+                         ws.data_ptr(), ws.numel(), _stream_ptr(stream), St.data_ptr(),
+                         Gt.data_ptr(), f, nnz)
+    L.check(rc, "gpspca_step")
+    return StepResult(S=St.t(), G=Gt.t(), f=list(f), nnz=list(nnz))
+
+
+def column_norms(A: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    lib = L.load()
+    M = matrix(A)
+    out = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+    L.check(lib.gpspca_column_norms(ctypes.byref(M), out.data_ptr(), _stream_ptr(stream)),
+            "gpspca_column_norms")
+    return out
+
+
+def profile_enable(on: bool = True) -> None:
+    L.load().gpspca_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """(total_ms, launches, kernel name) of the dominant kernel since the last read."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    buf = ctypes.create_string_buffer(128)
+    L.load().gpspca_profile_read(ctypes.byref(ms), ctypes.byref(cnt), buf, 128)
+    return ms.value, cnt.value, buf.value.decode()

@@ -1,0 +1,523 @@
+// C ABI of the gfx950 GP-SPCA library: argument validation, workspace layout,
+// kernel selection and the iteration driver.
+//
+// Per pass k (Section 2, Table 1):
+//   m = 1, p <= 20480   k_pass_m1 (one read of A; correlation, threshold and
+//                       back-projection fused)
+//   otherwise           k_corr (correlation + threshold, one read of A) and
+//                       k_backproj (reads only the columns in the support)
+//   then                k_reduce_partials -> k_gram -> k_stop -> k_apply
+// The stopping rule runs on the device; the host polls the control block once
+// per chunk of passes and never per pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gpspca_internal.h"
+
+namespace gpspca {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define GPSPCA_HIP(expr)                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(GPSPCA_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- device info
+static int device_cus(int* out) {
+    static std::mutex mu;
+    static int cached[64] = {0};
+    int dev = 0;
+    GPSPCA_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev < 0 || dev >= 64) return fail(GPSPCA_EDEVICE, "device index out of range");
+    if (cached[dev] == 0) {
+        int cus = 0;
+        GPSPCA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        cached[dev] = cus > 0 ? cus : 1;
+    }
+    *out = cached[dev];
+    return GPSPCA_OK;
+}
+
+// ----------------------------------------------------------------- validation
+static int check_matrix(const gpspca_matrix* A) {
+    if (!A) return fail(GPSPCA_EINVAL, "A is NULL");
+    if (!A->data) return fail(GPSPCA_EINVAL, "A->data is NULL");
+    if (A->p < 1 || A->n < 1) return fail(GPSPCA_EINVAL, "p and n must be >= 1");
+    if (A->p > (int64_t)1 << 30) return fail(GPSPCA_EINVAL, "p must be <= 2^30");
+    if (A->lda < A->p) return fail(GPSPCA_EINVAL, "lda must be >= p");
+    if (A->dtype != GPSPCA_F32) {
+        if (A->dtype == GPSPCA_BF16 || A->dtype == GPSPCA_F8E4M3)
+            return fail(GPSPCA_EDTYPE, "reduced-precision storage is not supported by this entry point");
+        return fail(GPSPCA_EDTYPE, "unknown dtype");
+    }
+    return GPSPCA_OK;
+}
+
+static int check_problem(const gpspca_matrix* A, int form, int m, double gamma, const double* mu) {
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    if (form < GPSPCA_SL1 || form > GPSPCA_BL0) return fail(GPSPCA_EINVAL, "unknown formulation");
+    const bool block = form >= GPSPCA_BL1;
+    if (!block && m != 1) return fail(GPSPCA_EINVAL, "single-unit formulations need m = 1");
+    if (m < 1 || m > A->p) return fail(GPSPCA_EINVAL, "need 1 <= m <= p");
+    if (m > kMaxM) return fail(GPSPCA_EINVAL, "m exceeds GPSPCA_MAX_M");
+    if (!std::isfinite(gamma) || gamma < 0.0) return fail(GPSPCA_EINVAL, "gamma must be finite and >= 0");
+    if (block && mu) {
+        for (int j = 0; j < m; ++j)
+            if (!std::isfinite(mu[j]) || !(mu[j] > 0.0))
+                return fail(GPSPCA_EINVAL, "mu must be finite and > 0");
+    }
+    return GPSPCA_OK;
+}
+
+// ----------------------------------------------------------------------- plan
+static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int ncu, Plan* pl) {
+    std::memset(pl, 0, sizeof(Plan));
+    pl->p = A->p;
+    pl->n = A->n;
+    pl->lda = A->lda;
+    pl->m = m;
+    pl->form = form;
+    pl->l0 = (form == GPSPCA_SL0 || form == GPSPCA_BL0) ? 1 : 0;
+    pl->max_iter = max_iter;
+    pl->ldx = (int)align_up((size_t)A->p, 4);
+    pl->vec4 = ((A->lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A->data) & 15) == 0);
+    const int64_t nq = cdiv(A->p, 4);
+
+    pl->fused_m1 = (m == 1 && A->p <= 20480) ? 1 : 0;
+    if (pl->fused_m1) {
+        const int cand[4] = {64, 256, 512, 1024};
+        int T = 1024;
+        for (int c : cand)
+            if (cdiv(nq, c) <= 5) { T = c; break; }
+        pl->m1_threads = T;
+        pl->m1_kq = (int)std::max<int64_t>(1, cdiv(nq, T));
+        const int per_cu = T <= 64 ? 8 : T <= 256 ? 2 : 1;
+        int64_t grid = (int64_t)ncu * per_cu;
+        grid = std::min<int64_t>(grid, std::max<int64_t>(1, A->n / 8));
+        pl->m1_grid = (int)std::max<int64_t>(1, grid);
+        pl->npart = pl->m1_grid;
+        pl->nwave_part = pl->m1_grid;
+    } else {
+        pl->corr_M = m >= 5 ? 8 : m >= 3 ? 4 : m == 2 ? 2 : 1;
+        int64_t grid = std::min<int64_t>((int64_t)ncu * 2, std::max<int64_t>(1, cdiv(A->n, 32)));
+        pl->corr_grid = (int)std::max<int64_t>(1, grid);
+        pl->nwave_part = pl->corr_grid * 4;
+        pl->bp_kq = 2;
+        pl->bp_rb = (int)cdiv(nq, 256 * pl->bp_kq);
+        int64_t cr = std::min<int64_t>(cdiv(A->n, 1024), std::max<int64_t>(1, (4LL * ncu) / pl->bp_rb));
+        pl->bp_cr = (int)std::max<int64_t>(1, cr);
+        pl->npart = pl->bp_cr;
+    }
+    const int64_t ne = (int64_t)m * pl->ldx;
+    const int64_t bx = cdiv(ne, 256);
+    int64_t split = cdiv(2LL * ncu, bx);
+    split = std::min<int64_t>(split, std::max<int64_t>(1, pl->npart / 8));
+    split = std::min<int64_t>(split, 64);
+    pl->red_split = (int)std::max<int64_t>(1, split);
+    pl->gram_rows = ((size_t)(m + 1) * 256 * 16 <= 140000) ? 256 : 128;
+    pl->gram_grid = (int)cdiv(A->p, pl->gram_rows);
+    pl->fin_grid = (int)std::max<int64_t>(1, cdiv(cdiv(A->n, 32), 256));
+    pl->topm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(A->n, 1024)));
+
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1), 256);
+        return at;
+    };
+    const size_t P = (size_t)A->p, N = (size_t)A->n, M = (size_t)m, L = (size_t)pl->ldx;
+    pl->o_ctrl = take(sizeof(Ctrl));
+    pl->o_trace = take(sizeof(double) * (size_t)std::max(1, max_iter));
+    pl->o_x0 = take(sizeof(float) * L * M);
+    pl->o_x1 = take(sizeof(float) * L * M);
+    pl->o_s = take(sizeof(float) * N * M);
+    pl->o_act = take(N);
+    pl->o_gpart = take(sizeof(float) * (size_t)pl->npart * M * L);
+    pl->o_touched = take(sizeof(int) * (size_t)pl->npart);
+    pl->o_fpart = take(sizeof(double) * (size_t)pl->nwave_part * M);
+    pl->o_nnzpart = take(sizeof(int) * (size_t)pl->nwave_part * M);
+    pl->o_l1 = take(sizeof(double) * (size_t)pl->red_split * M * L);
+    pl->o_g64 = take(sizeof(double) * M * P);
+    pl->o_gram = take(sizeof(double) * (size_t)pl->gram_grid * 3 * M * M);
+    pl->o_coef = take(sizeof(double) * 5 * M * M);
+    pl->o_norms = take(sizeof(double) * N);
+    pl->o_cand_v = take(sizeof(double) * (size_t)pl->topm_grid * M);
+    pl->o_cand_i = take(sizeof(int64_t) * (size_t)pl->topm_grid * M);
+    pl->o_idx = take(sizeof(int64_t) * M);
+    pl->o_fin = take(sizeof(double) * (size_t)pl->fin_grid * M);
+    pl->o_invn = take(sizeof(double) * M);
+    pl->o_fcomp = take(sizeof(double) * 2 * M);
+    pl->total = o;
+}
+
+struct Ptrs {
+    Ctrl* ctrl;
+    double* trace;
+    float* x[2];
+    float* S;
+    uint8_t* act;
+    float* gpart;
+    int* touched;
+    double* fpart;
+    int* nnzpart;
+    double* l1;
+    double* g64;
+    double* gram;
+    double* coef;
+    double* norms;
+    double* cand_v;
+    int64_t* cand_i;
+    int64_t* idx;
+    double* fin;
+    double* invn;
+    double* fcomp;
+};
+
+static Ptrs carve(const Plan& pl, void* ws) {
+    char* b = static_cast<char*>(ws);
+    Ptrs P;
+    P.ctrl = reinterpret_cast<Ctrl*>(b + pl.o_ctrl);
+    P.trace = reinterpret_cast<double*>(b + pl.o_trace);
+    P.x[0] = reinterpret_cast<float*>(b + pl.o_x0);
+    P.x[1] = reinterpret_cast<float*>(b + pl.o_x1);
+    P.S = reinterpret_cast<float*>(b + pl.o_s);
+    P.act = reinterpret_cast<uint8_t*>(b + pl.o_act);
+    P.gpart = reinterpret_cast<float*>(b + pl.o_gpart);
+    P.touched = reinterpret_cast<int*>(b + pl.o_touched);
+    P.fpart = reinterpret_cast<double*>(b + pl.o_fpart);
+    P.nnzpart = reinterpret_cast<int*>(b + pl.o_nnzpart);
+    P.l1 = reinterpret_cast<double*>(b + pl.o_l1);
+    P.g64 = reinterpret_cast<double*>(b + pl.o_g64);
+    P.gram = reinterpret_cast<double*>(b + pl.o_gram);
+    P.coef = reinterpret_cast<double*>(b + pl.o_coef);
+    P.norms = reinterpret_cast<double*>(b + pl.o_norms);
+    P.cand_v = reinterpret_cast<double*>(b + pl.o_cand_v);
+    P.cand_i = reinterpret_cast<int64_t*>(b + pl.o_cand_i);
+    P.idx = reinterpret_cast<int64_t*>(b + pl.o_idx);
+    P.fin = reinterpret_cast<double*>(b + pl.o_fin);
+    P.invn = reinterpret_cast<double*>(b + pl.o_invn);
+    P.fcomp = reinterpret_cast<double*>(b + pl.o_fcomp);
+    return P;
+}
+
+static PassParams make_params(const gpspca_matrix* A, const Plan& pl, double gamma,
+                              const double* mu) {
+    PassParams pp;
+    std::memset(&pp, 0, sizeof(pp));
+    pp.A = static_cast<const float*>(A->data);
+    pp.scale = A->col_scale;
+    pp.lda = A->lda;
+    pp.n = A->n;
+    pp.p = (int)A->p;
+    pp.ldx = pl.ldx;
+    pp.m = pl.m;
+    pp.l0 = pl.l0;
+    pp.gamma = gamma;
+    const bool block = pl.form >= GPSPCA_BL1;
+    for (int j = 0; j < kMaxM; ++j) {
+        const double v = (block && mu && j < pl.m) ? mu[j] : 1.0;
+        pp.mu[j] = v;
+        pp.muf[j] = (float)v;
+    }
+    return pp;
+}
+
+// ------------------------------------------------------------------ profiling
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    double total_ms = 0.0;
+    int64_t launches = 0;
+    std::string name;
+};
+static Prof g_prof;
+
+struct TimedLaunches {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    bool on = false;
+    ~TimedLaunches() {
+        for (auto& e : ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+    hipError_t begin(hipStream_t st) {
+        if (!on) return hipSuccess;
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        ev.emplace_back(a, b);
+        return hipEventRecord(a, st);
+    }
+    hipError_t end(hipStream_t st) {
+        if (!on) return hipSuccess;
+        return hipEventRecord(ev.back().second, st);
+    }
+    void collect(const char* name) {
+        if (!on) return;
+        double tot = 0.0;
+        for (auto& e : ev) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) tot += ms;
+        }
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        g_prof.total_ms += tot;
+        g_prof.launches += (int64_t)ev.size();
+        g_prof.name = name;
+    }
+};
+
+// ----------------------------------------------------------------- driver
+static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int k,
+                        hipStream_t st, TimedLaunches& tl) {
+    const float* Xk = P.x[k & 1];
+    float* Xn = P.x[(k + 1) & 1];
+    GPSPCA_HIP(tl.begin(st));
+    if (pl.fused_m1) {
+        GPSPCA_HIP(launch_pass_m1(pl, pp, Xk, P.S, P.gpart, P.fpart, P.nnzpart, P.ctrl, st));
+        GPSPCA_HIP(tl.end(st));
+        GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, nullptr, P.l1, P.ctrl, st));
+    } else {
+        GPSPCA_HIP(launch_corr(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+        GPSPCA_HIP(tl.end(st));
+        GPSPCA_HIP(launch_backproj(pl, pp, P.S, P.act, P.gpart, P.touched, P.ctrl, st));
+        GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, P.touched, P.l1, P.ctrl, st));
+    }
+    GPSPCA_HIP(launch_gram(pl, P.l1, pl.red_split, Xk, pl.m > 1 ? 1 : 0, P.g64, P.gram, P.ctrl, st));
+    GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp, P.ctrl, st));
+    GPSPCA_HIP(launch_apply(pl, P.g64, Xk, P.coef, Xn, P.ctrl, st));
+    return GPSPCA_OK;
+}
+
+struct Pinned {
+    Ctrl* snap = nullptr;
+    ~Pinned() {
+        if (snap) (void)hipHostFree(snap);
+    }
+};
+static thread_local Pinned t_pinned;
+
+static int pinned_ctrl(Ctrl** out) {
+    if (!t_pinned.snap) {
+        void* p = nullptr;
+        GPSPCA_HIP(hipHostMalloc(&p, sizeof(Ctrl), hipHostMallocDefault));
+        t_pinned.snap = static_cast<Ctrl*>(p);
+    }
+    *out = t_pinned.snap;
+    return GPSPCA_OK;
+}
+
+static const char* status_text(int s) {
+    switch (s) {
+        case GPSPCA_EINVAL: return "rank-deficient or zero starting point";
+        case GPSPCA_ENONFINITE: return "objective or ascent direction became non-finite";
+        default: return "device error";
+    }
+}
+
+}  // namespace gpspca
+
+using namespace gpspca;
+
+extern "C" {
+
+const char* gpspca_last_error(void) { return g_err.c_str(); }
+
+const char* gpspca_version(void) { return "gpspca-gfx950 0.1"; }
+
+size_t gpspca_workspace_bytes(const gpspca_matrix* A, int form, int m, int max_iter) {
+    if (check_problem(A, form, m, 0.0, nullptr) != GPSPCA_OK) return 0;
+    if (max_iter < 1) {
+        fail(GPSPCA_EINVAL, "max_iter must be >= 1");
+        return 0;
+    }
+    int ncu = 0;
+    if (device_cus(&ncu) != GPSPCA_OK) return 0;
+    Plan pl;
+    make_plan(A, form, m, max_iter, ncu, &pl);
+    return pl.total;
+}
+
+int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
+                 const float* X0, double tol, int max_iter, void* workspace, size_t ws_bytes,
+                 void* stream, float* X, float* Z, uint32_t* support, double* obj_trace,
+                 int* n_iter) {
+    int rc = check_problem(A, form, m, gamma, mu);
+    if (rc) return rc;
+    if (!std::isfinite(tol) || tol < 0.0) return fail(GPSPCA_EINVAL, "tol must be finite and >= 0");
+    if (max_iter < 1) return fail(GPSPCA_EINVAL, "max_iter must be >= 1");
+    if (!X) return fail(GPSPCA_EINVAL, "X is NULL");
+    if (!workspace) return fail(GPSPCA_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(GPSPCA_EINVAL, "workspace must be 256-byte aligned");
+    if (!X0 && m > A->n) return fail(GPSPCA_EINVAL, "default start needs m <= n");
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int ncu = 0;
+    rc = device_cus(&ncu);
+    if (rc) return rc;
+    Plan pl;
+    make_plan(A, form, m, max_iter, ncu, &pl);
+    if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
+    const Ptrs P = carve(pl, workspace);
+    const PassParams pp = make_params(A, pl, gamma, mu);
+
+    // start: project X0 (or the top-m norm columns) onto the feasible set
+    GPSPCA_HIP(launch_ctrl_reset(P.ctrl, max_iter, tol, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * m, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * m, st));
+    if (X0) {
+        GPSPCA_HIP(launch_load_g64(pl, X0, (int)A->p, P.g64, st));
+    } else {
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
+        GPSPCA_HIP(launch_colnorm(pp, P.norms, grid, st));
+        GPSPCA_HIP(launch_topm(pl, P.norms, P.cand_v, P.cand_i, P.idx, st));
+        GPSPCA_HIP(launch_gather(pl, pp, P.idx, P.g64, st));
+    }
+    GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
+    GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
+    GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+
+    TimedLaunches tl;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        tl.on = g_prof.on;
+    }
+    Ctrl* snap = nullptr;
+    rc = pinned_ctrl(&snap);
+    if (rc) return rc;
+    int kk = 0;
+    int chunk = (tol == 0.0) ? max_iter : 1;
+    while (kk < max_iter) {
+        const int c = std::min(chunk, max_iter - kk);
+        for (int i = 0; i < c; ++i) {
+            rc = enqueue_pass(pl, pp, P, kk + i, st, tl);
+            if (rc) return rc;
+        }
+        kk += c;
+        if (kk >= max_iter) break;
+        GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        GPSPCA_HIP(hipStreamSynchronize(st));
+        if (snap->done) break;
+        chunk = std::min(chunk * 2, 32);
+    }
+    GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    GPSPCA_HIP(hipStreamSynchronize(st));
+    tl.collect(pl.fused_m1 ? "k_pass_m1" : "k_corr");
+    const Ctrl fin = *snap;
+    if (fin.status < 0) return fail(fin.status, status_text(fin.status));
+    if (fin.n_iter < 1) return fail(GPSPCA_EDEVICE, "solve ended without a pass");
+
+    const float* Xf = P.x[(fin.n_iter - 1) & 1];
+    GPSPCA_HIP(launch_copy_x(pl, Xf, X, st));
+    GPSPCA_HIP(launch_finalize(pl, P.S, P.fin, P.invn, Z, support, st));
+    if (obj_trace)
+        GPSPCA_HIP(hipMemcpyAsync(obj_trace, P.trace, sizeof(double) * fin.n_iter,
+                                  hipMemcpyDeviceToHost, st));
+    GPSPCA_HIP(hipStreamSynchronize(st));
+    if (n_iter) *n_iter = fin.n_iter;
+    if (fin.status != GPSPCA_OK) {
+        g_err = fin.status == GPSPCA_MAXITER ? "stopped at max_iter" : "degenerate components";
+    }
+    return fin.status;
+}
+
+int gpspca_step(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
+                const float* Xin, void* workspace, size_t ws_bytes, void* stream, float* S,
+                double* G, double* f, int64_t* nnz) {
+    int rc = check_problem(A, form, m, gamma, mu);
+    if (rc) return rc;
+    if (!Xin) return fail(GPSPCA_EINVAL, "X is NULL");
+    if (!workspace) return fail(GPSPCA_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(GPSPCA_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int ncu = 0;
+    rc = device_cus(&ncu);
+    if (rc) return rc;
+    Plan pl;
+    make_plan(A, form, m, 1, ncu, &pl);
+    if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
+    const Ptrs P = carve(pl, workspace);
+    const PassParams pp = make_params(A, pl, gamma, mu);
+    GPSPCA_HIP(launch_ctrl_reset(P.ctrl, 1, 0.0, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * m, st));
+    GPSPCA_HIP(hipMemcpy2DAsync(P.x[0], sizeof(float) * pl.ldx, Xin, sizeof(float) * A->p,
+                                sizeof(float) * A->p, m, hipMemcpyDeviceToDevice, st));
+    TimedLaunches tl;
+    rc = enqueue_pass(pl, pp, P, 0, st, tl);
+    if (rc) return rc;
+    if (S) GPSPCA_HIP(launch_finalize(pl, P.S, P.fin, nullptr, S, nullptr, st));
+    if (G)
+        GPSPCA_HIP(hipMemcpyAsync(G, P.g64, sizeof(double) * m * A->p, hipMemcpyDeviceToDevice, st));
+    std::vector<double> host(2 * (size_t)m);
+    GPSPCA_HIP(hipMemcpyAsync(host.data(), P.fcomp, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, st));
+    Ctrl* snap = nullptr;
+    rc = pinned_ctrl(&snap);
+    if (rc) return rc;
+    GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    GPSPCA_HIP(hipStreamSynchronize(st));
+    if (snap->status == GPSPCA_ENONFINITE) return fail(GPSPCA_ENONFINITE, status_text(GPSPCA_ENONFINITE));
+    for (int j = 0; j < m; ++j) {
+        if (f) f[j] = host[j];
+        if (nnz) std::memcpy(&nnz[j], &host[m + j], sizeof(int64_t));
+    }
+    return GPSPCA_OK;
+}
+
+int gpspca_column_norms(const gpspca_matrix* A, double* norms, void* stream) {
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    if (!norms) return fail(GPSPCA_EINVAL, "norms is NULL");
+    int ncu = 0;
+    rc = device_cus(&ncu);
+    if (rc) return rc;
+    Plan pl;
+    make_plan(A, GPSPCA_SL1, 1, 1, ncu, &pl);
+    const PassParams pp = make_params(A, pl, 0.0, nullptr);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
+    GPSPCA_HIP(launch_colnorm(pp, norms, grid, static_cast<hipStream_t>(stream)));
+    return GPSPCA_OK;
+}
+
+int gpspca_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return GPSPCA_OK;
+}
+
+int gpspca_profile_read(double* total_ms, int64_t* launches, char* name, size_t name_len) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (total_ms) *total_ms = g_prof.total_ms;
+    if (launches) *launches = g_prof.launches;
+    if (name && name_len) {
+        std::snprintf(name, name_len, "%s", g_prof.name.c_str());
+    }
+    g_prof.total_ms = 0.0;
+    g_prof.launches = 0;
+    return GPSPCA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Internal declarations of the gfx950 GP-SPCA library: device control block,
+// kernel parameter blocks and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gpspca.h"
+
+namespace gpspca {
+
+constexpr int kMaxM = GPSPCA_MAX_M;
+
+// Device-resident state of one solve.  Written only by single-workgroup
+// kernels (stop test / projection) and by the control reset kernel.
+struct Ctrl {
+    int k;                 // index of the next pass
+    int done;              // 1 once the stopping rule fired (or an error)
+    int status;            // GPSPCA_* status of the solve
+    int n_iter;            // passes made
+    int ndead;             // dead components at the last retraction
+    int degenerate_seen;   // some retraction completed dead components / F = 0
+    int max_iter;
+    int pad0;
+    double tol;
+    double last_F;
+};
+
+// Problem constants passed by value to every pass kernel.
+struct PassParams {
+    const float* A;        // column-major p x n FP32 (dtype F32)
+    const uint16_t* Abf;   // bf16 storage (dtype BF16)
+    const uint8_t* Af8;    // e4m3 storage (dtype F8E4M3)
+    const float* scale;    // per-column scales or nullptr
+    int64_t lda;
+    int64_t n;
+    int p;
+    int ldx;               // leading dimension of the internal X buffers (multiple of 4)
+    int m;
+    int l0;                // 1 for the l0 (hard threshold) forms
+    double gamma;
+    float muf[kMaxM];      // mu_j in FP32 (for the back-projection weights)
+    double mu[kMaxM];      // mu_j in FP64 (for the threshold)
+};
+
+// Layout of the caller's workspace for one solve (byte offsets).
+struct Plan {
+    // problem
+    int64_t p, n, lda;
+    int m, form, l0, max_iter;
+    int ldx;
+    // kernel choice
+    int fused_m1;          // 1: single fused pass kernel (m == 1), else corr + back-projection
+    int m1_threads, m1_kq, m1_grid;
+    int corr_M, corr_grid; // corr kernel: padded component count and grid
+    int bp_kq, bp_rb, bp_cr; // back-projection: quads per thread, row blocks, column ranges
+    int npart;             // number of G partials
+    int nwave_part;        // number of objective partial slots (waves or workgroups)
+    int red_split;         // split of the partial reduction
+    int gram_rows, gram_grid;
+    int fin_grid;
+    int topm_grid;
+    int vec4;              // float4 loads of A are legal
+    // workspace offsets (bytes)
+    size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
+        o_l1, o_g64, o_gram, o_coef, o_norms, o_cand_v, o_cand_i, o_idx, o_fin, o_invn, o_fcomp;
+    size_t total;
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+// pass kernels (k_pass.hip)
+hipError_t launch_pass_m1(const Plan& pl, const PassParams& pp, const float* x, float* S,
+                          float* gpart, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st);
+hipError_t launch_corr(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                       uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                       hipStream_t st);
+hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
+                           const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
+                           hipStream_t st);
+hipError_t launch_colnorm(const PassParams& pp, double* norms, int grid, hipStream_t st);
+
+// reductions, retraction, stop test (k_reduce.hip)
+hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t st);
+hipError_t launch_ctrl_reset(Ctrl* ctrl, int max_iter, double tol, hipStream_t st);
+hipError_t launch_reduce_partials(const Plan& pl, const float* gpart, const int* touched,
+                                  double* l1, const Ctrl* ctrl, hipStream_t st);
+hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float* X,
+                       int with_x, double* g64, double* gram, const Ctrl* ctrl,
+                       hipStream_t st);
+hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
+                       const double* gram, double* trace, double* coef, double* fcomp,
+                       Ctrl* ctrl, hipStream_t st);
+hipError_t launch_project(const Plan& pl, const double* gram, double* coef, Ctrl* ctrl,
+                          hipStream_t st);
+hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, const double* coef,
+                        float* Xn, const Ctrl* ctrl, hipStream_t st);
+hipError_t launch_load_g64(const Plan& pl, const float* X0, int ldx0, double* g64,
+                           hipStream_t st);
+
+// init and finalize (k_init_fin.hip)
+hipError_t launch_topm(const Plan& pl, const double* norms, double* cand_v, int64_t* cand_i,
+                       int64_t* idx, hipStream_t st);
+hipError_t launch_gather(const Plan& pl, const PassParams& pp, const int64_t* idx, double* g64,
+                         hipStream_t st);
+hipError_t launch_finalize(const Plan& pl, const float* S, double* fin, double* invn, float* Z,
+                           uint32_t* support, hipStream_t st);
+hipError_t launch_copy_x(const Plan& pl, const float* Xint, float* Xout, hipStream_t st);
+
+// Offsets of the coefficient block (doubles) written by the stop / projection kernels.
+inline size_t coef_omega(int m) { return 0; }
+inline size_t coef_psi(int m) { return (size_t)m * m; }
+
+}  // namespace gpspca

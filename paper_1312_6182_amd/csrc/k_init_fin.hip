@@ -1,0 +1,193 @@
+// Default start and output kernels of the GP-SPCA power iteration.
+//
+// Default start: the m columns of largest norm, ordered by (-||a_i||, i), so
+// ties go to the lower index; their polar factor (or normalization) is the
+// starting point.  Selection is two-level: each workgroup keeps the top m of
+// its column range, one workgroup merges the candidates.
+//
+// Outputs: Z = S with unit-norm columns (a column with empty support stays
+// zero), the support as packed bit words, and X copied out of the internal
+// padded buffer.
+#include "gpspca_internal.h"
+
+namespace gpspca {
+
+__device__ __forceinline__ bool better(double va, int64_t ia, double vb, int64_t ib) {
+    if (ib < 0) return ia >= 0;
+    if (ia < 0) return false;
+    return va > vb || (va == vb && ia < ib);
+}
+
+// m rounds of a workgroup argmax over [b, e) of (val, idx) pairs; pairs whose
+// index is already chosen are skipped.  Results in chosen_v / chosen_i.
+__device__ void topm_block(int m, int64_t b, int64_t e, const double* __restrict__ val,
+                           const int64_t* __restrict__ idx, double* chosen_v, int64_t* chosen_i,
+                           double* rv, int64_t* ri) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int r = 0; r < m; ++r) {
+        double bv = -INFINITY;
+        int64_t bi = -1;
+        for (int64_t i = b + t; i < e; i += nt) {
+            const int64_t ci = idx ? idx[i] : i;
+            if (ci < 0) continue;
+            bool taken = false;
+            for (int q = 0; q < r; ++q) taken |= (chosen_i[q] == ci);
+            if (taken) continue;
+            const double cv = val[i];
+            if (better(cv, ci, bv, bi)) {
+                bv = cv;
+                bi = ci;
+            }
+        }
+        rv[t] = bv;
+        ri[t] = bi;
+        __syncthreads();
+        for (int h = nt / 2; h > 0; h >>= 1) {
+            if (t < h && better(rv[t + h], ri[t + h], rv[t], ri[t])) {
+                rv[t] = rv[t + h];
+                ri[t] = ri[t + h];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            chosen_v[r] = rv[0];
+            chosen_i[r] = ri[0];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_topm_local(int64_t n, int m, const double* __restrict__ norms,
+                                                    double* __restrict__ cv, int64_t* __restrict__ ci) {
+    __shared__ double rv[256];
+    __shared__ int64_t ri[256];
+    __shared__ double chv[kMaxM];
+    __shared__ int64_t chi[kMaxM];
+    const int64_t b = n * blockIdx.x / gridDim.x, e = n * (blockIdx.x + 1) / gridDim.x;
+    topm_block(m, b, e, norms, nullptr, chv, chi, rv, ri);
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        cv[(size_t)blockIdx.x * m + r] = chv[r];
+        ci[(size_t)blockIdx.x * m + r] = chi[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_topm_final(int ncand, int m, const double* __restrict__ cv,
+                                                    const int64_t* __restrict__ ci,
+                                                    int64_t* __restrict__ idx) {
+    __shared__ double rv[256];
+    __shared__ int64_t ri[256];
+    __shared__ double chv[kMaxM];
+    __shared__ int64_t chi[kMaxM];
+    topm_block(m, 0, ncand, cv, ci, chv, chi, rv, ri);
+    for (int r = threadIdx.x; r < m; r += blockDim.x) idx[r] = chi[r];
+}
+
+hipError_t launch_topm(const Plan& pl, const double* norms, double* cand_v, int64_t* cand_i,
+                       int64_t* idx, hipStream_t st) {
+    hipLaunchKernelGGL(k_topm_local, dim3(pl.topm_grid), dim3(256), 0, st, pl.n, pl.m, norms,
+                       cand_v, cand_i);
+    hipLaunchKernelGGL(k_topm_final, dim3(1), dim3(256), 0, st, pl.topm_grid * pl.m, pl.m,
+                       cand_v, cand_i, idx);
+    return hipGetLastError();
+}
+
+// g64[j*p + r] = A[r, idx[j]] in FP64.
+__global__ void k_gather(PassParams pp, const int64_t* __restrict__ idx, double* __restrict__ g64) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)pp.m * pp.p) return;
+    const int j = (int)(e / pp.p), r = (int)(e % pp.p);
+    const int64_t c = idx[j];
+    g64[e] = (double)pp.A[c * pp.lda + r];
+}
+
+hipError_t launch_gather(const Plan& pl, const PassParams& pp, const int64_t* idx, double* g64,
+                         hipStream_t st) {
+    const int64_t ne = (int64_t)pl.m * pl.p;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pp, idx,
+                       g64);
+    return hipGetLastError();
+}
+
+// Support words and per-block sums of s^2 per component.
+__global__ __launch_bounds__(256) void k_fin_support(int64_t n, int m, const float* __restrict__ S,
+                                                     uint32_t* __restrict__ support,
+                                                     double* __restrict__ fin) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    const int64_t nw = (n + 31) / 32;
+    const int64_t w = (int64_t)blockIdx.x * 256 + t;
+    for (int j = 0; j < m; ++j) {
+        double ss = 0.0;
+        if (w < nw) {
+            uint32_t bits = 0;
+            for (int b = 0; b < 32; ++b) {
+                const int64_t i = w * 32 + b;
+                if (i < n) {
+                    const float s = S[i * m + j];
+                    bits |= (s != 0.f ? 1u : 0u) << b;
+                    ss += (double)s * (double)s;
+                }
+            }
+            if (support) support[(size_t)j * nw + w] = bits;
+        }
+        red[t] = ss;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) fin[(size_t)blockIdx.x * m + j] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_fin_norm(int m, int nblk, const double* __restrict__ fin,
+                           double* __restrict__ invn) {
+    const int j = threadIdx.x;
+    if (j >= m) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += fin[(size_t)b * m + j];
+    invn[j] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+}
+
+// Z[i + j*n] = S[i*m + j] * invn[j]  (invn == nullptr: plain transpose)
+__global__ void k_fin_z(int64_t n, int m, const float* __restrict__ S,
+                        const double* __restrict__ invn, float* __restrict__ Z) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * m) return;
+    const int j = (int)(e / n);
+    const int64_t i = e % n;
+    const float s = S[i * m + j];
+    Z[e] = invn ? (float)((double)s * invn[j]) : s;
+}
+
+hipError_t launch_finalize(const Plan& pl, const float* S, double* fin, double* invn, float* Z,
+                           uint32_t* support, hipStream_t st) {
+    const int64_t ne = pl.n * pl.m;
+    if (invn) {
+        hipLaunchKernelGGL(k_fin_support, dim3(pl.fin_grid), dim3(256), 0, st, pl.n, pl.m, S,
+                           support, fin);
+        hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(64), 0, st, pl.m, pl.fin_grid, fin, invn);
+    }
+    if (Z)
+        hipLaunchKernelGGL(k_fin_z, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pl.n,
+                           pl.m, S, invn, Z);
+    return hipGetLastError();
+}
+
+// Xout (p x m, leading dim p) <- Xint (leading dim ldx)
+__global__ void k_copy_x(int m, int p, int ldx, const float* __restrict__ Xi, float* __restrict__ Xo) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)m * p) return;
+    const int j = (int)(e / p), r = (int)(e % p);
+    Xo[e] = Xi[(size_t)j * ldx + r];
+}
+
+hipError_t launch_copy_x(const Plan& pl, const float* Xint, float* Xout, hipStream_t st) {
+    const int64_t ne = (int64_t)pl.m * pl.p;
+    hipLaunchKernelGGL(k_copy_x, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pl.m,
+                       (int)pl.p, pl.ldx, Xint, Xout);
+    return hipGetLastError();
+}
+
+}  // namespace gpspca

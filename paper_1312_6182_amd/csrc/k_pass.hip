@@ -1,0 +1,576 @@
+// Pass kernels of the GP-SPCA power iteration on gfx950: the only kernels that
+// stream the data matrix A from HBM.
+//
+// One pass (Section 2, Table 1) computes, for every variable column a_i and
+// component j:
+//   y_ij = a_i^T x_j                                         (correlation)
+//   l1: s_ij = sign(y_ij) [mu_j |y_ij| - gamma]_+ ,  f_j += [.]_+^2
+//   l0: s_ij = mu_j y_ij if (mu_j y_ij)^2 > gamma,  f_j += (mu_j y_ij)^2 - gamma
+//   g_j += mu_j s_ij a_i                                     (ascent direction)
+//
+// Kernels:
+//  k_pass_m1   m = 1, single pass over A: each workgroup keeps x and its partial
+//              of g in registers (rows distributed over threads), loads a batch
+//              of columns, reduces the dot products across the workgroup, applies
+//              the threshold and the axpy on the registers it already holds.
+//  k_corr      block forms (m <= 8 per launch): one wavefront owns a contiguous
+//              range of columns and computes B columns x M components of a_i^T X
+//              per sweep over the rows (float4 loads, 64-value butterfly reduction),
+//              thresholds in registers and writes S and a per-column activity flag.
+//  k_backproj  block forms: G partials = sum over ACTIVE columns only of
+//              a_i (mu * s_i)^T, so a sparse support costs a small fraction of a
+//              second pass; workgroups own a (row block, column range) tile.
+//  k_colnorm   ||a_i|| in FP64 (default start).
+#include "gpspca_internal.h"
+
+namespace gpspca {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }
+
+// Quad q (rows 4q..4q+3) of one column.  Full quads use one 16-byte load when
+// the column is 16-byte aligned (VEC); the ragged last quad is masked.
+template <bool VEC>
+__device__ __forceinline__ f4 load_quad(const float* __restrict__ col, int q, int nqf, int p) {
+    const int r = 4 * q;
+    if (q < nqf) {
+        if constexpr (VEC) {
+            return __builtin_nontemporal_load(reinterpret_cast<const f4*>(col + r));
+        } else {
+            return f4{col[r], col[r + 1], col[r + 2], col[r + 3]};
+        }
+    }
+    f4 v = zero4();
+    if (r < p) v.x = col[r];
+    if (r + 1 < p) v.y = col[r + 1];
+    if (r + 2 < p) v.z = col[r + 2];
+    if (r + 3 < p) v.w = col[r + 3];
+    return v;
+}
+
+__device__ __forceinline__ float dot4(f4 a, f4 b, float acc) {
+    acc = __builtin_fmaf(a.x, b.x, acc);
+    acc = __builtin_fmaf(a.y, b.y, acc);
+    acc = __builtin_fmaf(a.z, b.z, acc);
+    acc = __builtin_fmaf(a.w, b.w, acc);
+    return acc;
+}
+
+// Threshold of one correlation (Table 1).  Returns true when the entry is in
+// the support; s is the thresholded value and fv its objective term.
+__device__ __forceinline__ bool threshold(bool l0, double mu, double gamma, float y, float& s,
+                                          double& fv) {
+    const double yd = (double)y;
+    if (l0) {
+        const double my = mu * yd;
+        const double q = my * my - gamma;
+        if (q > 0.0) {
+            s = (float)my;
+            fv = q;
+            return true;
+        }
+    } else {
+        const double t = mu * fabs(yd) - gamma;
+        if (t > 0.0) {
+            s = (float)(yd > 0.0 ? t : -t);
+            fv = t * t;
+            return true;
+        }
+    }
+    s = 0.f;
+    fv = 0.0;
+    return false;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_allreduce_sum(T v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// k_pass_m1: fused single pass, m = 1.
+//   T threads; thread t owns row quads t + T*k (k < KQ).  B columns per batch,
+//   the next batch is loaded before the current one is reduced.
+// ---------------------------------------------------------------------------
+template <int T, int KQ, int B, bool VEC>
+__global__ __launch_bounds__(T) void k_pass_m1(PassParams pp, const float* __restrict__ x,
+                                               float* __restrict__ S, float* __restrict__ gpart,
+                                               double* __restrict__ fpart,
+                                               int* __restrict__ nnzpart,
+                                               const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int NWV = T / 64;
+    __shared__ float red[2][NWV][B];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int p = pp.p, nqf = p >> 2, nq = (p + 3) >> 2;
+    const int64_t cb = pp.n * (int64_t)blockIdx.x / gridDim.x;
+    const int64_t ce = pp.n * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    const bool l0 = pp.l0 != 0;
+    const double gamma = pp.gamma, mu = pp.mu[0];
+    const float muf = pp.muf[0];
+
+    f4 xr[KQ], g[KQ];
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+        const int q = t + T * k;
+        xr[k] = (q < nq) ? *reinterpret_cast<const f4*>(x + 4 * q) : zero4();
+        g[k] = zero4();
+    }
+    double f_acc = 0.0;
+    int nnz_acc = 0;
+
+    f4 a[B][KQ];
+    auto load_batch = [&](int64_t c0, f4(&dst)[B][KQ]) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int64_t c = (c0 + b < ce) ? c0 + b : ce - 1;
+            const float* col = pp.A + c * pp.lda;
+#pragma unroll
+            for (int k = 0; k < KQ; ++k) {
+                const int q = t + T * k;
+                dst[b][k] = (q < nq) ? load_quad<VEC>(col, q, nqf, p) : zero4();
+            }
+        }
+    };
+    if (cb < ce) load_batch(cb, a);
+
+    int it = 0;
+    for (int64_t c0 = cb; c0 < ce; c0 += B, ++it) {
+        float d[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < KQ; ++k) acc = dot4(a[b][k], xr[k], acc);
+            d[b] = acc;
+        }
+        const bool more = c0 + B < ce;
+        f4 an[B][KQ];
+        if (more) load_batch(c0 + B, an);
+#pragma unroll
+        for (int b = 0; b < B; ++b) d[b] = wave_allreduce_sum(d[b]);
+        if (lane == 0) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) red[it & 1][wv][b] = d[b];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            float y = 0.f;
+#pragma unroll
+            for (int w = 0; w < NWV; ++w) y += red[it & 1][w][b];
+            if (c0 + b < ce) {
+                float s;
+                double fv;
+                const bool act = threshold(l0, mu, gamma, y, s, fv);
+                if (act) {
+                    const float wgt = muf * s;
+#pragma unroll
+                    for (int k = 0; k < KQ; ++k) {
+                        g[k].x = __builtin_fmaf(wgt, a[b][k].x, g[k].x);
+                        g[k].y = __builtin_fmaf(wgt, a[b][k].y, g[k].y);
+                        g[k].z = __builtin_fmaf(wgt, a[b][k].z, g[k].z);
+                        g[k].w = __builtin_fmaf(wgt, a[b][k].w, g[k].w);
+                    }
+                    if (t == 0) {
+                        f_acc += fv;
+                        nnz_acc += 1;
+                    }
+                }
+                if (t == 0) S[c0 + b] = s;
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int k = 0; k < KQ; ++k) a[b][k] = an[b][k];
+        }
+    }
+    float* gp = gpart + (size_t)blockIdx.x * pp.ldx;
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+        const int q = t + T * k;
+        if (q < nq) *reinterpret_cast<f4*>(gp + 4 * q) = g[k];
+    }
+    if (t == 0) {
+        fpart[blockIdx.x] = f_acc;
+        nnzpart[blockIdx.x] = nnz_acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_corr: correlation + threshold for the block forms.
+//   M components (padded, m_g <= M real ones starting at j0), B columns per
+//   sweep, V = B*M = 64 accumulators per lane reduced by a butterfly so that lane
+//   l ends with value (b, j) = (l / M, l % M) (V = 64) or shared by 64/V lanes.
+// ---------------------------------------------------------------------------
+template <int O, int S, int V>
+__device__ __forceinline__ void butterfly(float (&v)[V], int lane) {
+    if constexpr (O >= 1) {
+        if constexpr (S > 1) {
+            constexpr int H = S / 2;
+            const bool up = (lane & O) != 0;
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const float send = up ? v[i] : v[i + H];
+                const float keep = up ? v[i + H] : v[i];
+                v[i] = keep + __shfl_xor(send, O, 64);
+            }
+            butterfly<O / 2, H, V>(v, lane);
+        } else {
+            v[0] += __shfl_xor(v[0], O, 64);
+            butterfly<O / 2, 1, V>(v, lane);
+        }
+    }
+}
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+template <int M, int B, bool VEC>
+__global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float* __restrict__ X,
+                                              float* __restrict__ S, uint8_t* __restrict__ act,
+                                              double* __restrict__ fpart,
+                                              int* __restrict__ nnzpart,
+                                              const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int V = B * M;
+    static_assert(V <= 64 && (V & (V - 1)) == 0, "B*M must be a power of two <= 64");
+    constexpr int SHIFT = 6 - ilog2c(V);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t cb = pp.n * wave / nw, ce = pp.n * (wave + 1) / nw;
+    const int p = pp.p, nqf = p >> 2, nq = (p + 3) >> 2;
+    const int m = pp.m;
+    const int mg = (m - j0 < M) ? m - j0 : M;  // real components in this launch
+    const bool l0 = pp.l0 != 0;
+    const double gamma = pp.gamma;
+
+    const int vidx = lane >> SHIFT;
+    const int ob = vidx / M, oj = vidx % M;
+    const bool rep = (lane & ((1 << SHIFT) - 1)) == 0;
+    const double muj = (oj < mg) ? pp.mu[j0 + oj] : 1.0;
+    uint64_t grpmask = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) grpmask |= 1ull << (j << SHIFT);
+
+    const float* Xg = X + (size_t)j0 * pp.ldx;
+    double f_acc = 0.0;
+    int nnz_acc = 0;
+
+    for (int64_t c0 = cb; c0 < ce; c0 += B) {
+        const float* colp[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int64_t c = (c0 + b < ce) ? c0 + b : ce - 1;
+            colp[b] = pp.A + c * pp.lda;
+        }
+        float acc[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[i] = 0.f;
+        for (int q = lane; q < nq; q += 64) {
+            f4 xv[M];
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                xv[j] = (j < mg) ? *reinterpret_cast<const f4*>(Xg + (size_t)j * pp.ldx + 4 * q)
+                                 : zero4();
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const f4 a = load_quad<VEC>(colp[b], q, nqf, p);
+#pragma unroll
+                for (int j = 0; j < M; ++j) acc[b * M + j] = dot4(a, xv[j], acc[b * M + j]);
+            }
+        }
+        butterfly<32, V, V>(acc, lane);
+        const float y = acc[0];
+        const int64_t col = c0 + ob;
+        const bool valid = rep && (col < ce) && (oj < mg);
+        bool active = false;
+        if (valid) {
+            float s;
+            double fv;
+            active = threshold(l0, muj, gamma, y, s, fv);
+            S[col * m + j0 + oj] = s;
+            if (active) {
+                f_acc += fv;
+                nnz_acc += 1;
+            }
+        }
+        const uint64_t bal = __ballot(active);
+        if (valid && oj == 0) {
+            const bool any = (bal & (grpmask << ((ob * M) << SHIFT))) != 0;
+            if (j0 == 0) act[col] = any ? 1 : 0;
+            else if (any) act[col] = 1;
+        }
+    }
+    // Per-component totals over the lanes that share oj (fixed xor order).
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        if (o >= (1 << SHIFT) && o < (M << SHIFT)) continue;
+        f_acc += __shfl_xor(f_acc, o, 64);
+        nnz_acc += __shfl_xor(nnz_acc, o, 64);
+    }
+    if (ob == 0 && rep && oj < mg) {
+        fpart[wave * m + j0 + oj] = f_acc;
+        nnzpart[wave * m + j0 + oj] = nnz_acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_backproj: G partial of column range cr over its active columns.
+//   grid (row blocks, column ranges); 256 threads, thread t owns quads
+//   qbase + t + 256 k (k < KQ2) of the row block; U active columns per step.
+// ---------------------------------------------------------------------------
+template <int M, int KQ2, bool VEC>
+__global__ __launch_bounds__(256) void k_backproj(PassParams pp, int j0,
+                                                  const float* __restrict__ S,
+                                                  const uint8_t* __restrict__ act,
+                                                  float* __restrict__ gpart,
+                                                  int* __restrict__ touched, int ncr,
+                                                  const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int U = 4;
+    __shared__ int list[256];
+    __shared__ int wcount[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int p = pp.p, nqf = p >> 2, nq = (p + 3) >> 2, m = pp.m;
+    const int mg = (m - j0 < M) ? m - j0 : M;
+    const int qbase = blockIdx.x * 256 * KQ2;
+    const int cr = blockIdx.y;
+    const int64_t cb = pp.n * cr / ncr, ce = pp.n * (cr + 1) / ncr;
+
+    f4 g[KQ2][M];
+#pragma unroll
+    for (int k = 0; k < KQ2; ++k)
+#pragma unroll
+        for (int j = 0; j < M; ++j) g[k][j] = zero4();
+    bool any = false;
+
+    for (int64_t base = cb; base < ce; base += 256) {
+        const int64_t i = base + t;
+        const bool fl = (i < ce) && act[i] != 0;
+        const uint64_t bal = __ballot(fl);
+        if (lane == 0) wcount[wv] = __popcll(bal);
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wv; ++w) off += wcount[w];
+        const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (fl) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+        __syncthreads();
+        for (int e = 0; e < total; e += U) {
+            f4 a[U][KQ2];
+            float w[U][M];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int li = (e + u < total) ? list[e + u] : list[e];
+                const int64_t col = base + li;
+                const float* colp = pp.A + col * pp.lda;
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    w[u][j] = (j < mg) ? pp.muf[j0 + j] * S[col * m + j0 + j] : 0.f;
+#pragma unroll
+                for (int k = 0; k < KQ2; ++k) {
+                    const int q = qbase + t + 256 * k;
+                    a[u][k] = (q < nq) ? load_quad<VEC>(colp, q, nqf, p) : zero4();
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (e + u < total) {
+#pragma unroll
+                    for (int k = 0; k < KQ2; ++k)
+#pragma unroll
+                        for (int j = 0; j < M; ++j) {
+                            g[k][j].x = __builtin_fmaf(w[u][j], a[u][k].x, g[k][j].x);
+                            g[k][j].y = __builtin_fmaf(w[u][j], a[u][k].y, g[k][j].y);
+                            g[k][j].z = __builtin_fmaf(w[u][j], a[u][k].z, g[k][j].z);
+                            g[k][j].w = __builtin_fmaf(w[u][j], a[u][k].w, g[k][j].w);
+                        }
+                }
+            }
+        }
+        any = any || total > 0;
+        __syncthreads();
+    }
+    if (any) {
+        float* gp = gpart + (size_t)cr * m * pp.ldx;
+#pragma unroll
+        for (int k = 0; k < KQ2; ++k) {
+            const int q = qbase + t + 256 * k;
+            if (q < nq) {
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j < mg)
+                        *reinterpret_cast<f4*>(gp + (size_t)(j0 + j) * pp.ldx + 4 * q) = g[k][j];
+            }
+        }
+    }
+    if (t == 0 && blockIdx.x == 0 && j0 == 0) touched[cr] = any ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_colnorm: ||a_i||_2 with FP64 accumulation; one wavefront per column range,
+// four columns in flight.
+// ---------------------------------------------------------------------------
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_colnorm(PassParams pp, double* __restrict__ norms) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t cb = pp.n * wave / nw, ce = pp.n * (wave + 1) / nw;
+    const int p = pp.p, nqf = p >> 2, nq = (p + 3) >> 2;
+    constexpr int C = 4;
+    for (int64_t c0 = cb; c0 < ce; c0 += C) {
+        double s[C];
+        const float* colp[C];
+#pragma unroll
+        for (int b = 0; b < C; ++b) {
+            s[b] = 0.0;
+            const int64_t c = (c0 + b < ce) ? c0 + b : ce - 1;
+            colp[b] = pp.A + c * pp.lda;
+        }
+        for (int q = lane; q < nq; q += 64) {
+#pragma unroll
+            for (int b = 0; b < C; ++b) {
+                const f4 a = load_quad<VEC>(colp[b], q, nqf, p);
+                s[b] += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z +
+                        (double)a.w * a.w;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < C; ++b) {
+            const double tot = wave_allreduce_sum(s[b]);
+            if (lane == 0 && c0 + b < ce) norms[c0 + b] = sqrt(tot);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int T, int KQ, bool VEC>
+static hipError_t launch_m1_t(const Plan& pl, const PassParams& pp, const float* x, float* S,
+                              float* gpart, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_pass_m1<T, KQ, 2, VEC>), dim3(pl.m1_grid), dim3(T), 0, st, pp, x, S,
+                       gpart, fpart, nnzpart, ctrl);
+    return hipGetLastError();
+}
+
+template <int T, bool VEC>
+static hipError_t launch_m1_kq(const Plan& pl, const PassParams& pp, const float* x, float* S,
+                               float* gpart, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                               hipStream_t st) {
+    switch (pl.m1_kq) {
+        case 1: return launch_m1_t<T, 1, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        case 2: return launch_m1_t<T, 2, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        case 3: return launch_m1_t<T, 3, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        case 4: return launch_m1_t<T, 4, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        case 5: return launch_m1_t<T, 5, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool VEC>
+static hipError_t launch_m1_v(const Plan& pl, const PassParams& pp, const float* x, float* S,
+                              float* gpart, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                              hipStream_t st) {
+    switch (pl.m1_threads) {
+        case 64: return launch_m1_kq<64, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        case 256: return launch_m1_kq<256, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        case 512: return launch_m1_kq<512, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        case 1024: return launch_m1_kq<1024, VEC>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pass_m1(const Plan& pl, const PassParams& pp, const float* x, float* S,
+                          float* gpart, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st) {
+    return pl.vec4 ? launch_m1_v<true>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st)
+                   : launch_m1_v<false>(pl, pp, x, S, gpart, fpart, nnzpart, ctrl, st);
+}
+
+template <int M, int B, bool VEC>
+static hipError_t launch_corr_t(const Plan& pl, const PassParams& pp, int j0, const float* X,
+                                float* S, uint8_t* act, double* fpart, int* nnzpart,
+                                const Ctrl* ctrl, hipStream_t st) {
+    hipLaunchKernelGGL((k_corr<M, B, VEC>), dim3(pl.corr_grid), dim3(256), 0, st, pp, j0, X, S,
+                       act, fpart, nnzpart, ctrl);
+    return hipGetLastError();
+}
+
+template <bool VEC>
+static hipError_t launch_corr_v(const Plan& pl, const PassParams& pp, int j0, const float* X,
+                                float* S, uint8_t* act, double* fpart, int* nnzpart,
+                                const Ctrl* ctrl, hipStream_t st) {
+    switch (pl.corr_M) {
+        case 1: return launch_corr_t<1, 16, VEC>(pl, pp, j0, X, S, act, fpart, nnzpart, ctrl, st);
+        case 2: return launch_corr_t<2, 16, VEC>(pl, pp, j0, X, S, act, fpart, nnzpart, ctrl, st);
+        case 4: return launch_corr_t<4, 16, VEC>(pl, pp, j0, X, S, act, fpart, nnzpart, ctrl, st);
+        case 8: return launch_corr_t<8, 8, VEC>(pl, pp, j0, X, S, act, fpart, nnzpart, ctrl, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_corr(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                       uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                       hipStream_t st) {
+    for (int j0 = 0; j0 < pl.m; j0 += pl.corr_M) {
+        hipError_t e = pl.vec4 ? launch_corr_v<true>(pl, pp, j0, X, S, act, fpart, nnzpart, ctrl, st)
+                               : launch_corr_v<false>(pl, pp, j0, X, S, act, fpart, nnzpart, ctrl, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int M, bool VEC>
+static hipError_t launch_bp_t(const Plan& pl, const PassParams& pp, int j0, const float* S,
+                              const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_backproj<M, 2, VEC>), dim3(pl.bp_rb, pl.bp_cr), dim3(256), 0, st, pp,
+                       j0, S, act, gpart, touched, pl.bp_cr, ctrl);
+    return hipGetLastError();
+}
+
+template <bool VEC>
+static hipError_t launch_bp_v(const Plan& pl, const PassParams& pp, int j0, const float* S,
+                              const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
+                              hipStream_t st) {
+    const int r = pl.m - j0;
+    const int mb = r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 16;
+    switch (mb) {
+        case 1: return launch_bp_t<1, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 2: return launch_bp_t<2, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 4: return launch_bp_t<4, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 8: return launch_bp_t<8, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        default: return launch_bp_t<16, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+    }
+}
+
+// Component groups of at most 16 (the group's partial of g lives in registers).
+hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
+                           const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
+                           hipStream_t st) {
+    for (int j0 = 0; j0 < pl.m; j0 += 16) {
+        hipError_t e = pl.vec4 ? launch_bp_v<true>(pl, pp, j0, S, act, gpart, touched, ctrl, st)
+                               : launch_bp_v<false>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_colnorm(const PassParams& pp, double* norms, int grid, hipStream_t st) {
+    const bool vec = ((pp.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(pp.A) & 15) == 0);
+    if (vec)
+        hipLaunchKernelGGL((k_colnorm<true>), dim3(grid), dim3(256), 0, st, pp, norms);
+    else
+        hipLaunchKernelGGL((k_colnorm<false>), dim3(grid), dim3(256), 0, st, pp, norms);
+    return hipGetLastError();
+}
+
+}  // namespace gpspca

@@ -1,0 +1,657 @@
+// Reduction, retraction and stopping kernels of the GP-SPCA power iteration.
+//
+// After a pass has produced per-workgroup partials of the ascent direction G
+// (FP32) and per-wave objective partials (FP64), these kernels:
+//   k_reduce_partials  sum the G partials in a fixed order (FP64 accumulation),
+//   k_gram             finish G (FP64), and per row block the Gram matrices
+//                      G^T G, G^T X_k, X_k^T X_k,
+//   k_stop             (one workgroup) sum the objective F_k in fixed order, apply
+//                      the stopping rule, and compute the retraction
+//                      X_{k+1} = G Omega + X_k Psi:
+//                        m = 1   Omega = 1/||g||           (unit sphere)
+//                        block   Omega = (G^T G)^{-1/2}    (polar factor on the
+//                                Stiefel manifold), from a cyclic Jacobi
+//                                eigen-decomposition in FP64;
+//                        dead components (empty support) are completed by the
+//                        polar factor of the previous columns projected off the
+//                        live part, expressed through the same Gram matrices,
+//   k_apply            X_{k+1} = G Omega + X_k Psi, rounded to FP32.
+// Every reduction runs in a fixed order, so results are bitwise reproducible.
+#include "gpspca_internal.h"
+
+namespace gpspca {
+
+constexpr int LDM = kMaxM + 1;  // padded leading dimension of m x m LDS matrices
+
+// Allow dynamic LDS beyond 64 KB (gfx950 has 160 KB per CU).
+static void set_lds_limit(const void* fn) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();  // the attribute is advisory; do not leave a sticky error behind
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t st) {
+    const size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    size_t blocks = (words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<uint32_t*>(ptr), words);
+    return hipGetLastError();
+}
+
+__global__ void k_ctrl_reset(Ctrl* ctrl, int max_iter, double tol) {
+    if (threadIdx.x == 0) {
+        ctrl->k = 0;
+        ctrl->done = 0;
+        ctrl->status = GPSPCA_OK;
+        ctrl->n_iter = 0;
+        ctrl->ndead = 0;
+        ctrl->degenerate_seen = 0;
+        ctrl->max_iter = max_iter;
+        ctrl->pad0 = 0;
+        ctrl->tol = tol;
+        ctrl->last_F = 0.0;
+    }
+}
+
+hipError_t launch_ctrl_reset(Ctrl* ctrl, int max_iter, double tol, hipStream_t st) {
+    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, ctrl, max_iter, tol);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// l1[y][e] = sum_{c in chunk y} gpart[c][e]  (e < m*ldx), skipping untouched
+// partials; chunks are contiguous ranges of the partial index.
+__global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ gpart,
+                                                         const int* __restrict__ touched,
+                                                         int npart, int nsplit, int64_t ne,
+                                                         double* __restrict__ l1,
+                                                         const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const int y = blockIdx.y;
+    const int c0 = (int)((int64_t)npart * y / nsplit), c1 = (int)((int64_t)npart * (y + 1) / nsplit);
+    double s = 0.0;
+    int c = c0;
+    if (!touched) {
+        for (; c + 4 <= c1; c += 4) {
+            const float v0 = gpart[(size_t)c * ne + e];
+            const float v1 = gpart[(size_t)(c + 1) * ne + e];
+            const float v2 = gpart[(size_t)(c + 2) * ne + e];
+            const float v3 = gpart[(size_t)(c + 3) * ne + e];
+            s += (double)v0;
+            s += (double)v1;
+            s += (double)v2;
+            s += (double)v3;
+        }
+    }
+    for (; c < c1; ++c)
+        if (!touched || touched[c]) s += (double)gpart[(size_t)c * ne + e];
+    l1[(size_t)y * ne + e] = s;
+}
+
+hipError_t launch_reduce_partials(const Plan& pl, const float* gpart, const int* touched,
+                                  double* l1, const Ctrl* ctrl, hipStream_t st) {
+    const int64_t ne = (int64_t)pl.m * pl.ldx;
+    dim3 grid((unsigned)((ne + 255) / 256), (unsigned)pl.red_split);
+    hipLaunchKernelGGL(k_reduce_partials, grid, dim3(256), 0, st, gpart, touched, pl.npart,
+                       pl.red_split, ne, l1, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Row block r0..r0+nr: g_r = sum_y l1[y][.][r] (fixed order) -> g64 (p x m,
+// leading dim p); partial Gram matrices over the block ->
+// gram[blk][0|1|2][m*m] = G^T G, G^T X, X^T X.
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ l1, int nsplit, int m,
+                                              int ldx, int p, int rows, const float* __restrict__ X,
+                                              int with_x, double* __restrict__ g64,
+                                              double* __restrict__ gram,
+                                              const Ctrl* __restrict__ ctrl) {
+    if (ctrl && ctrl->done) return;
+    extern __shared__ double sh[];
+    const int mp = m + 1;
+    double* gt = sh;                         // rows x (m+1)
+    double* xt = sh + (size_t)rows * mp;     // rows x (m+1)
+    const int r0 = blockIdx.x * rows;
+    const int nr = (p - r0 < rows) ? p - r0 : rows;
+    const int t = threadIdx.x;
+    const size_t ne = (size_t)m * ldx;
+    for (int e = t; e < nr * m; e += blockDim.x) {
+        const int rr = e % nr, j = e / nr;
+        double s;
+        if (l1) {
+            s = 0.0;
+            for (int y = 0; y < nsplit; ++y) s += l1[(size_t)y * ne + (size_t)j * ldx + r0 + rr];
+            g64[(size_t)j * p + r0 + rr] = s;
+        } else {
+            s = g64[(size_t)j * p + r0 + rr];
+        }
+        gt[rr * mp + j] = s;
+        xt[rr * mp + j] = with_x ? (double)X[(size_t)j * ldx + r0 + rr] : 0.0;
+    }
+    __syncthreads();
+    const int mm = m * m;
+    double* out = gram + (size_t)blockIdx.x * 3 * mm;
+    for (int e = t; e < mm; e += blockDim.x) {
+        const int a = e / m, b = e % m;
+        double sgg = 0.0, sgx = 0.0, sxx = 0.0;
+        for (int rr = 0; rr < nr; ++rr) {
+            const double ga = gt[rr * mp + a];
+            sgg += ga * gt[rr * mp + b];
+            if (with_x) {
+                sgx += ga * xt[rr * mp + b];
+                sxx += xt[rr * mp + a] * xt[rr * mp + b];
+            }
+        }
+        out[e] = sgg;
+        out[mm + e] = sgx;
+        out[2 * mm + e] = sxx;
+    }
+}
+
+hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float* X, int with_x,
+                       double* g64, double* gram, const Ctrl* ctrl, hipStream_t st) {
+    const size_t shm = (size_t)2 * pl.gram_rows * (pl.m + 1) * sizeof(double);
+    static const bool lds_once = (set_lds_limit((const void*)k_gram), true);
+    (void)lds_once;
+    hipLaunchKernelGGL(k_gram, dim3(pl.gram_grid), dim3(256), shm, st, l1, nsplit, pl.m, pl.ldx,
+                       (int)pl.p, pl.gram_rows, X, with_x, g64, gram, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric eigen-decomposition by the cyclic Jacobi method with a parallel
+// (round-robin) ordering: each step applies msz/2 disjoint plane rotations.
+// a (msz x msz, leading dim LDM, LDS) is diagonalized in place; v receives the
+// eigenvectors (columns).  Executed by the whole workgroup.
+__device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs, double* red) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int e = t; e < msz * msz; e += nt) {
+        const int i = e / msz, j = e % msz;
+        v[i * LDM + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (msz < 2) return;
+    const int mm = msz + (msz & 1);
+    const int half = mm / 2;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        // convergence: off-diagonal mass against the diagonal mass
+        double off = 0.0, dg = 0.0;
+        for (int e = t; e < msz * msz; e += nt) {
+            const int i = e / msz, j = e % msz;
+            const double x = a[i * LDM + j];
+            if (i == j) dg += x * x;
+            else off += x * x;
+        }
+        red[t] = off;
+        red[nt + t] = dg;
+        __syncthreads();
+        for (int s = nt / 2; s > 0; s >>= 1) {
+            if (t < s) {
+                red[t] += red[t + s];
+                red[nt + t] += red[nt + t + s];
+            }
+            __syncthreads();
+        }
+        const double offt = red[0], dgt = red[nt];
+        __syncthreads();
+        if (!(offt > 1e-32 * dgt)) break;
+        for (int r = 0; r < mm - 1; ++r) {
+            if (t < half) {
+                // round-robin schedule: position 0 fixed, the others rotate
+                auto pos = [&](int i) { return i == 0 ? 0 : 1 + ((i - 1 + r) % (mm - 1)); };
+                int pp = pos(t), qq = pos(mm - 1 - t);
+                if (pp > qq) { const int tmp = pp; pp = qq; qq = tmp; }
+                double c = 1.0, s = 0.0;
+                if (qq < msz) {
+                    const double apq = a[pp * LDM + qq];
+                    const double app = a[pp * LDM + pp], aqq = a[qq * LDM + qq];
+                    if (apq != 0.0 && fabs(apq) > 1e-300) {
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        s = tt * c;
+                    }
+                }
+                rot[2 * t] = c;
+                rot[2 * t + 1] = s;
+                prs[2 * t] = pp;
+                prs[2 * t + 1] = qq;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int e = t; e < half * msz; e += nt) {
+                const int k = e / msz, col = e % msz;
+                const int pp = prs[2 * k], qq = prs[2 * k + 1];
+                if (qq >= msz) continue;
+                const double c = rot[2 * k], s = rot[2 * k + 1];
+                const double ap = a[pp * LDM + col], aq = a[qq * LDM + col];
+                a[pp * LDM + col] = c * ap - s * aq;
+                a[qq * LDM + col] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int e = t; e < half * msz; e += nt) {
+                const int k = e / msz, row = e % msz;
+                const int pp = prs[2 * k], qq = prs[2 * k + 1];
+                if (qq >= msz) continue;
+                const double c = rot[2 * k], s = rot[2 * k + 1];
+                const double ap = a[row * LDM + pp], aq = a[row * LDM + qq];
+                a[row * LDM + pp] = c * ap - s * aq;
+                a[row * LDM + qq] = s * ap + c * aq;
+                const double vp = v[row * LDM + pp], vq = v[row * LDM + qq];
+                v[row * LDM + pp] = c * vp - s * vq;
+                v[row * LDM + qq] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// out = V diag(lam^{-1/2}) V^T from the diagonalized a and eigenvectors v.
+// Eigenvalues below (msz * eps)^2 * lam_max count as zero (their inverse root
+// is dropped) and set *rankdef.
+__device__ void inv_sqrt_from_eig(const double* a, const double* v, double* out, int msz,
+                                  double* lam, int* rankdef) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    if (t == 0) {
+        double lmax = 0.0;
+        for (int i = 0; i < msz; ++i) lmax = fmax(lmax, a[i * LDM + i]);
+        const double thr = lmax * ((double)msz * 2.220446049250313e-16) * ((double)msz * 2.220446049250313e-16);
+        int rd = !(lmax > 0.0);
+        for (int i = 0; i < msz; ++i) {
+            const double l = a[i * LDM + i];
+            if (l > thr && l > 0.0) lam[i] = 1.0 / sqrt(l);
+            else { lam[i] = 0.0; rd = 1; }
+        }
+        *rankdef = rd;
+    }
+    __syncthreads();
+    for (int e = t; e < msz * msz; e += nt) {
+        const int i = e / msz, j = e % msz;
+        double s = 0.0;
+        for (int k = 0; k < msz; ++k) s += v[i * LDM + k] * lam[k] * v[j * LDM + k];
+        out[i * LDM + j] = s;
+    }
+    __syncthreads();
+}
+
+struct StopShared {
+    double rot[kMaxM];
+    int prs[kMaxM];
+    double lam[kMaxM];
+    double fj[kMaxM];
+    int nj[kMaxM];
+    int live[kMaxM];
+    int dead[kMaxM];
+    int nlive, ndead, rankdef, stop;
+};
+
+// Sum per-block Gram partials in fixed order into coef scratch:
+// coef[2mm..3mm) = G^T G, [3mm..4mm) = G^T X, [4mm..5mm) = X^T X.
+__device__ void sum_gram(int m, int ngram, const double* __restrict__ gram, double* coef) {
+    const int mm = m * m;
+    for (int e = threadIdx.x; e < 3 * mm; e += blockDim.x) {
+        double s = 0.0;
+        for (int g = 0; g < ngram; ++g) s += gram[(size_t)g * 3 * mm + e];
+        coef[2 * mm + e] = s;
+    }
+    __syncthreads();
+}
+
+// Retraction coefficients for the block forms with live set L and dead set D.
+__device__ void block_coefficients(int m, double* coef, StopShared& ss, double* A0, double* A1,
+                                   double* A2, double* red, Ctrl* ctrl) {
+    const int t = threadIdx.x, nt = blockDim.x, mm = m * m;
+    const double* GtG = coef + 2 * mm;
+    const double* GtX = coef + 3 * mm;
+    const double* XtX = coef + 4 * mm;
+    double* Om = coef;
+    double* Ps = coef + mm;
+    const int nl = ss.nlive, nd = ss.ndead;
+    for (int e = t; e < 2 * mm; e += nt) coef[e] = 0.0;
+    // W_L = (G_L^T G_L)^{-1/2}
+    for (int e = t; e < nl * nl; e += nt) {
+        const int i = e / nl, j = e % nl;
+        A0[i * LDM + j] = GtG[ss.live[i] * m + ss.live[j]];
+    }
+    __syncthreads();
+    jacobi_eig(A0, A1, nl, ss.rot, ss.prs, red);
+    int rd1 = 0;
+    inv_sqrt_from_eig(A0, A1, A2, nl, ss.lam, &ss.rankdef);
+    rd1 = ss.rankdef;
+    __syncthreads();
+    // Omega[L,L] = W_L
+    for (int e = t; e < nl * nl; e += nt) {
+        const int i = e / nl, j = e % nl;
+        Om[ss.live[i] * m + ss.live[j]] = A2[i * LDM + j];
+    }
+    if (nd > 0) {
+        // C = W_L^T (G^T X)[L, D]   (nl x nd) -> A0
+        __syncthreads();
+        for (int e = t; e < nl * nd; e += nt) {
+            const int a = e / nd, d = e % nd;
+            double s = 0.0;
+            for (int l = 0; l < nl; ++l) s += A2[l * LDM + a] * GtX[ss.live[l] * m + ss.dead[d]];
+            A0[a * LDM + d] = s;
+        }
+        __syncthreads();
+        // H^T H = (X^T X)[D,D] - C^T C -> A1
+        for (int e = t; e < nd * nd; e += nt) {
+            const int d1 = e / nd, d2 = e % nd;
+            double s = XtX[ss.dead[d1] * m + ss.dead[d2]];
+            for (int a = 0; a < nl; ++a) s -= A0[a * LDM + d1] * A0[a * LDM + d2];
+            A1[d1 * LDM + d2] = s;
+        }
+        __syncthreads();
+        // W_L C  (nl x nd) -> keep in Om scratch rows?  compute into A0 in place:
+        // B = W_L C; needs W_L (A2) and C (A0): write B into Ps temporarily.
+        for (int e = t; e < nl * nd; e += nt) {
+            const int a = e / nd, d = e % nd;
+            double s = 0.0;
+            for (int l = 0; l < nl; ++l) s += A2[a * LDM + l] * A0[l * LDM + d];
+            Ps[a * m + d] = s;  // temporary (nl x nd, leading dim m)
+        }
+        __syncthreads();
+        // W_D = (H^T H)^{-1/2}: eig of A1 into (A1, A0), inverse root into A2
+        for (int e = t; e < nd * nd; e += nt) {
+            const int i = e / nd, j = e % nd;
+            A0[i * LDM + j] = A1[i * LDM + j];
+        }
+        __syncthreads();
+        jacobi_eig(A0, A1, nd, ss.rot, ss.prs, red);
+        inv_sqrt_from_eig(A0, A1, A2, nd, ss.lam, &ss.rankdef);
+        // Omega[L,D] = -(W_L C) W_D ; Psi[D,D] = W_D
+        double* tmp = A0;  // nl x nd product
+        for (int e = t; e < nl * nd; e += nt) {
+            const int a = e / nd, d = e % nd;
+            double s = 0.0;
+            for (int k = 0; k < nd; ++k) s += Ps[a * m + k] * A2[k * LDM + d];
+            tmp[a * LDM + d] = -s;
+        }
+        __syncthreads();
+        for (int e = t; e < mm; e += nt) Ps[e] = 0.0;
+        __syncthreads();
+        for (int e = t; e < nl * nd; e += nt) {
+            const int a = e / nd, d = e % nd;
+            Om[ss.live[a] * m + ss.dead[d]] = tmp[a * LDM + d];
+        }
+        for (int e = t; e < nd * nd; e += nt) {
+            const int i = e / nd, j = e % nd;
+            Ps[ss.dead[i] * m + ss.dead[j]] = A2[i * LDM + j];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        ctrl->ndead = nd;
+        if (nd > 0 || rd1 || ss.rankdef) ctrl->degenerate_seen = 1;
+    }
+    __syncthreads();
+}
+
+// One workgroup: objective, trace, stopping rule, retraction coefficients.
+__global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
+                       const int* __restrict__ nnzpart, int ngram, const double* __restrict__ gram,
+                       double* __restrict__ trace, double* __restrict__ coef,
+                       double* __restrict__ fcomp, Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ StopShared ss;
+    __shared__ double red[2 * 256];
+    __shared__ int redi[256];
+    extern __shared__ double dyn[];
+    double* A0 = dyn;
+    double* A1 = dyn + (size_t)m * LDM;
+    double* A2 = dyn + (size_t)2 * m * LDM;
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int k = ctrl->k;
+
+    for (int j = 0; j < m; ++j) {
+        double s = 0.0;
+        int c = 0;
+        for (int w = t; w < nwp; w += nt) {
+            s += fpart[(size_t)w * m + j];
+            c += nnzpart[(size_t)w * m + j];
+        }
+        red[t] = s;
+        redi[t] = c;
+        __syncthreads();
+        for (int h = nt / 2; h > 0; h >>= 1) {
+            if (t < h) {
+                red[t] += red[t + h];
+                redi[t] += redi[t + h];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            ss.fj[j] = red[0];
+            ss.nj[j] = redi[0];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double F = 0.0;
+        int nl = 0, nd = 0;
+        for (int j = 0; j < m; ++j) {
+            F += ss.fj[j];
+            fcomp[j] = ss.fj[j];
+            reinterpret_cast<int64_t*>(fcomp + m)[j] = ss.nj[j];
+            if (ss.nj[j] > 0) ss.live[nl++] = j;
+            else ss.dead[nd++] = j;
+        }
+        ss.nlive = nl;
+        ss.ndead = nd;
+        trace[k] = F;
+        int stop = 0, status = GPSPCA_OK;
+        if (!isfinite(F)) {
+            stop = 1;
+            status = GPSPCA_ENONFINITE;
+        } else if (F == 0.0) {
+            stop = 1;
+            ctrl->degenerate_seen = 1;
+        } else if (k >= 1 && fabs(F - ctrl->last_F) < ctrl->tol * fabs(ctrl->last_F)) {
+            stop = 1;
+        } else if (k + 1 >= ctrl->max_iter) {
+            stop = 1;
+            status = GPSPCA_MAXITER;
+        }
+        if (stop) {
+            if (status >= 0 && ctrl->degenerate_seen) status = GPSPCA_DEGENERATE;
+            ctrl->status = status;
+            ctrl->done = 1;
+            ctrl->n_iter = k + 1;
+        }
+        ctrl->last_F = F;
+        ss.stop = stop;
+    }
+    __syncthreads();
+    if (ss.stop) return;
+
+    sum_gram(m, ngram, gram, coef);
+    const int mm = m * m;
+    if (m == 1) {
+        if (t == 0) {
+            const double g2 = coef[2];
+            const double om = 1.0 / sqrt(g2);
+            coef[0] = om;
+            coef[1] = 0.0;
+            ctrl->ndead = 0;
+            if (!(g2 > 0.0) || !isfinite(om)) {
+                ctrl->status = GPSPCA_ENONFINITE;
+                ctrl->done = 1;
+                ctrl->n_iter = k + 1;
+            }
+        }
+        __syncthreads();
+    } else {
+        block_coefficients(m, coef, ss, A0, A1, A2, red, ctrl);
+        // finiteness of the coefficients
+        if (t == 0) {
+            int ok = 1;
+            for (int e = 0; e < 2 * mm; ++e) ok &= isfinite(coef[e]) ? 1 : 0;
+            if (!ok) {
+                ctrl->status = GPSPCA_ENONFINITE;
+                ctrl->done = 1;
+                ctrl->n_iter = k + 1;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0 && !ctrl->done) ctrl->k = k + 1;
+}
+
+hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
+                       const double* gram, double* trace, double* coef, double* fcomp,
+                       Ctrl* ctrl, hipStream_t st) {
+    const int threads = pl.m <= 16 ? 64 : 256;
+    const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
+    static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
+    (void)lds_once;
+    hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
+                       nnzpart, pl.gram_grid, gram, trace, coef, fcomp, ctrl);
+    return hipGetLastError();
+}
+
+// Projection of a starting point onto the feasible set: Omega = (G^T G)^{-1/2}
+// (or 1/||g||); a rank-deficient start fails with GPSPCA_EINVAL.
+__global__ void k_project(int m, int ngram, const double* __restrict__ gram,
+                          double* __restrict__ coef, Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ StopShared ss;
+    __shared__ double red[2 * 256];
+    extern __shared__ double dyn[];
+    double* A0 = dyn;
+    double* A1 = dyn + (size_t)m * LDM;
+    double* A2 = dyn + (size_t)2 * m * LDM;
+    const int t = threadIdx.x, nt = blockDim.x, mm = m * m;
+    sum_gram(m, ngram, gram, coef);
+    if (m == 1) {
+        if (t == 0) {
+            const double g2 = coef[2];
+            coef[0] = 1.0 / sqrt(g2);
+            coef[1] = 0.0;
+            if (!(g2 > 0.0) || !isfinite(coef[0])) {
+                ctrl->status = GPSPCA_EINVAL;
+                ctrl->done = 1;
+            }
+        }
+        return;
+    }
+    for (int e = t; e < mm; e += nt) {
+        const int i = e / m, j = e % m;
+        A0[i * LDM + j] = coef[2 * mm + e];
+    }
+    __syncthreads();
+    jacobi_eig(A0, A1, m, ss.rot, ss.prs, red);
+    inv_sqrt_from_eig(A0, A1, A2, m, ss.lam, &ss.rankdef);
+    for (int e = t; e < mm; e += nt) {
+        const int i = e / m, j = e % m;
+        coef[e] = A2[i * LDM + j];
+        coef[mm + e] = 0.0;
+    }
+    if (t == 0) {
+        ctrl->ndead = 0;
+        if (ss.rankdef) {
+            ctrl->status = GPSPCA_EINVAL;
+            ctrl->done = 1;
+        }
+    }
+}
+
+hipError_t launch_project(const Plan& pl, const double* gram, double* coef, Ctrl* ctrl,
+                          hipStream_t st) {
+    const int threads = pl.m <= 16 ? 64 : 256;
+    const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
+    static const bool lds_once = (set_lds_limit((const void*)k_project), true);
+    (void)lds_once;
+    hipLaunchKernelGGL(k_project, dim3(1), dim3(threads), shm, st, pl.m, pl.gram_grid, gram,
+                       coef, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// X_{k+1}[r, j] = sum_l G[r, l] Omega[l, j] + sum_l X_k[r, l] Psi[l, j]
+template <int MB>
+__global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
+                                               const double* __restrict__ g64,
+                                               const float* __restrict__ Xk,
+                                               const double* __restrict__ coef,
+                                               float* __restrict__ Xn,
+                                               const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double om[MB * MB];
+    __shared__ double ps[MB * MB];
+    const int t = threadIdx.x, mm = m * m;
+    const bool dead = ctrl->ndead > 0;
+    for (int e = t; e < mm; e += 256) {
+        om[e] = coef[e];
+        ps[e] = dead ? coef[mm + e] : 0.0;
+    }
+    __syncthreads();
+    const int r = blockIdx.x * 256 + t;
+    if (r >= p) return;
+    double acc[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) acc[j] = 0.0;
+    for (int l = 0; l < m; ++l) {
+        const double gl = g64[(size_t)l * p + r];
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+            if (j < m) acc[j] += gl * om[l * m + j];
+    }
+    if (dead) {
+        for (int l = 0; l < m; ++l) {
+            const double xl = (double)Xk[(size_t)l * ldx + r];
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < m) acc[j] += xl * ps[l * m + j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MB; ++j)
+        if (j < m) Xn[(size_t)j * ldx + r] = (float)acc[j];
+}
+
+hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, const double* coef,
+                        float* Xn, const Ctrl* ctrl, hipStream_t st) {
+    const int m = pl.m, p = (int)pl.p;
+    dim3 grid((p + 255) / 256);
+#define GPSPCA_APPLY(MB)                                                                        \
+    hipLaunchKernelGGL(k_apply<MB>, grid, dim3(256), 0, st, m, p, pl.ldx, g64, Xk, coef, Xn, ctrl)
+    if (m <= 1) GPSPCA_APPLY(1);
+    else if (m <= 2) GPSPCA_APPLY(2);
+    else if (m <= 4) GPSPCA_APPLY(4);
+    else if (m <= 8) GPSPCA_APPLY(8);
+    else if (m <= 16) GPSPCA_APPLY(16);
+    else if (m <= 32) GPSPCA_APPLY(32);
+    else GPSPCA_APPLY(64);
+#undef GPSPCA_APPLY
+    return hipGetLastError();
+}
+
+// g64[j*p + r] = X0[j*ldx0 + r]
+__global__ void k_load_g64(int m, int p, const float* __restrict__ X0, int ldx0,
+                           double* __restrict__ g64) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)m * p) return;
+    const int j = (int)(e / p), r = (int)(e % p);
+    g64[e] = (double)X0[(size_t)j * ldx0 + r];
+}
+
+hipError_t launch_load_g64(const Plan& pl, const float* X0, int ldx0, double* g64,
+                           hipStream_t st) {
+    const int64_t ne = (int64_t)pl.m * pl.p;
+    hipLaunchKernelGGL(k_load_g64, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pl.m,
+                       (int)pl.p, X0, ldx0, g64);
+    return hipGetLastError();
+}
+
+}  // namespace gpspca

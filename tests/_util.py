@@ -1,0 +1,100 @@
+"""Helpers shared by the GPU parity tests: device transfer, the FP32 tie band of
+the correlation, and gamma selection away from ties.  Expected values always
+come from the oracle (never from the GPU path)."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle as O
+
+FORM_NAMES = {O.SL1: "SL1", O.SL0: "SL0", O.BL1: "BL1", O.BL0: "BL0"}
+
+
+def is_l0(form: int) -> bool:
+    return form in (O.SL0, O.BL0)
+
+
+def to_device(A: np.ndarray, lda: int | None = None, dtype=None):
+    """Column-major device copy of A (p, n) as a torch (p, n) view with stride (1, lda)."""
+    import torch
+    p, n = A.shape
+    lda = p if lda is None else lda
+    buf = np.zeros((n, lda), dtype=np.float32 if dtype is None else dtype)
+    buf[:, :p] = A.T
+    t = torch.from_numpy(buf).cuda()
+    return t[:, :p].t()
+
+
+def x_to_device(X: np.ndarray):
+    import torch
+    X = np.asarray(X, dtype=np.float32).reshape(X.shape[0], -1)
+    return torch.from_numpy(np.ascontiguousarray(X.T)).cuda().t()
+
+
+def chain_depth(p: int) -> int:
+    """Upper bound on the length of the longest FP32 summation chain of one
+    correlation on the GPU (per-lane sequential part + tree levels)."""
+    return 4 * math.ceil(p / 256) + 48
+
+
+def corr_band(A64: np.ndarray, X64: np.ndarray) -> np.ndarray:
+    """Forward-error bound of the FP32 correlation a_i^T x_j (n x m)."""
+    p = A64.shape[0]
+    return chain_depth(p) * 2.0 ** -24 * (np.abs(A64).T @ np.abs(X64)) + 1e-30
+
+
+def margins(Y: np.ndarray, form: int, gamma: float, mu: np.ndarray):
+    """Threshold margin per element and its band given the correlation band."""
+    if is_l0(form):
+        return (mu[None, :] * Y) ** 2 - gamma
+    return mu[None, :] * np.abs(Y) - gamma
+
+
+def margin_band(Y: np.ndarray, eb: np.ndarray, form: int, mu: np.ndarray):
+    if is_l0(form):
+        return mu[None, :] ** 2 * (2 * np.abs(Y) * eb + eb * eb)
+    return mu[None, :] * eb
+
+
+def trajectory(A64, form, m, gamma, mu, X0, iters):
+    """Oracle iterates X_0..X_{iters-1} (composition of oracle.step / oracle.retract)."""
+    Xs = [np.asfortranarray(X0)]
+    X = Xs[0]
+    for _ in range(iters - 1):
+        st = O.step(A64, form, X, gamma, mu=None if m == 1 and form < 2 else mu)
+        if st["F"] == 0.0:
+            break
+        X, _ = O.retract(st["G"], st["nnz"], X)
+        Xs.append(X)
+    return Xs
+
+
+def pick_gamma(A64, form, m, mu, X0, gamma0, iters=1, safety=8.0, tries=60):
+    """Smallest nudge of gamma0 (multiplicative, deterministic) such that at every
+    oracle iterate no threshold margin lies within `safety` x its FP32 band."""
+    mu = np.ones(m) if mu is None else np.asarray(mu, dtype=np.float64)
+    for k in range(tries):
+        g = gamma0 * (1.0 + 0.0137 * k) if k else gamma0
+        ok = True
+        for X in trajectory(A64, form, m, g, mu, X0, iters):
+            Y = A64.T @ X
+            eb = corr_band(A64, X)
+            if np.any(np.abs(margins(Y, form, g, mu)) <= safety * margin_band(Y, eb, form, mu)):
+                ok = False
+                break
+        if ok:
+            return g
+    raise RuntimeError("could not place gamma away from ties")
+
+
+def fp32_round(X: np.ndarray) -> np.ndarray:
+    return np.asarray(X, dtype=np.float32).astype(np.float64)
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))

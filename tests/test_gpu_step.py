@@ -1,0 +1,84 @@
+"""Step parity: one pass of the HIP path (gpspca_step through the C ABI) against
+the FP64 oracle at the same FP32 point X, element by element.
+
+Supports must match exactly (gamma is placed so that no margin lies within
+8x the FP32 forward-error band of the correlation); thresholded values within
+the band; G and the objective within 1e-5 relative."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import generators as W
+
+from _util import (FORM_NAMES, corr_band, fp32_round, is_l0, margin_band, margins, pick_gamma,
+                   rel, to_device, x_to_device)
+
+pytestmark = pytest.mark.gpu
+
+# (form, m, p, n, lda_extra, seed): covers the fused m = 1 kernel (several
+# thread counts, ragged row quads), the block path with 1, 2 and 3 component
+# groups, the non-vector path (lda not a multiple of 4) and p > 20480 (m = 1 on
+# the block kernels).
+CASES = [
+    (O.SL1, 1, 1003, 5011, 0, 1),
+    (O.SL0, 1, 1003, 5011, 0, 2),
+    (O.SL1, 1, 4999, 3001, 0, 3),
+    (O.SL0, 1, 4999, 3001, 1, 4),
+    (O.SL1, 1, 90, 2000, 0, 5),
+    (O.SL0, 1, 21003, 700, 0, 6),
+    (O.BL1, 1, 777, 1500, 0, 7),
+    (O.BL1, 3, 517, 4099, 0, 8),
+    (O.BL0, 3, 517, 4099, 3, 9),
+    (O.BL1, 8, 2050, 3333, 0, 10),
+    (O.BL0, 8, 2050, 3333, 0, 11),
+    (O.BL1, 13, 301, 2000, 0, 12),
+    (O.BL0, 20, 300, 1500, 2, 13),
+    (O.BL1, 64, 200, 900, 0, 14),
+]
+
+
+def _ids(c):
+    return f"{FORM_NAMES[c[0]]}-m{c[1]}-p{c[2]}-n{c[3]}-ldx{c[4]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_step_parity(gpu, case):
+    form, m, p, n, extra, seed = case
+    print(f"\n[step] {_ids(case)} seed={seed}", flush=True)
+    A32, _, _ = W.planted_block(p, n, min(m, 4), seed, k=min(50, n // 8))
+    A64 = A32.astype(np.float64)
+    mu = np.linspace(1.0, 0.6, m) if form >= O.BL1 else np.ones(1)
+    X0 = fp32_round(O.init(A64, m)[0])
+    frac = 0.05 if not is_l0(form) else 0.02
+    g0 = W.gamma_absolute(A64, is_l0(form), frac)
+    gamma = pick_gamma(A64, form, m, mu, X0, g0, iters=1)
+    ref = O.step(A64, form, X0, gamma, mu=mu if form >= O.BL1 else None)
+
+    Ad = to_device(A32, lda=p + extra)
+    out = gpu.step(Ad, form, x_to_device(X0), gamma, mu=list(mu) if form >= O.BL1 else None)
+    S = out.S.cpu().numpy().astype(np.float64)
+    G = out.G.cpu().numpy()
+
+    np.testing.assert_array_equal(S != 0, ref["S"] != 0)
+    assert list(out.nnz) == list(ref["nnz"])
+    eb = corr_band(A64, X0)
+    sb = eb * mu[None, :] + 1e-7 * np.abs(ref["S"])
+    assert np.all(np.abs(S - ref["S"]) <= sb)
+    assert rel(G, ref["G"]) <= 1e-5
+    np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5, atol=1e-9 * max(1.0, ref["F"]))
+
+
+@pytest.mark.parametrize("form", [O.SL1, O.SL0, O.BL1, O.BL0])
+def test_step_zero_gamma_dense_support(gpu, form):
+    """gamma = 0: every entry is active, the back-projection is a full GEMM."""
+    p, n = 333, 2500
+    m = 1 if form < O.BL1 else 5
+    A32 = W.gaussian(p, n, 21)
+    A64 = A32.astype(np.float64)
+    X0 = fp32_round(W.random_orthonormal(p, m, 22))
+    mu = np.ones(m)
+    ref = O.step(A64, form, X0, 0.0, mu=mu if form >= O.BL1 else None)
+    out = gpu.step(to_device(A32), form, x_to_device(X0), 0.0)
+    assert list(out.nnz) == [n] * m
+    assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
+    np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
