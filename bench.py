@@ -1,0 +1,215 @@
+"""Benchmark of the GP-SPCA power iteration on one MI355X.
+
+A step is one full pass of the power iteration (correlation, threshold,
+back-projection, fixed-order reductions, FP64 retraction and the on-device
+stopping rule) over the block workload A: 10000 x 100000 FP32 (4 GB,
+N(0,1) noise plus 8 planted sparse components), m = 8, BL1 with
+gamma = 0.05 max ||a_i|| and mu = 1.  A is resident in HBM before timing.
+
+Prints one JSON line with the headline rate (passes/s), the roofline of the
+dominant kernel (HBM bytes of A per launch over its HIP-event duration), and
+the FP64 oracle timed on the host's cores on a column sample of the same A.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GPM iters/s + HBM GB/s at 10k×100k m=8; solves/s, p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--p", type=int, default=10000)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--m", type=int, default=8)
+    ap.add_argument("--form", default="BL1", choices=["SL1", "SL0", "BL1", "BL0"])
+    ap.add_argument("--frac", type=float, default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extra", action="store_true", help="also time BL0 and the m=1 workload")
+    return ap.parse_args()
+
+
+def column_norm_max(A: np.ndarray) -> float:
+    best = 0.0
+    step = 8192
+    for c in range(0, A.shape[1], step):
+        blk = A[:, c:c + step].astype(np.float64)
+        best = max(best, float(np.sqrt((blk * blk).sum(axis=0)).max()))
+    return best
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_pass.hip",):
+        h.update(open(os.path.join(ROOT, "paper_1312_6182_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, workload_key: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload_key}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def time_gpu(G, torch, Ad, form, m, gamma, steps, warmup):
+    # warm-up run from the default start (top-m norm columns), then the timed
+    # run continues from its iterate with exactly `steps` passes (tol = 0).
+    w = G.solve(Ad, form, m, gamma, tol=0.0, max_iter=max(1, warmup))
+    torch.cuda.synchronize()
+    G.profile_read()
+    G.profile_enable(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    r = G.solve(Ad, form, m, gamma, X0=w.X, tol=0.0, max_iter=steps)
+    t1.record()
+    torch.cuda.synchronize()
+    G.profile_enable(False)
+    ms = t0.elapsed_time(t1)
+    kms, launches, kname = G.profile_read()
+    return r, ms, kms, launches, kname
+
+
+def cpu_baseline(A32, form_id, m, gamma, budget_s):
+    import oracle as O
+    p, n = A32.shape
+    ns = min(n, 20000)
+    As = A32[:, :ns].astype(np.float64)
+    X, _ = O.init(As, m)
+    passes = 0
+    t0 = time.perf_counter()
+    while True:
+        st = O.step(As, form_id, X, gamma, mu=None)
+        passes += 1
+        if st["F"] == 0.0:
+            break
+        X, _ = O.retract(st["G"], st["nnz"], X)
+        if time.perf_counter() - t0 > budget_s or passes >= 50:
+            break
+    el = time.perf_counter() - t0
+    per_pass_sample = el / passes
+    full_pass = per_pass_sample * (n / ns)
+    return {
+        "value": 1.0 / full_pass,
+        "unit": "iters/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"FP64 oracle passes (step + retract) on the first {ns} of {n} columns of the same A "
+                  f"({passes} passes in {el:.1f} s), scaled by n/{ns} to one full pass",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_1312_6182_amd as G
+    from workloads import generators as W
+
+    G.load()
+    form_id = {"SL1": 0, "SL0": 1, "BL1": 2, "BL0": 3}[args.form]
+    l0 = form_id in (1, 3)
+    m = 1 if form_id < 2 else args.m
+    frac = args.frac if args.frac is not None else (0.01 if l0 else 0.05)
+    t = time.perf_counter()
+    A32, _, _ = W.planted_block(args.p, args.n, max(1, min(args.m, 8)), args.seed, k=200)
+    cmax = column_norm_max(A32)
+    gamma = frac * (cmax * cmax if l0 else cmax)
+    At = torch.from_numpy(np.ascontiguousarray(A32.T)).cuda()
+    Ad = At.t()
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t
+    print(f"[bench] data ready in {prep_s:.1f}s: p={args.p} n={args.n} m={m} {args.form} "
+          f"gamma={gamma:.4g}", file=sys.stderr, flush=True)
+
+    r, ms, kms, launches, kname = time_gpu(G, torch, Ad, form_id, m, gamma, args.steps, args.warmup)
+    ms_per_step = ms / args.steps
+    iters_per_s = 1000.0 / ms_per_step
+    a_bytes = float(args.p) * args.n * 4.0
+    k_avg_ms = kms / max(1, launches)
+    achieved = a_bytes / (k_avg_ms * 1e-3) / 1e9
+    nnz = int(r.support_mask().sum().item())
+    print(f"[bench] {args.steps} passes in {ms:.2f} ms; {kname} avg {k_avg_ms*1e3:.1f} us "
+          f"({achieved:.0f} GB/s); final support {nnz}", file=sys.stderr, flush=True)
+    wkey = f"{args.form}_m{m}_p{args.p}_n{args.n}"
+    traffic = traffic_from_profiles(kname, wkey)
+
+    out = {
+        "metric": METRIC,
+        "value": iters_per_s,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.form} m={m}, A {args.p}x{args.n} FP32 column-major (N(0,1) noise + "
+                        f"{min(args.m, 8)} planted 200-sparse components, seed {args.seed}), "
+                        f"gamma={frac} max||a_i||{'^2' if l0 else ''}, mu=1, tol=0 (fixed passes)",
+            "p": args.p, "n": args.n, "m": m, "form": args.form, "gamma": gamma,
+        },
+        "hbm_gbps": a_bytes * args.steps / (ms * 1e-3) / 1e9,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kname,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": a_bytes,
+            "avg_launch_us": k_avg_ms * 1e3,
+        },
+        "final_support_nnz": nnz,
+    }
+    if args.extra:
+        extra = {}
+        for fname, fid in (("BL0", 3),):
+            g2 = 0.01 * cmax * cmax
+            r2, ms2, kms2, l2, kn2 = time_gpu(G, torch, Ad, fid, m, g2, args.steps, args.warmup)
+            extra[fname] = {"iters_per_s": 1000.0 * args.steps / ms2,
+                            "kernel_gbps": a_bytes / (kms2 / max(1, l2) * 1e-3) / 1e9}
+        out["extra"] = extra
+    if not args.no_cpu:
+        print("[bench] timing the oracle on host cores", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(A32, form_id, m, gamma, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -72,8 +72,14 @@ def trajectory(A64, form, m, gamma, mu, X0, iters):
 
 
 def pick_gamma(A64, form, m, mu, X0, gamma0, iters=1, safety=8.0, tries=60):
-    """Smallest nudge of gamma0 (multiplicative, deterministic) such that at every
-    oracle iterate no threshold margin lies within `safety` x its FP32 band."""
+    """l0 forms: smallest nudge of gamma0 (multiplicative, deterministic) such that
+    at every oracle iterate no threshold margin lies within `safety` x its FP32
+    band -- a hard threshold that flips moves G by mu*y*a_i, so l0 parity needs
+    no ties.  l1 forms: gamma0 unchanged -- the soft threshold is continuous
+    (s is within the band of 0 on both sides of a tie), so ties are excluded
+    from the support comparison instead (tie_mask)."""
+    if not is_l0(form):
+        return gamma0
     mu = np.ones(m) if mu is None else np.asarray(mu, dtype=np.float64)
     for k in range(tries):
         g = gamma0 * (1.0 + 0.0137 * k) if k else gamma0
@@ -98,3 +104,13 @@ def rel(a, b) -> float:
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def tie_mask(A64, X64, form, gamma, mu, safety=4.0):
+    """Elements (n x m) whose threshold margin at X lies within `safety` x the FP32
+    band: there the GPU and the oracle may legitimately decide differently."""
+    m = X64.shape[1]
+    mu = np.ones(m) if mu is None else np.asarray(mu, dtype=np.float64)
+    Y = A64.T @ X64
+    eb = corr_band(A64, X64)
+    return np.abs(margins(Y, form, gamma, mu)) <= safety * margin_band(Y, eb, form, mu)

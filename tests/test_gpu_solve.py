@@ -1,27 +1,36 @@
 """Solve parity: full power iterations of the HIP path (gpspca_solve through the
 C ABI) against the FP64 oracle from the same start, with tol = 0 and a fixed
 pass count so both stop at the same k.  X, Z and the objective trace within
-1e-5 relative; supports exactly equal (gamma placed away from ties at every
-oracle iterate)."""
+1e-5 relative; supports exactly equal outside the FP32 tie band (l0 cases place
+gamma away from ties at every oracle iterate)."""
 import numpy as np
 import pytest
 
 import oracle as O
 from workloads import generators as W
 
-from _util import FORM_NAMES, fp32_round, is_l0, pick_gamma, rel, to_device, x_to_device
+from _util import (FORM_NAMES, fp32_round, is_l0, pick_gamma, rel, tie_mask, to_device,
+                   x_to_device)
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 
 
-def _compare(res, ref, m):
+def _compare(res, ref, m, A64=None, form=None, gamma=None, mu=None):
+    """Supports compared outside the FP32 tie band of the final iterate (l1 forms
+    only; l0 cases place gamma away from ties at every iterate)."""
     X = res.X.cpu().numpy().astype(np.float64)
     Z = res.Z.cpu().numpy().astype(np.float64)
     assert res.n_iter == ref["n_iter"]
     assert res.status == ref["status"]
-    np.testing.assert_array_equal(res.support_mask().cpu().numpy(), ref["support"])
+    sup = res.support_mask().cpu().numpy()
+    if A64 is not None and not is_l0(form):
+        ties = tie_mask(A64, ref["X"], form, gamma, mu)
+        assert ties.sum() <= max(2, 1e-3 * ties.size)
+        np.testing.assert_array_equal(sup[~ties], ref["support"][~ties])
+    else:
+        np.testing.assert_array_equal(sup, ref["support"])
     assert rel(X, ref["X"]) <= TOL
     for j in range(m):
         assert rel(Z[:, j], ref["Z"][:, j]) <= TOL
@@ -57,7 +66,7 @@ def test_solve_parity_fixed_passes(gpu, case):
     ref = O.solve(A64, form, m, gamma, mu=mu, X0=X0, tol=0.0, max_iter=iters)
     res = gpu.solve(to_device(A32), form, m, gamma, mu=None if mu is None else list(mu),
                     X0=x_to_device(X0), tol=0.0, max_iter=iters)
-    _compare(res, ref, m)
+    _compare(res, ref, m, A64, form, gamma, mu)
 
 
 @pytest.mark.parametrize("form", [O.SL1, O.BL0])
@@ -77,7 +86,7 @@ def test_default_start_matches_oracle(gpu, form):
     gamma = pick_gamma(A64, form, m, None, Xi, g0, iters=6)
     ref = O.solve(A64, form, m, gamma, tol=0.0, max_iter=6)
     res = gpu.solve(to_device(A32), form, m, gamma, tol=0.0, max_iter=6)
-    _compare(res, ref, m)
+    _compare(res, ref, m, A64, form, gamma, None)
 
 
 def test_paper_shape_c1_converged(gpu):
@@ -95,7 +104,7 @@ def test_paper_shape_c1_converged(gpu):
     ratios = np.abs(np.diff(tr)) / np.abs(tr[:-1])
     assert np.all(np.abs(ratios - 1e-4) > 1e-6)
     res = gpu.solve(to_device(A32), O.SL1, 1, gamma, tol=1e-4, max_iter=1000)
-    _compare(res, ref, 1)
+    _compare(res, ref, 1, A64, O.SL1, gamma, None)
 
 
 @pytest.mark.parametrize("form", [O.SL1, O.SL0, O.BL1, O.BL0])
@@ -146,7 +155,7 @@ def test_degenerate_shapes(gpu, shape):
     gamma = pick_gamma(A64, form, m, None, X0, g0, iters=5)
     ref = O.solve(A64, form, m, gamma, X0=X0, tol=0.0, max_iter=5)
     res = gpu.solve(to_device(A32), form, m, gamma, X0=x_to_device(X0), tol=0.0, max_iter=5)
-    _compare(res, ref, m)
+    _compare(res, ref, m, A64, form, gamma, None)
 
 
 def test_deterministic_bitwise(gpu):

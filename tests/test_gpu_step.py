@@ -10,8 +10,8 @@ import pytest
 import oracle as O
 from workloads import generators as W
 
-from _util import (FORM_NAMES, corr_band, fp32_round, is_l0, margin_band, margins, pick_gamma,
-                   rel, to_device, x_to_device)
+from _util import (FORM_NAMES, corr_band, fp32_round, is_l0, pick_gamma, rel, tie_mask,
+                   to_device, x_to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -59,8 +59,12 @@ def test_step_parity(gpu, case):
     S = out.S.cpu().numpy().astype(np.float64)
     G = out.G.cpu().numpy()
 
-    np.testing.assert_array_equal(S != 0, ref["S"] != 0)
-    assert list(out.nnz) == list(ref["nnz"])
+    ties = tie_mask(A64, X0, form, gamma, mu if form >= O.BL1 else None)
+    if is_l0(form):
+        assert not ties.any()
+    np.testing.assert_array_equal((S != 0)[~ties], (ref["S"] != 0)[~ties])
+    nt = ties.sum(axis=0)
+    assert np.all(np.abs(np.asarray(out.nnz) - ref["nnz"]) <= nt)
     eb = corr_band(A64, X0)
     sb = eb * mu[None, :] + 1e-7 * np.abs(ref["S"])
     assert np.all(np.abs(S - ref["S"]) <= sb)
