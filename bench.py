@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", action="store_true", help="also time BL0 and the m=1 workload")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary workloads (BL0, m=64, m=1 and the 5000x50000 single-unit case)")
     return ap.parse_args()
 
 
@@ -55,10 +56,14 @@ def column_norm_max(A: np.ndarray) -> float:
     return best
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("k_pass.hip",):
-        h.update(open(os.path.join(ROOT, "paper_1312_6182_amd", "csrc", f), "rb").read())
+KERNEL_SOURCE = {"k_corr_mfma": "k_corr_mfma.hip", "k_corr": "k_pass.hip", "k_pass_m1": "k_pass.hip"}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of the source file that defines `kernel` (traffic counters are only
+    reported while they were taken on this exact source)."""
+    f = KERNEL_SOURCE.get(kernel, "k_pass.hip")
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_1312_6182_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -72,7 +77,7 @@ def traffic_from_profiles(kernel: str, workload_key: str):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_hash") != kernel_source_hash():
+    if d.get("kernel_hash") != kernel_source_hash(kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -197,13 +202,28 @@ def main():
         },
         "final_support_nnz": nnz,
     }
-    if args.extra:
+    if not args.no_extra:
         extra = {}
-        for fname, fid in (("BL0", 3),):
-            g2 = 0.01 * cmax * cmax
-            r2, ms2, kms2, l2, kn2 = time_gpu(G, torch, Ad, fid, m, g2, args.steps, args.warmup)
-            extra[fname] = {"iters_per_s": 1000.0 * args.steps / ms2,
-                            "kernel_gbps": a_bytes / (kms2 / max(1, l2) * 1e-3) / 1e9}
+        xs = max(5, args.steps // 3)
+
+        def rec(name, Adev, fid, mm, g, nbytes):
+            r2, ms2, kms2, l2, kn2 = time_gpu(G, torch, Adev, fid, mm, g, xs, 2)
+            extra[name] = {"iters_per_s": 1000.0 * xs / ms2, "kernel": kn2,
+                           "kernel_gbps": nbytes / (kms2 / max(1, l2) * 1e-3) / 1e9,
+                           "ms_per_step": ms2 / xs}
+            print(f"[bench] extra {name}: {extra[name]}", file=sys.stderr, flush=True)
+
+        if args.p == 10000 and args.n == 100000:
+            rec("c3_BL0_m8", Ad, 3, 8, 0.01 * cmax * cmax, a_bytes)
+            rec("c3_BL1_m64", Ad, 2, 64, 0.05 * cmax, a_bytes)
+            rec("c3_SL1_m1", Ad, 0, 1, 0.05 * cmax, a_bytes)
+        A2, _, _, _ = W.planted_single(5000, 50000, args.seed, k=500)
+        c2max = column_norm_max(A2)
+        A2d = torch.from_numpy(np.ascontiguousarray(A2.T)).cuda().t()
+        rec("c2_SL1_f0.05", A2d, 0, 1, 0.05 * c2max, 5000 * 50000 * 4.0)
+        rec("c2_SL0_f0.01", A2d, 1, 1, 0.01 * c2max * c2max, 5000 * 50000 * 4.0)
+        rec("c2_SL1_f0.01_dense", A2d, 0, 1, 0.01 * c2max, 5000 * 50000 * 4.0)
+        del A2d
         out["extra"] = extra
     if not args.no_cpu:
         print("[bench] timing the oracle on host cores", file=sys.stderr, flush=True)

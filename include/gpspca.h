@@ -129,6 +129,32 @@ int gpspca_step(const gpspca_matrix* A, int form, int m, double gamma, const dou
                 float* S, double* G, double* f, int64_t* nnz);
 
 /*
+ * Gamma path: K independent single-unit problems on the same A (Table 1, SL1
+ * or SL0), problem k with its own sparsity weight gammas[k].  Every pass over A
+ * serves all K problems (the correlations of the K columns of X come from one
+ * read of A); each column is retracted on its own sphere (x_k = g_k/||g_k||) and
+ * has its own stopping rule, after which it is frozen, so column k's result is
+ * that of gpspca_solve(A, form, 1, gammas[k], ...) from the same start.
+ *
+ *  K          1 <= K <= GPSPCA_MAX_M problems.
+ *  gammas     host, K absolute weights >= 0.
+ *  X0         device p x K starts (leading dim p; each column is normalized), or
+ *             NULL: every column starts at the normalized column of largest norm.
+ *  workspace  >= gpspca_path_workspace_bytes(A, K, max_iter) bytes, 256-aligned.
+ * Outputs: X (device p x K), Z (device n x K), support (device ceil(n/32) x K
+ * words) as in gpspca_solve; obj_trace (host, K x max_iter doubles, problem k's
+ * trace at obj_trace[k * max_iter ...]); n_iter and status (host, K ints).
+ * Returns GPSPCA_OK when every problem converged, otherwise the largest
+ * per-problem status (or a negative error).  Synchronizes `stream`.
+ */
+size_t gpspca_path_workspace_bytes(const gpspca_matrix* A, int K, int max_iter);
+int gpspca_solve_path(const gpspca_matrix* A, int form, int K, const double* gammas,
+                      const float* X0, double tol, int max_iter,
+                      void* workspace, size_t ws_bytes, void* stream,
+                      float* X, float* Z, uint32_t* support, double* obj_trace,
+                      int* n_iter, int* status);
+
+/*
  * Column norms ||a_i||_2 of A (FP64 accumulation) into device `norms` (n doubles).
  * Stream-ordered; does not synchronize.
  */

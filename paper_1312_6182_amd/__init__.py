@@ -15,7 +15,8 @@ def __getattr__(name):
     # torch-facing helpers are imported lazily so that loading the C library
     # (e.g. for symbol checks) does not require a GPU.
     if name in ("solve", "step", "column_norms", "workspace_bytes", "matrix", "column_major",
-                "profile_enable", "profile_read", "SolveResult", "StepResult"):
+                "profile_enable", "profile_read", "SolveResult", "StepResult", "solve_path",
+                "PathResult"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

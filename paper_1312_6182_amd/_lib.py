@@ -48,6 +48,8 @@ SIGNATURES = {
     "gpspca_solve": (_I, [_MP, _I, _I, _D, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P]),
     "gpspca_step": (_I, [_MP, _I, _I, _D, _P, _P, _P, _SZ, _P, _P, _P, _P, _P]),
     "gpspca_column_norms": (_I, [_MP, _P, _P]),
+    "gpspca_path_workspace_bytes": (_SZ, [_MP, _I, _I]),
+    "gpspca_solve_path": (_I, [_MP, _I, _I, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P, _P]),
     "gpspca_last_error": (ctypes.c_char_p, []),
     "gpspca_version": (ctypes.c_char_p, []),
     "gpspca_profile_enable": (_I, [_I]),

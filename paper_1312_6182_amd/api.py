@@ -181,3 +181,52 @@ def profile_read():
     buf = ctypes.create_string_buffer(128)
     L.load().gpspca_profile_read(ctypes.byref(ms), ctypes.byref(cnt), buf, 128)
     return ms.value, cnt.value, buf.value.decode()
+
+
+@dataclass
+class PathResult:
+    X: torch.Tensor          # (p, K) column-major view
+    Z: torch.Tensor          # (n, K) column-major view
+    support: torch.Tensor    # (K, ceil(n/32)) int32 bit words
+    traces: list             # per problem: objective F_0 .. F_{n_iter[k]-1}
+    n_iter: list
+    status: list
+    rc: int
+
+    def support_mask(self) -> torch.Tensor:
+        return SolveResult(self.X, self.Z, self.support, [], 0, 0).support_mask()
+
+
+def solve_path(A: torch.Tensor, form: int, gammas: Sequence[float],
+               X0: Optional[torch.Tensor] = None, tol: float = 1e-4, max_iter: int = 1000,
+               col_scale: Optional[torch.Tensor] = None,
+               stream: Optional[torch.cuda.Stream] = None) -> SolveResult:
+    """K single-unit problems sharing every pass over A (gpspca_solve_path)."""
+    lib = L.load()
+    M = matrix(A, col_scale)
+    p, n = A.shape
+    K = len(gammas)
+    nb = lib.gpspca_path_workspace_bytes(ctypes.byref(M), K, max_iter)
+    if nb == 0:
+        raise L.GpspcaError(L.EINVAL, L.last_error())
+    ws = _workspace(int(nb), A.device)
+    Xt = torch.empty((K, p), dtype=torch.float32, device=A.device)
+    Zt = torch.empty((K, n), dtype=torch.float32, device=A.device)
+    sup = torch.empty((K, (n + 31) // 32), dtype=torch.int32, device=A.device)
+    g = (ctypes.c_double * K)(*[float(v) for v in gammas])
+    tr = (ctypes.c_double * (K * max_iter))()
+    nit = (ctypes.c_int * K)()
+    sts = (ctypes.c_int * K)()
+    x0p = None
+    if X0 is not None:
+        X0c = X0.t().contiguous()
+        if X0c.shape != (K, p) or X0c.dtype != torch.float32:
+            raise ValueError("X0 must be a float32 (p, K) tensor")
+        x0p = X0c.data_ptr()
+    rc = lib.gpspca_solve_path(ctypes.byref(M), form, K, g, x0p, float(tol), int(max_iter),
+                               ws.data_ptr(), ws.numel(), _stream_ptr(stream), Xt.data_ptr(),
+                               Zt.data_ptr(), sup.data_ptr(), tr, nit, sts)
+    L.check(rc, "gpspca_solve_path")
+    traces = [list(tr[k * max_iter:k * max_iter + nit[k]]) for k in range(K)]
+    return PathResult(X=Xt.t(), Z=Zt.t(), support=sup, traces=traces, n_iter=list(nit),
+                      status=list(sts), rc=rc)

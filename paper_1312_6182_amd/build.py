@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgpspca.so")
-SOURCES = ["k_pass.hip", "k_reduce.hip", "k_init_fin.hip", "gpspca_abi.cpp"]
+SOURCES = ["k_pass.hip", "k_corr_mfma.hip", "k_reduce.hip", "k_init_fin.hip", "gpspca_abi.cpp"]
 ARCH = "gfx950"
 
 

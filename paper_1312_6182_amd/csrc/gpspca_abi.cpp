@@ -90,8 +90,10 @@ static int check_problem(const gpspca_matrix* A, int form, int m, double gamma, 
 }
 
 // ----------------------------------------------------------------------- plan
-static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int ncu, Plan* pl) {
+static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int ncu, Plan* pl,
+                      int path = 0) {
     std::memset(pl, 0, sizeof(Plan));
+    pl->path = path;
     pl->p = A->p;
     pl->n = A->n;
     pl->lda = A->lda;
@@ -99,11 +101,13 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->form = form;
     pl->l0 = (form == GPSPCA_SL0 || form == GPSPCA_BL0) ? 1 : 0;
     pl->max_iter = max_iter;
-    pl->ldx = (int)align_up((size_t)A->p, 4);
+    // rows of the internal X buffers: room for the 32-row stages of the matrix-core
+    // kernel and at least one quad of zero rows past p
+    pl->ldx = (int)align_up((size_t)A->p + 4, 32);
     pl->vec4 = ((A->lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A->data) & 15) == 0);
     const int64_t nq = cdiv(A->p, 4);
 
-    pl->fused_m1 = (m == 1 && A->p <= 20480) ? 1 : 0;
+    pl->fused_m1 = (m == 1 && A->p <= 20480 && !path) ? 1 : 0;
     if (pl->fused_m1) {
         const int cand[4] = {64, 256, 512, 1024};
         int T = 1024;
@@ -118,16 +122,26 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         pl->npart = pl->m1_grid;
         pl->nwave_part = pl->m1_grid;
     } else {
-        pl->corr_M = m >= 5 ? 8 : m >= 3 ? 4 : m == 2 ? 2 : 1;
-        int64_t grid = std::min<int64_t>((int64_t)ncu * 2, std::max<int64_t>(1, cdiv(A->n, 32)));
-        pl->corr_grid = (int)std::max<int64_t>(1, grid);
-        pl->nwave_part = pl->corr_grid * 4;
+        pl->use_mfma = pl->vec4;
+        if (pl->use_mfma) {
+            // one wavefront per workgroup, four per CU (LDS-bound)
+            pl->corr_M = 16;
+            int64_t grid = std::min<int64_t>((int64_t)ncu * 4, cdiv(A->n, 16));
+            pl->corr_grid = (int)std::max<int64_t>(1, grid);
+            pl->nwave_part = pl->corr_grid;
+        } else {
+            pl->corr_M = m >= 5 ? 8 : m >= 3 ? 4 : m == 2 ? 2 : 1;
+            int64_t grid = std::min<int64_t>((int64_t)ncu * 2, std::max<int64_t>(1, cdiv(A->n, 32)));
+            pl->corr_grid = (int)std::max<int64_t>(1, grid);
+            pl->nwave_part = pl->corr_grid * 4;
+        }
         pl->bp_kq = 2;
         pl->bp_rb = (int)cdiv(nq, 256 * pl->bp_kq);
         int64_t cr = std::min<int64_t>(cdiv(A->n, 1024), std::max<int64_t>(1, (4LL * ncu) / pl->bp_rb));
         pl->bp_cr = (int)std::max<int64_t>(1, cr);
         pl->npart = pl->bp_cr;
     }
+    pl->mpad = pl->fused_m1 ? 1 : (int)align_up((size_t)m, (size_t)pl->corr_M);
     const int64_t ne = (int64_t)m * pl->ldx;
     const int64_t bx = cdiv(ne, 256);
     int64_t split = cdiv(2LL * ncu, bx);
@@ -147,9 +161,9 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     };
     const size_t P = (size_t)A->p, N = (size_t)A->n, M = (size_t)m, L = (size_t)pl->ldx;
     pl->o_ctrl = take(sizeof(Ctrl));
-    pl->o_trace = take(sizeof(double) * (size_t)std::max(1, max_iter));
-    pl->o_x0 = take(sizeof(float) * L * M);
-    pl->o_x1 = take(sizeof(float) * L * M);
+    pl->o_trace = take(sizeof(double) * (size_t)std::max(1, max_iter) * (path ? M : 1));
+    pl->o_x0 = take(sizeof(float) * L * (size_t)pl->mpad);
+    pl->o_x1 = take(sizeof(float) * L * (size_t)pl->mpad);
     pl->o_s = take(sizeof(float) * N * M);
     pl->o_act = take(N);
     pl->o_gpart = take(sizeof(float) * (size_t)pl->npart * M * L);
@@ -167,6 +181,7 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->o_fin = take(sizeof(double) * (size_t)pl->fin_grid * M);
     pl->o_invn = take(sizeof(double) * M);
     pl->o_fcomp = take(sizeof(double) * 2 * M);
+    pl->o_pstate = take(path ? sizeof(PathState) * M : 1);
     pl->total = o;
 }
 
@@ -191,6 +206,7 @@ struct Ptrs {
     double* fin;
     double* invn;
     double* fcomp;
+    PathState* pstate;
 };
 
 static Ptrs carve(const Plan& pl, void* ws) {
@@ -217,11 +233,12 @@ static Ptrs carve(const Plan& pl, void* ws) {
     P.fin = reinterpret_cast<double*>(b + pl.o_fin);
     P.invn = reinterpret_cast<double*>(b + pl.o_invn);
     P.fcomp = reinterpret_cast<double*>(b + pl.o_fcomp);
+    P.pstate = reinterpret_cast<PathState*>(b + pl.o_pstate);
     return P;
 }
 
 static PassParams make_params(const gpspca_matrix* A, const Plan& pl, double gamma,
-                              const double* mu) {
+                              const double* mu, const double* gammas = nullptr) {
     PassParams pp;
     std::memset(&pp, 0, sizeof(pp));
     pp.A = static_cast<const float*>(A->data);
@@ -238,6 +255,7 @@ static PassParams make_params(const gpspca_matrix* A, const Plan& pl, double gam
         const double v = (block && mu && j < pl.m) ? mu[j] : 1.0;
         pp.mu[j] = v;
         pp.muf[j] = (float)v;
+        pp.gam[j] = (gammas && j < pl.m) ? gammas[j] : gamma;
     }
     return pp;
 }
@@ -300,13 +318,24 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
         GPSPCA_HIP(tl.end(st));
         GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, nullptr, P.l1, P.ctrl, st));
     } else {
-        GPSPCA_HIP(launch_corr(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+        if (pl.use_mfma)
+            GPSPCA_HIP(launch_corr_mfma(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+        else
+            GPSPCA_HIP(launch_corr(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         GPSPCA_HIP(tl.end(st));
         GPSPCA_HIP(launch_backproj(pl, pp, P.S, P.act, P.gpart, P.touched, P.ctrl, st));
         GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, P.touched, P.l1, P.ctrl, st));
     }
-    GPSPCA_HIP(launch_gram(pl, P.l1, pl.red_split, Xk, pl.m > 1 ? 1 : 0, P.g64, P.gram, P.ctrl, st));
-    GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp, P.ctrl, st));
+    if (pl.path) {
+        GPSPCA_HIP(launch_gram(pl, P.l1, pl.red_split, Xk, 2, P.g64, P.gram, P.ctrl, st));
+        GPSPCA_HIP(launch_stop_path(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp,
+                                    P.pstate, P.ctrl, st));
+    } else {
+        GPSPCA_HIP(launch_gram(pl, P.l1, pl.red_split, Xk, pl.m > 1 ? 1 : 0, P.g64, P.gram,
+                               P.ctrl, st));
+        GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp, P.ctrl,
+                               st));
+    }
     GPSPCA_HIP(launch_apply(pl, P.g64, Xk, P.coef, Xn, P.ctrl, st));
     return GPSPCA_OK;
 }
@@ -326,6 +355,42 @@ static int pinned_ctrl(Ctrl** out) {
         t_pinned.snap = static_cast<Ctrl*>(p);
     }
     *out = t_pinned.snap;
+    return GPSPCA_OK;
+}
+
+
+// Enqueue passes in growing chunks; the stopping rule runs on the device and
+// the host reads the control block once per chunk (with tol = 0 every pass is
+// enqueued at once).  Returns the final control block in *fin.
+static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int max_iter,
+                      double tol, hipStream_t st, Ctrl* fin) {
+    TimedLaunches tl;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        tl.on = g_prof.on;
+    }
+    Ctrl* snap = nullptr;
+    int rc = pinned_ctrl(&snap);
+    if (rc) return rc;
+    int kk = 0;
+    int chunk = (tol == 0.0) ? max_iter : 1;
+    while (kk < max_iter) {
+        const int c = std::min(chunk, max_iter - kk);
+        for (int i = 0; i < c; ++i) {
+            rc = enqueue_pass(pl, pp, P, kk + i, st, tl);
+            if (rc) return rc;
+        }
+        kk += c;
+        if (kk >= max_iter) break;
+        GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+        GPSPCA_HIP(hipStreamSynchronize(st));
+        if (snap->done) break;
+        chunk = std::min(chunk * 2, 32);
+    }
+    GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    GPSPCA_HIP(hipStreamSynchronize(st));
+    tl.collect(pl.fused_m1 ? "k_pass_m1" : pl.use_mfma ? "k_corr_mfma" : "k_corr");
+    *fin = *snap;
     return GPSPCA_OK;
 }
 
@@ -386,8 +451,8 @@ int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const do
 
     // start: project X0 (or the top-m norm columns) onto the feasible set
     GPSPCA_HIP(launch_ctrl_reset(P.ctrl, max_iter, tol, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * m, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * m, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad, st));
     if (X0) {
         GPSPCA_HIP(launch_load_g64(pl, X0, (int)A->p, P.g64, st));
     } else {
@@ -400,33 +465,9 @@ int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const do
     GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
     GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
 
-    TimedLaunches tl;
-    {
-        std::lock_guard<std::mutex> lk(g_prof.mu);
-        tl.on = g_prof.on;
-    }
-    Ctrl* snap = nullptr;
-    rc = pinned_ctrl(&snap);
+    Ctrl fin;
+    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin);
     if (rc) return rc;
-    int kk = 0;
-    int chunk = (tol == 0.0) ? max_iter : 1;
-    while (kk < max_iter) {
-        const int c = std::min(chunk, max_iter - kk);
-        for (int i = 0; i < c; ++i) {
-            rc = enqueue_pass(pl, pp, P, kk + i, st, tl);
-            if (rc) return rc;
-        }
-        kk += c;
-        if (kk >= max_iter) break;
-        GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-        GPSPCA_HIP(hipStreamSynchronize(st));
-        if (snap->done) break;
-        chunk = std::min(chunk * 2, 32);
-    }
-    GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-    GPSPCA_HIP(hipStreamSynchronize(st));
-    tl.collect(pl.fused_m1 ? "k_pass_m1" : "k_corr");
-    const Ctrl fin = *snap;
     if (fin.status < 0) return fail(fin.status, status_text(fin.status));
     if (fin.n_iter < 1) return fail(GPSPCA_EDEVICE, "solve ended without a pass");
 
@@ -463,7 +504,7 @@ int gpspca_step(const gpspca_matrix* A, int form, int m, double gamma, const dou
     const Ptrs P = carve(pl, workspace);
     const PassParams pp = make_params(A, pl, gamma, mu);
     GPSPCA_HIP(launch_ctrl_reset(P.ctrl, 1, 0.0, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * m, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
     GPSPCA_HIP(hipMemcpy2DAsync(P.x[0], sizeof(float) * pl.ldx, Xin, sizeof(float) * A->p,
                                 sizeof(float) * A->p, m, hipMemcpyDeviceToDevice, st));
     TimedLaunches tl;
@@ -485,6 +526,107 @@ int gpspca_step(const gpspca_matrix* A, int form, int m, double gamma, const dou
         if (nnz) std::memcpy(&nnz[j], &host[m + j], sizeof(int64_t));
     }
     return GPSPCA_OK;
+}
+
+size_t gpspca_path_workspace_bytes(const gpspca_matrix* A, int K, int max_iter) {
+    if (check_matrix(A) != GPSPCA_OK) return 0;
+    if (K < 1 || K > kMaxM) {
+        fail(GPSPCA_EINVAL, "need 1 <= K <= GPSPCA_MAX_M");
+        return 0;
+    }
+    if (max_iter < 1) {
+        fail(GPSPCA_EINVAL, "max_iter must be >= 1");
+        return 0;
+    }
+    int ncu = 0;
+    if (device_cus(&ncu) != GPSPCA_OK) return 0;
+    Plan pl;
+    make_plan(A, GPSPCA_BL1, K, max_iter, ncu, &pl, 1);
+    return pl.total;
+}
+
+int gpspca_solve_path(const gpspca_matrix* A, int form, int K, const double* gammas,
+                      const float* X0, double tol, int max_iter, void* workspace,
+                      size_t ws_bytes, void* stream, float* X, float* Z, uint32_t* support,
+                      double* obj_trace, int* n_iter, int* status) {
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    if (form != GPSPCA_SL1 && form != GPSPCA_SL0)
+        return fail(GPSPCA_EINVAL, "a gamma path takes a single-unit formulation");
+    if (K < 1 || K > kMaxM) return fail(GPSPCA_EINVAL, "need 1 <= K <= GPSPCA_MAX_M");
+    if (!gammas) return fail(GPSPCA_EINVAL, "gammas is NULL");
+    for (int j = 0; j < K; ++j)
+        if (!std::isfinite(gammas[j]) || gammas[j] < 0.0)
+            return fail(GPSPCA_EINVAL, "gammas must be finite and >= 0");
+    if (!std::isfinite(tol) || tol < 0.0) return fail(GPSPCA_EINVAL, "tol must be finite and >= 0");
+    if (max_iter < 1) return fail(GPSPCA_EINVAL, "max_iter must be >= 1");
+    if (!X) return fail(GPSPCA_EINVAL, "X is NULL");
+    if (!workspace) return fail(GPSPCA_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(GPSPCA_EINVAL, "workspace must be 256-byte aligned");
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int ncu = 0;
+    rc = device_cus(&ncu);
+    if (rc) return rc;
+    Plan pl;
+    make_plan(A, form == GPSPCA_SL0 ? GPSPCA_BL0 : GPSPCA_BL1, K, max_iter, ncu, &pl, 1);
+    if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
+    const Ptrs P = carve(pl, workspace);
+    const PassParams pp = make_params(A, pl, 0.0, nullptr, gammas);
+
+    GPSPCA_HIP(launch_ctrl_reset(P.ctrl, max_iter, tol, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad, st));
+    GPSPCA_HIP(launch_fill_zero(P.pstate, sizeof(PathState) * K, st));
+    if (X0) {
+        // every column normalized on its own
+        GPSPCA_HIP(launch_load_g64(pl, X0, (int)A->p, P.g64, st));
+        GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 2, P.g64, P.gram, P.ctrl, st));
+        GPSPCA_HIP(launch_project_diag(pl, P.gram, P.coef, P.ctrl, st));
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+    } else {
+        // all columns start at the normalized column of largest norm
+        Plan p1;
+        make_plan(A, GPSPCA_SL1, 1, 1, ncu, &p1);
+        p1.ldx = pl.ldx;
+        p1.gram_grid = pl.gram_grid;
+        p1.gram_rows = pl.gram_rows;
+        p1.topm_grid = pl.topm_grid;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
+        GPSPCA_HIP(launch_colnorm(pp, P.norms, grid, st));
+        GPSPCA_HIP(launch_topm(p1, P.norms, P.cand_v, P.cand_i, P.idx, st));
+        PassParams pp1 = pp;
+        pp1.m = 1;
+        GPSPCA_HIP(launch_gather(p1, pp1, P.idx, P.g64, st));
+        GPSPCA_HIP(launch_gram(p1, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
+        GPSPCA_HIP(launch_project(p1, P.gram, P.coef, P.ctrl, st));
+        GPSPCA_HIP(launch_apply(p1, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+        GPSPCA_HIP(launch_bcast_col0(pl, P.x[0], st));
+    }
+    Ctrl fin;
+    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin);
+    if (rc) return rc;
+    if (fin.status < 0) return fail(fin.status, status_text(fin.status));
+    if (fin.n_iter < 1) return fail(GPSPCA_EDEVICE, "solve ended without a pass");
+    std::vector<PathState> ps(K);
+    const float* Xf = P.x[(fin.n_iter - 1) & 1];
+    GPSPCA_HIP(launch_copy_x(pl, Xf, X, st));
+    GPSPCA_HIP(launch_finalize(pl, P.S, P.fin, P.invn, Z, support, st));
+    GPSPCA_HIP(hipMemcpyAsync(ps.data(), P.pstate, sizeof(PathState) * K, hipMemcpyDeviceToHost, st));
+    if (obj_trace)
+        GPSPCA_HIP(hipMemcpyAsync(obj_trace, P.trace, sizeof(double) * K * max_iter,
+                                  hipMemcpyDeviceToHost, st));
+    GPSPCA_HIP(hipStreamSynchronize(st));
+    int worst = GPSPCA_OK;
+    for (int j = 0; j < K; ++j) {
+        if (n_iter) n_iter[j] = ps[j].n_iter;
+        if (status) status[j] = ps[j].status;
+        if (ps[j].status < 0) worst = ps[j].status;
+        else if (worst >= 0 && ps[j].status > worst) worst = ps[j].status;
+    }
+    if (worst < 0) return fail(worst, status_text(worst));
+    return worst;
 }
 
 int gpspca_column_norms(const gpspca_matrix* A, double* norms, void* stream) {

@@ -42,6 +42,7 @@ struct PassParams {
     double gamma;
     float muf[kMaxM];      // mu_j in FP32 (for the back-projection weights)
     double mu[kMaxM];      // mu_j in FP64 (for the threshold)
+    double gam[kMaxM];     // gamma of component j (all equal, except on a gamma path)
 };
 
 // Layout of the caller's workspace for one solve (byte offsets).
@@ -50,21 +51,25 @@ struct Plan {
     int64_t p, n, lda;
     int m, form, l0, max_iter;
     int ldx;
+    int mpad;              // columns of the internal X buffers (zero padded to the group size)
     // kernel choice
     int fused_m1;          // 1: single fused pass kernel (m == 1), else corr + back-projection
     int m1_threads, m1_kq, m1_grid;
     int corr_M, corr_grid; // corr kernel: padded component count and grid
     int bp_kq, bp_rb, bp_cr; // back-projection: quads per thread, row blocks, column ranges
     int npart;             // number of G partials
-    int nwave_part;        // number of objective partial slots (waves or workgroups)
+    int nwave_part;        // objective partial slots per component (fpart[j * nwave_part + w])
     int red_split;         // split of the partial reduction
     int gram_rows, gram_grid;
     int fin_grid;
     int topm_grid;
     int vec4;              // float4 loads of A are legal
+    int use_mfma;          // block correlation on the matrix cores (LDS DMA staging)
+    int path;              // gamma path: independent single-unit columns (normalize, per-column stop)
     // workspace offsets (bytes)
     size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
-        o_l1, o_g64, o_gram, o_coef, o_norms, o_cand_v, o_cand_i, o_idx, o_fin, o_invn, o_fcomp;
+        o_l1, o_g64, o_gram, o_coef, o_norms, o_cand_v, o_cand_i, o_idx, o_fin, o_invn, o_fcomp,
+        o_pstate;
     size_t total;
 };
 
@@ -76,6 +81,9 @@ hipError_t launch_pass_m1(const Plan& pl, const PassParams& pp, const float* x, 
 hipError_t launch_corr(const Plan& pl, const PassParams& pp, const float* X, float* S,
                        uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                        hipStream_t st);
+hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                            uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                            hipStream_t st);
 hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
                            const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                            hipStream_t st);
@@ -92,6 +100,20 @@ hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
                        Ctrl* ctrl, hipStream_t st);
+// gamma path: per-column objective, trace, stopping and normalization
+struct PathState {
+    int frozen;            // 1 once this column's stopping rule fired
+    int n_iter;            // passes of this column
+    int status;            // GPSPCA_* status of this column
+    int degenerate;        // F = 0 was reached
+    double last_F;
+};
+hipError_t launch_stop_path(const Plan& pl, const double* fpart, const int* nnzpart,
+                            const double* gram, double* trace, double* coef, double* fcomp,
+                            PathState* ps, Ctrl* ctrl, hipStream_t st);
+hipError_t launch_bcast_col0(const Plan& pl, float* X, hipStream_t st);
+hipError_t launch_project_diag(const Plan& pl, const double* gram, double* coef, Ctrl* ctrl,
+                               hipStream_t st);
 hipError_t launch_project(const Plan& pl, const double* gram, double* coef, Ctrl* ctrl,
                           hipStream_t st);
 hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, const double* coef,

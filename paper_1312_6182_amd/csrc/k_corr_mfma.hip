@@ -1,0 +1,284 @@
+// Correlation + threshold of the block power iteration on the gfx950 matrix
+// cores, with A streamed from HBM into LDS by direct global->LDS DMA.
+//
+//   Y^T = X^T A,  y_ij = a_i^T x_j  (Table 1), then the soft / hard threshold
+//   of each y_ij, S and a per-column activity flag, objective partials.
+//
+// Work decomposition (one wavefront per workgroup, no barriers):
+//   - each wave owns a contiguous range of n/W columns (+-1) and walks it in
+//     chunks of T = 4 tiles of 16 columns (64 columns);
+//   - the rows of a chunk are streamed in stages of 32 rows: 9 DMA
+//     instructions bring the 64 x 32 A tile into LDS (column-major with one
+//     16-byte pad slot per column, so that the MFMA operand reads are free of
+//     bank conflicts), 2 per component block bring the matching X rows;
+//     STAGES stages are in flight while the oldest is consumed;
+//   - each stage feeds v_mfma_f32_16x16x4_f32 with M = 16 columns, N = 16
+//     components, K = 4 rows: lane l supplies A[row 4(l/16)+t][col l%16] and
+//     X[row 4(l/16)+t][comp l%16] for t = 0..3 (one 16-byte LDS read each);
+//   - the accumulators hold D[col][comp] (lane l: comp l%16, columns
+//     4(l/16)+v), so the threshold runs directly on them.
+// LDS reads are issued with inline asm and every wait is explicit, because
+// the compiler cannot count LDS DMA completions across the loop back-edge.
+#include "gpspca_internal.h"
+
+namespace gpspca {
+
+typedef float f4m __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kT = 4;          // column tiles of 16 per chunk
+constexpr int kQS = 8;         // row quads per stage (32 rows)
+constexpr int kSlot = kQS + 1; // padded 16-byte slots per column in LDS
+constexpr int kAStageBytes = 16 * kT * kSlot * 16;  // 9216
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N <= 63, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+__device__ __forceinline__ void wait_lgkm0() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Re-define a register after the preceding (volatile, hence ordered) wait, so
+// that its consumers cannot be scheduled before the wait: the output of an
+// inline-asm LDS read counts as available as soon as the asm is issued.
+__device__ __forceinline__ void after_wait(f4m& v) { asm volatile("" : "+v"(v)); }
+
+__device__ __forceinline__ f4m lds_read16(uint32_t lds_addr) {
+    f4m v;
+    asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(lds_addr) : "memory");
+    return v;
+}
+
+__device__ __forceinline__ void dma16(const float* gptr, uint32_t lds_base) {
+    __builtin_amdgcn_global_load_lds(
+        (const void __attribute__((address_space(1)))*)gptr,
+        (void __attribute__((address_space(3)))*)(uintptr_t)lds_base, 16, 0, 0);
+}
+
+__device__ __forceinline__ bool threshold_m(bool l0, double mu, double gamma, float y, float& s,
+                                            double& fv) {
+    const double yd = (double)y;
+    if (l0) {
+        const double my = mu * yd;
+        const double q = my * my - gamma;
+        if (q > 0.0) { s = (float)my; fv = q; return true; }
+    } else {
+        const double t = mu * fabs(yd) - gamma;
+        if (t > 0.0) { s = (float)(yd > 0.0 ? t : -t); fv = t * t; return true; }
+    }
+    s = 0.f;
+    fv = 0.0;
+    return false;
+}
+
+}  // namespace
+
+// J: component blocks of 16 (m <= 16 J);  STAGES: stages in flight.
+template <int J, int STAGES>
+__global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __restrict__ X,
+                                                  float* __restrict__ S,
+                                                  uint8_t* __restrict__ act,
+                                                  double* __restrict__ fpart,
+                                                  int* __restrict__ nnzpart,
+                                                  const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int XStageBytes = J * 2 * 1024;
+    constexpr int StageBytes = kAStageBytes + XStageBytes;
+    constexpr int PER = 9 + 2 * J;  // DMA instructions per stage
+    __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
+    const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
+
+    const int lane = threadIdx.x;
+    const int p = pp.p, m = pp.m, ldx = pp.ldx;
+    const int nqf = p >> 2;
+    const int rem = p & 3;
+    const int nst = (nqf + kQS - 1) / kQS;
+    const bool l0 = pp.l0 != 0;
+    const int64_t n = pp.n;
+    const int64_t W = gridDim.x, w = blockIdx.x;
+    // exact column partition: every wave streams the same number of columns
+    // (+-1), so HBM traffic is balanced; a partial last chunk repeats its last
+    // column, which costs L2 hits, not HBM reads
+    const int64_t cbeg = n * w / W;
+    const int64_t cend = n * (w + 1) / W;
+
+    const int lj = lane & 15;   // MFMA N index (component within block) / M index
+    const int lk = lane >> 4;   // MFMA K group
+
+    double f_acc[J];
+    int nnz_acc[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) { f_acc[jb] = 0.0; nnz_acc[jb] = 0; }
+
+    // X DMA source pointers: slot L = 64 i + lane -> quad k = 4 i + lane/16, comp lane%16
+    const float* xcol[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
+    const int xzero = ldx - 4;  // a quad of zero rows (ldx >= p + 4)
+
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kT) {
+        // A DMA source columns: slot L = 64 i + lane -> column L / 9, quad slot L % 9
+        const float* acol[kSlot];
+        int aq[kSlot];
+#pragma unroll
+        for (int i = 0; i < kSlot; ++i) {
+            const int L = 64 * i + lane;
+            const int cl = L / kSlot;
+            int q = L % kSlot;
+            q = (q == kQS) ? kQS - 1 : q;  // pad slot: duplicate a real quad
+            int64_t col = c0 + cl;
+            col = (col < cend) ? col : cend - 1;
+            acol[i] = pp.A + col * pp.lda;
+            aq[i] = q;
+        }
+        auto issue = [&](int st) {
+            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+            const int q0 = kQS * st;
+#pragma unroll
+            for (int i = 0; i < kSlot; ++i) {
+                int q = q0 + aq[i];
+                q = (q < nqf) ? q : nqf - 1;
+                dma16(acol[i] + 4 * q, sb + 1024 * i);
+            }
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int q = q0 + 4 * i + lk;
+                    const int off = (q < nqf) ? 4 * q : xzero;
+                    dma16(xcol[jb] + off, sb + kAStageBytes + 1024 * (2 * jb + i));
+                }
+        };
+
+        f4m acc[kT][J];
+#pragma unroll
+        for (int t = 0; t < kT; ++t)
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4m{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+        for (int s = 0; s < STAGES - 1; ++s)
+            if (s < nst) issue(s);
+
+        for (int st = 0; st < nst; ++st) {
+            if (st + STAGES - 1 < nst) issue(st + STAGES - 1);
+            const int ahead = (nst - 1 - st < STAGES - 1) ? nst - 1 - st : STAGES - 1;
+            if constexpr (STAGES >= 4) {
+                if (ahead >= 3) wait_vmcnt<3 * PER>();
+                else if (ahead == 2) wait_vmcnt<2 * PER>();
+                else if (ahead == 1) wait_vmcnt<PER>();
+                else wait_vmcnt<0>();
+            } else if constexpr (STAGES == 3) {
+                if (ahead >= 2) wait_vmcnt<2 * PER>();
+                else if (ahead == 1) wait_vmcnt<PER>();
+                else wait_vmcnt<0>();
+            } else {
+                if (ahead >= 1) wait_vmcnt<PER>();
+                else wait_vmcnt<0>();
+            }
+            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                f4m av[kT], xv[J];
+#pragma unroll
+                for (int t = 0; t < kT; ++t)
+                    av[t] = lds_read16(sb + 16u * (uint32_t)((16 * t + lj) * kSlot + 4 * h + lk));
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    xv[jb] = lds_read16(sb + kAStageBytes + 2048u * jb +
+                                        16u * (uint32_t)((4 * h + lk) * 16 + lj));
+                wait_lgkm0();
+#pragma unroll
+                for (int t = 0; t < kT; ++t) after_wait(av[t]);
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb) after_wait(xv[jb]);
+#pragma unroll
+                for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+                    for (int t = 0; t < kT; ++t)
+#pragma unroll
+                        for (int jb = 0; jb < J; ++jb)
+                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                av[t][tm], xv[jb][tm], acc[t][jb], 0, 0, 0);
+            }
+        }
+
+        // ragged tail rows 4*nqf .. p-1 (p % 4 of them)
+        if (rem) {
+#pragma unroll
+            for (int t = 0; t < kT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int64_t col = c0 + 16 * t + 4 * lk + v;
+                    col = (col < cend) ? col : cend - 1;
+                    const float* ac = pp.A + col * pp.lda;
+                    for (int r = 4 * nqf; r < p; ++r) {
+                        const float a = ac[r];
+#pragma unroll
+                        for (int jb = 0; jb < J; ++jb)
+                            acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
+                    }
+                }
+        }
+
+        // threshold, S, activity flags
+#pragma unroll
+        for (int t = 0; t < kT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t col = c0 + 16 * t + 4 * lk + v;
+                const bool cvalid = col < cend;
+                bool any = false;
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb) {
+                    const int comp = 16 * jb + lj;
+                    if (cvalid && comp < m) {
+                        float s;
+                        double fv;
+                        const bool a = threshold_m(l0, pp.mu[comp], pp.gam[comp], acc[t][jb][v], s, fv);
+                        S[col * m + comp] = s;
+                        if (a) {
+                            f_acc[jb] += fv;
+                            nnz_acc[jb] += 1;
+                            any = true;
+                        }
+                    }
+                }
+                const uint64_t bal = __ballot(any);
+                if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+            }
+    }
+
+    // per-component totals over the lanes sharing lane % 16 (fixed xor order)
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) {
+        double f = f_acc[jb];
+        int c = nnz_acc[jb];
+        f += __shfl_xor(f, 16, 64);
+        c += __shfl_xor(c, 16, 64);
+        f += __shfl_xor(f, 32, 64);
+        c += __shfl_xor(c, 32, 64);
+        const int comp = 16 * jb + lj;
+        if (lane < 16 && comp < m) {
+            fpart[(int64_t)comp * W + w] = f;
+            nnzpart[(int64_t)comp * W + w] = c;
+        }
+    }
+}
+
+hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                            uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                            hipStream_t st) {
+    const dim3 grid(pl.corr_grid), block(64);
+    if (pl.m <= 16)
+        hipLaunchKernelGGL((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
+    else if (pl.m <= 32)
+        hipLaunchKernelGGL((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
+    else
+        hipLaunchKernelGGL((k_corr_mfma<4, 2>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace gpspca

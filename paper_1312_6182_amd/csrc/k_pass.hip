@@ -49,6 +49,16 @@ __device__ __forceinline__ f4 load_quad(const float* __restrict__ col, int q, in
     return v;
 }
 
+// One full quad (4 rows known to lie inside the column).
+template <bool VEC>
+__device__ __forceinline__ f4 load_full(const float* __restrict__ ptr) {
+    if constexpr (VEC) {
+        return __builtin_nontemporal_load(reinterpret_cast<const f4*>(ptr));
+    } else {
+        return f4{ptr[0], ptr[1], ptr[2], ptr[3]};
+    }
+}
+
 __device__ __forceinline__ float dot4(f4 a, f4 b, float acc) {
     acc = __builtin_fmaf(a.x, b.x, acc);
     acc = __builtin_fmaf(a.y, b.y, acc);
@@ -109,7 +119,7 @@ __global__ __launch_bounds__(T) void k_pass_m1(PassParams pp, const float* __res
     const int64_t cb = pp.n * (int64_t)blockIdx.x / gridDim.x;
     const int64_t ce = pp.n * (int64_t)(blockIdx.x + 1) / gridDim.x;
     const bool l0 = pp.l0 != 0;
-    const double gamma = pp.gamma, mu = pp.mu[0];
+    const double gamma = pp.gam[0], mu = pp.mu[0];
     const float muf = pp.muf[0];
 
     f4 xr[KQ], g[KQ];
@@ -123,15 +133,45 @@ __global__ __launch_bounds__(T) void k_pass_m1(PassParams pp, const float* __res
     int nnz_acc = 0;
 
     f4 a[B][KQ];
+    // Loads of one batch: every full quad with one unconditional 16-byte load
+    // (address clamped into the column, value zeroed past the last full quad),
+    // then the ragged last quad (p % 4 rows) by its single owner thread.
+    const int tail_t = nqf % T, tail_k = nqf / T;
+    const bool has_tail = (p & 3) != 0;
     auto load_batch = [&](int64_t c0, f4(&dst)[B][KQ]) {
+        const float* col[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int64_t c = (c0 + b < ce) ? c0 + b : ce - 1;
-            const float* col = pp.A + c * pp.lda;
+            col[b] = pp.A + c * pp.lda;
+        }
+        if (nqf > 0) {
 #pragma unroll
-            for (int k = 0; k < KQ; ++k) {
-                const int q = t + T * k;
-                dst[b][k] = (q < nq) ? load_quad<VEC>(col, q, nqf, p) : zero4();
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int k = 0; k < KQ; ++k) {
+                    const int q = t + T * k;
+                    const int qc = q < nqf ? q : nqf - 1;
+                    dst[b][k] = load_full<VEC>(col[b] + 4 * qc);
+                }
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int k = 0; k < KQ; ++k)
+                    if (t + T * k >= nqf) dst[b][k] = zero4();
+        } else {
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int k = 0; k < KQ; ++k) dst[b][k] = zero4();
+        }
+        if (has_tail && t == tail_t) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const f4 v = load_quad<false>(col[b], nqf, nqf, p);
+#pragma unroll
+                for (int k = 0; k < KQ; ++k)
+                    if (k == tail_k) dst[b][k] = v;
             }
         }
     };
@@ -244,11 +284,10 @@ __global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t cb = pp.n * wave / nw, ce = pp.n * (wave + 1) / nw;
-    const int p = pp.p, nqf = p >> 2, nq = (p + 3) >> 2;
+    const int p = pp.p, nqf = p >> 2;
     const int m = pp.m;
     const int mg = (m - j0 < M) ? m - j0 : M;  // real components in this launch
     const bool l0 = pp.l0 != 0;
-    const double gamma = pp.gamma;
 
     const int vidx = lane >> SHIFT;
     const int ob = vidx / M, oj = vidx % M;
@@ -272,17 +311,31 @@ __global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float
         float acc[V];
 #pragma unroll
         for (int i = 0; i < V; ++i) acc[i] = 0.f;
-        for (int q = lane; q < nq; q += 64) {
+        // full row quads: unconditional 16-byte loads (X is padded with zero
+        // components up to a multiple of M, so no component guard is needed)
+        for (int q = lane; q < nqf; q += 64) {
             f4 xv[M];
 #pragma unroll
             for (int j = 0; j < M; ++j)
-                xv[j] = (j < mg) ? *reinterpret_cast<const f4*>(Xg + (size_t)j * pp.ldx + 4 * q)
-                                 : zero4();
+                xv[j] = *reinterpret_cast<const f4*>(Xg + (size_t)j * pp.ldx + 4 * q);
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const f4 a = load_quad<VEC>(colp[b], q, nqf, p);
+                const f4 a = load_full<VEC>(colp[b] + 4 * q);
 #pragma unroll
                 for (int j = 0; j < M; ++j) acc[b * M + j] = dot4(a, xv[j], acc[b * M + j]);
+            }
+        }
+        // ragged tail rows 4*nqf .. p-1 (at most 3), one lane per row
+        if (lane < p - 4 * nqf) {
+            const int r = 4 * nqf + lane;
+            float xs[M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) xs[j] = Xg[(size_t)j * pp.ldx + r];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const float a = colp[b][r];
+#pragma unroll
+                for (int j = 0; j < M; ++j) acc[b * M + j] = __builtin_fmaf(a, xs[j], acc[b * M + j]);
             }
         }
         butterfly<32, V, V>(acc, lane);
@@ -293,7 +346,7 @@ __global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float
         if (valid) {
             float s;
             double fv;
-            active = threshold(l0, muj, gamma, y, s, fv);
+            active = threshold(l0, muj, pp.gam[j0 + oj], y, s, fv);
             S[col * m + j0 + oj] = s;
             if (active) {
                 f_acc += fv;
@@ -315,8 +368,8 @@ __global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float
         nnz_acc += __shfl_xor(nnz_acc, o, 64);
     }
     if (ob == 0 && rep && oj < mg) {
-        fpart[wave * m + j0 + oj] = f_acc;
-        nnzpart[wave * m + j0 + oj] = nnz_acc;
+        fpart[(int64_t)(j0 + oj) * nw + wave] = f_acc;
+        nnzpart[(int64_t)(j0 + oj) * nw + wave] = nnz_acc;
     }
 }
 

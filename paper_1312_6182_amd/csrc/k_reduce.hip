@@ -136,18 +136,26 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ l1, int
             s = g64[(size_t)j * p + r0 + rr];
         }
         gt[rr * mp + j] = s;
-        xt[rr * mp + j] = with_x ? (double)X[(size_t)j * ldx + r0 + rr] : 0.0;
+        xt[rr * mp + j] = (with_x == 1) ? (double)X[(size_t)j * ldx + r0 + rr] : 0.0;
     }
     __syncthreads();
     const int mm = m * m;
     double* out = gram + (size_t)blockIdx.x * 3 * mm;
+    if (with_x == 2) {  // independent columns (gamma path): only ||g_j||^2 is needed
+        for (int a = t; a < m; a += blockDim.x) {
+            double sgg = 0.0;
+            for (int rr = 0; rr < nr; ++rr) sgg += gt[rr * mp + a] * gt[rr * mp + a];
+            out[a * m + a] = sgg;
+        }
+        return;
+    }
     for (int e = t; e < mm; e += blockDim.x) {
         const int a = e / m, b = e % m;
         double sgg = 0.0, sgx = 0.0, sxx = 0.0;
         for (int rr = 0; rr < nr; ++rr) {
             const double ga = gt[rr * mp + a];
             sgg += ga * gt[rr * mp + b];
-            if (with_x) {
+            if (with_x == 1) {
                 sgx += ga * xt[rr * mp + b];
                 sxx += xt[rr * mp + a] * xt[rr * mp + b];
             }
@@ -173,7 +181,7 @@ hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float
 // (round-robin) ordering: each step applies msz/2 disjoint plane rotations.
 // a (msz x msz, leading dim LDM, LDS) is diagonalized in place; v receives the
 // eigenvectors (columns).  Executed by the whole workgroup.
-__device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs, double* red) {
+__device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs) {
     const int t = threadIdx.x, nt = blockDim.x;
     for (int e = t; e < msz * msz; e += nt) {
         const int i = e / msz, j = e % msz;
@@ -183,28 +191,12 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
     if (msz < 2) return;
     const int mm = msz + (msz & 1);
     const int half = mm / 2;
+    __shared__ int rotated;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        // convergence: off-diagonal mass against the diagonal mass
-        double off = 0.0, dg = 0.0;
-        for (int e = t; e < msz * msz; e += nt) {
-            const int i = e / msz, j = e % msz;
-            const double x = a[i * LDM + j];
-            if (i == j) dg += x * x;
-            else off += x * x;
-        }
-        red[t] = off;
-        red[nt + t] = dg;
+        // cyclic Jacobi stopping rule: a sweep that applies no rotation (every
+        // |a_pq| <= eps sqrt(|a_pp a_qq|)) ends the iteration
+        if (t == 0) rotated = 0;
         __syncthreads();
-        for (int s = nt / 2; s > 0; s >>= 1) {
-            if (t < s) {
-                red[t] += red[t + s];
-                red[nt + t] += red[nt + t + s];
-            }
-            __syncthreads();
-        }
-        const double offt = red[0], dgt = red[nt];
-        __syncthreads();
-        if (!(offt > 1e-32 * dgt)) break;
         for (int r = 0; r < mm - 1; ++r) {
             if (t < half) {
                 // round-robin schedule: position 0 fixed, the others rotate
@@ -215,7 +207,8 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                 if (qq < msz) {
                     const double apq = a[pp * LDM + qq];
                     const double app = a[pp * LDM + pp], aqq = a[qq * LDM + qq];
-                    if (apq != 0.0 && fabs(apq) > 1e-300) {
+                    if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+                        rotated = 1;
                         const double tau = (aqq - app) / (2.0 * apq);
                         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + tt * tt);
@@ -254,6 +247,9 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
             }
             __syncthreads();
         }
+        const int any_rot = rotated;
+        __syncthreads();
+        if (!any_rot) break;
     }
 }
 
@@ -325,7 +321,7 @@ __device__ void block_coefficients(int m, double* coef, StopShared& ss, double* 
         A0[i * LDM + j] = GtG[ss.live[i] * m + ss.live[j]];
     }
     __syncthreads();
-    jacobi_eig(A0, A1, nl, ss.rot, ss.prs, red);
+    jacobi_eig(A0, A1, nl, ss.rot, ss.prs);
     int rd1 = 0;
     inv_sqrt_from_eig(A0, A1, A2, nl, ss.lam, &ss.rankdef);
     rd1 = ss.rankdef;
@@ -368,7 +364,7 @@ __device__ void block_coefficients(int m, double* coef, StopShared& ss, double* 
             A0[i * LDM + j] = A1[i * LDM + j];
         }
         __syncthreads();
-        jacobi_eig(A0, A1, nd, ss.rot, ss.prs, red);
+        jacobi_eig(A0, A1, nd, ss.rot, ss.prs);
         inv_sqrt_from_eig(A0, A1, A2, nd, ss.lam, &ss.rankdef);
         // Omega[L,D] = -(W_L C) W_D ; Psi[D,D] = W_D
         double* tmp = A0;  // nl x nd product
@@ -417,9 +413,12 @@ __global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
     for (int j = 0; j < m; ++j) {
         double s = 0.0;
         int c = 0;
+        const double* fj = fpart + (size_t)j * nwp;
+        const int* cj = nnzpart + (size_t)j * nwp;
+#pragma unroll 8
         for (int w = t; w < nwp; w += nt) {
-            s += fpart[(size_t)w * m + j];
-            c += nnzpart[(size_t)w * m + j];
+            s += fj[w];
+            c += cj[w];
         }
         red[t] = s;
         redi[t] = c;
@@ -511,12 +510,163 @@ __global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
                        Ctrl* ctrl, hipStream_t st) {
-    const int threads = pl.m <= 16 ? 64 : 256;
+    const int threads = 256;
     const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
                        nnzpart, pl.gram_grid, gram, trace, coef, fcomp, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gamma path: m independent single-unit problems (column j has its own gamma).
+// Per column: objective trace, stopping rule, and the sphere retraction
+// x_j <- g_j / ||g_j||; a column whose rule fired is frozen (Psi_jj = 1), so
+// its x, and with it S, F and Z, stay those of its stopping pass.
+__global__ void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
+                            const int* __restrict__ nnzpart, int ngram,
+                            const double* __restrict__ gram, double* __restrict__ trace,
+                            double* __restrict__ coef, double* __restrict__ fcomp,
+                            PathState* __restrict__ ps, Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double red[256];
+    __shared__ int redi[256];
+    __shared__ double fj[kMaxM];
+    __shared__ int nj[kMaxM];
+    __shared__ int nfrozen;
+    const int t = threadIdx.x, nt = blockDim.x, mm = m * m;
+    const int k = ctrl->k;
+    const int max_iter = ctrl->max_iter;
+    const double tol = ctrl->tol;
+    for (int j = 0; j < m; ++j) {
+        double s = 0.0;
+        int c = 0;
+        const double* fp = fpart + (size_t)j * nwp;
+        const int* cp = nnzpart + (size_t)j * nwp;
+#pragma unroll 8
+        for (int w = t; w < nwp; w += nt) {
+            s += fp[w];
+            c += cp[w];
+        }
+        red[t] = s;
+        redi[t] = c;
+        __syncthreads();
+        for (int h = nt / 2; h > 0; h >>= 1) {
+            if (t < h) {
+                red[t] += red[t + h];
+                redi[t] += redi[t + h];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            fj[j] = red[0];
+            nj[j] = redi[0];
+        }
+        __syncthreads();
+    }
+    if (t == 0) nfrozen = 0;
+    for (int e = t; e < 2 * mm; e += nt) coef[e] = 0.0;
+    __syncthreads();
+    for (int j = t; j < m; j += nt) {
+        const double F = fj[j];
+        fcomp[j] = F;
+        reinterpret_cast<int64_t*>(fcomp + m)[j] = nj[j];
+        PathState st = ps[j];
+        if (!st.frozen) {
+            trace[(size_t)j * max_iter + k] = F;
+            int stop = 0, status = GPSPCA_OK;
+            if (!isfinite(F)) {
+                stop = 1;
+                status = GPSPCA_ENONFINITE;
+            } else if (F == 0.0) {
+                stop = 1;
+                st.degenerate = 1;
+            } else if (k >= 1 && fabs(F - st.last_F) < tol * fabs(st.last_F)) {
+                stop = 1;
+            } else if (k + 1 >= max_iter) {
+                stop = 1;
+                status = GPSPCA_MAXITER;
+            }
+            if (stop) {
+                st.frozen = 1;
+                st.n_iter = k + 1;
+                st.status = (status >= 0 && st.degenerate) ? GPSPCA_DEGENERATE : status;
+            }
+            st.last_F = F;
+            ps[j] = st;
+        }
+        double g2 = 0.0;
+        for (int g = 0; g < ngram; ++g) g2 += gram[(size_t)g * 3 * mm + (size_t)j * m + j];
+        if (st.frozen) {
+            coef[mm + j * m + j] = 1.0;
+            atomicAdd(&nfrozen, 1);
+        } else {
+            coef[j * m + j] = 1.0 / sqrt(g2);
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        if (nfrozen == m) {
+            ctrl->done = 1;
+            ctrl->n_iter = k + 1;
+        } else {
+            ctrl->ndead = nfrozen > 0 ? 1 : 0;
+            ctrl->k = k + 1;
+        }
+        ctrl->last_F = 0.0;
+    }
+}
+
+hipError_t launch_stop_path(const Plan& pl, const double* fpart, const int* nnzpart,
+                            const double* gram, double* trace, double* coef, double* fcomp,
+                            PathState* ps, Ctrl* ctrl, hipStream_t st) {
+    hipLaunchKernelGGL(k_stop_path, dim3(1), dim3(256), 0, st, pl.m, pl.nwave_part, fpart,
+                       nnzpart, pl.gram_grid, gram, trace, coef, fcomp, ps, ctrl);
+    return hipGetLastError();
+}
+
+// X[:, j] <- X[:, 0] for 1 <= j < m (rows < p)
+__global__ void k_bcast_col0(int m, int p, int ldx, float* __restrict__ X) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)(m - 1) * p) return;
+    const int j = 1 + (int)(e / p), r = (int)(e % p);
+    X[(size_t)j * ldx + r] = X[r];
+}
+
+hipError_t launch_bcast_col0(const Plan& pl, float* X, hipStream_t st) {
+    if (pl.m < 2) return hipSuccess;
+    const int64_t ne = (int64_t)(pl.m - 1) * pl.p;
+    hipLaunchKernelGGL(k_bcast_col0, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pl.m,
+                       (int)pl.p, pl.ldx, X);
+    return hipGetLastError();
+}
+
+// Column-wise normalization of a starting point (gamma path): Omega =
+// diag(1/||x_j||); a zero column fails with GPSPCA_EINVAL.
+__global__ void k_project_diag(int m, int ngram, const double* __restrict__ gram,
+                               double* __restrict__ coef, Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int t = threadIdx.x, mm = m * m;
+    for (int e = t; e < 2 * mm; e += blockDim.x) coef[e] = 0.0;
+    __syncthreads();
+    for (int j = t; j < m; j += blockDim.x) {
+        double g2 = 0.0;
+        for (int g = 0; g < ngram; ++g) g2 += gram[(size_t)g * 3 * mm + (size_t)j * m + j];
+        const double om = 1.0 / sqrt(g2);
+        coef[j * m + j] = om;
+        if (!(g2 > 0.0) || !isfinite(om)) {
+            ctrl->status = GPSPCA_EINVAL;
+            ctrl->done = 1;
+        }
+    }
+    if (t == 0) ctrl->ndead = 0;
+}
+
+hipError_t launch_project_diag(const Plan& pl, const double* gram, double* coef, Ctrl* ctrl,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_project_diag, dim3(1), dim3(256), 0, st, pl.m, pl.gram_grid, gram, coef,
+                       ctrl);
     return hipGetLastError();
 }
 
@@ -550,7 +700,7 @@ __global__ void k_project(int m, int ngram, const double* __restrict__ gram,
         A0[i * LDM + j] = coef[2 * mm + e];
     }
     __syncthreads();
-    jacobi_eig(A0, A1, m, ss.rot, ss.prs, red);
+    jacobi_eig(A0, A1, m, ss.rot, ss.prs);
     inv_sqrt_from_eig(A0, A1, A2, m, ss.lam, &ss.rankdef);
     for (int e = t; e < mm; e += nt) {
         const int i = e / m, j = e % m;

@@ -34,6 +34,15 @@ CASES = [
     (O.BL1, 13, 301, 2000, 0, 12),
     (O.BL0, 20, 300, 1500, 2, 13),
     (O.BL1, 64, 200, 900, 0, 14),
+    # matrix-core correlation path (lda % 4 == 0): ragged tails, 1/2/4
+    # component blocks of 16, m = 1 with p > 20480, n smaller than one tile
+    (O.BL1, 8, 2051, 3333, 1, 15),
+    (O.BL0, 8, 2048, 3000, 0, 16),
+    (O.BL0, 20, 300, 1500, 0, 17),
+    (O.BL1, 33, 257, 1000, 3, 18),
+    (O.SL1, 1, 20996, 600, 0, 19),
+    (O.BL0, 5, 1002, 37, 2, 20),
+    (O.BL1, 2, 3, 500, 1, 21),
 ]
 
 
