@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -122,11 +123,33 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         pl->npart = pl->m1_grid;
         pl->nwave_part = pl->m1_grid;
     } else {
-        pl->use_mfma = pl->vec4;
-        if (pl->use_mfma) {
-            // one wavefront per workgroup, four per CU (LDS-bound)
+        // correlation kernel: register-resident X for m <= 4, matrix cores otherwise
+        // (GPSPCA_CORR_KERNEL=vx|mv|mfma|valu forces one, for tests and benchmarks)
+        const char* force = std::getenv("GPSPCA_CORR_KERNEL");
+        const std::string fk = force ? force : "";
+        const bool vx_ok = pl->vec4 && m >= 2 && m <= 8 && A->p <= 10240 && A->p >= 4 && !path;
+        const bool mv_ok = pl->vec4 && m <= 16 && A->p >= 4;
+        if (fk == "vx" && vx_ok) pl->use_vx = 1;
+        else if (fk == "mv" && mv_ok) pl->use_mv = 1;
+        else if (fk == "mfma" && pl->vec4) pl->use_mfma = 1;
+        else if (fk == "valu") {}
+        else if (vx_ok && m <= 4) pl->use_vx = 1;
+        else pl->use_mfma = pl->vec4;
+        if (pl->use_vx) {
+            // X rows in registers: one workgroup per CU (512 threads) or two (256)
+            pl->corr_M = m <= 2 ? 2 : m <= 4 ? 4 : 8;
+            pl->vx_threads = (cdiv(nq, 256) <= 5) ? 256 : 512;
+            pl->vx_kq = (int)std::max<int64_t>(1, cdiv(nq, pl->vx_threads));
+            const int per_cu = pl->vx_threads == 256 ? 2 : 1;
+            int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, std::max<int64_t>(1, A->n / 4));
+            pl->corr_grid = (int)std::max<int64_t>(1, grid);
+            pl->nwave_part = pl->corr_grid;
+        } else if (pl->use_mfma || pl->use_mv) {
+            // one wavefront per workgroup; as many per CU as the LDS stages allow
             pl->corr_M = 16;
-            int64_t grid = std::min<int64_t>((int64_t)ncu * 4, cdiv(A->n, 16));
+            pl->mfma_stages = corr_mfma_stages(m);
+            const int per_cu = pl->use_mv ? 4 : corr_mfma_blocks_per_cu(m, pl->mfma_stages);
+            int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, cdiv(A->n, 16));
             pl->corr_grid = (int)std::max<int64_t>(1, grid);
             pl->nwave_part = pl->corr_grid;
         } else {
@@ -150,6 +173,10 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->red_split = (int)std::max<int64_t>(1, split);
     pl->gram_rows = ((size_t)(m + 1) * 256 * 16 <= 140000) ? 256 : 128;
     pl->gram_grid = (int)cdiv(A->p, pl->gram_rows);
+    // the fused m = 1 pass leaves one partial per workgroup (hundreds): those
+    // are summed faster by the split reduction
+    pl->fused_gram = (m <= 16 && !pl->fused_m1) ? 1 : 0;
+    pl->gram_blocks = pl->fused_gram ? (int)cdiv(A->p, 64) : pl->gram_grid;
     pl->fin_grid = (int)std::max<int64_t>(1, cdiv(cdiv(A->n, 32), 256));
     pl->topm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(A->n, 1024)));
 
@@ -172,8 +199,8 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->o_nnzpart = take(sizeof(int) * (size_t)pl->nwave_part * M);
     pl->o_l1 = take(sizeof(double) * (size_t)pl->red_split * M * L);
     pl->o_g64 = take(sizeof(double) * M * P);
-    pl->o_gram = take(sizeof(double) * (size_t)pl->gram_grid * 3 * M * M);
-    pl->o_coef = take(sizeof(double) * 5 * M * M);
+    pl->o_gram = take(sizeof(double) * (size_t)std::max(pl->gram_grid, pl->gram_blocks) * 3 * M * M);
+    pl->o_coef = take(sizeof(double) * 6 * M * M);  // Omega, Psi, G^T G, G^T X, X^T X, V
     pl->o_norms = take(sizeof(double) * N);
     pl->o_cand_v = take(sizeof(double) * (size_t)pl->topm_grid * M);
     pl->o_cand_i = take(sizeof(int64_t) * (size_t)pl->topm_grid * M);
@@ -312,29 +339,36 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
                         hipStream_t st, TimedLaunches& tl) {
     const float* Xk = P.x[k & 1];
     float* Xn = P.x[(k + 1) & 1];
+    const int* touched = pl.fused_m1 ? nullptr : P.touched;
     GPSPCA_HIP(tl.begin(st));
     if (pl.fused_m1) {
         GPSPCA_HIP(launch_pass_m1(pl, pp, Xk, P.S, P.gpart, P.fpart, P.nnzpart, P.ctrl, st));
         GPSPCA_HIP(tl.end(st));
-        GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, nullptr, P.l1, P.ctrl, st));
     } else {
-        if (pl.use_mfma)
+        if (pl.use_vx)
+            GPSPCA_HIP(launch_corr_vx(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+        else if (pl.use_mv)
+            GPSPCA_HIP(launch_corr_mv(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+        else if (pl.use_mfma)
             GPSPCA_HIP(launch_corr_mfma(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         else
             GPSPCA_HIP(launch_corr(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         GPSPCA_HIP(tl.end(st));
         GPSPCA_HIP(launch_backproj(pl, pp, P.S, P.act, P.gpart, P.touched, P.ctrl, st));
-        GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, P.touched, P.l1, P.ctrl, st));
+    }
+    const int with_x = pl.path ? 2 : (pl.m > 1 ? 1 : 0);
+    if (pl.fused_gram) {
+        GPSPCA_HIP(launch_reduce_gram(pl, P.gpart, touched, Xk, with_x, P.g64, P.gram, P.ctrl, st));
+    } else {
+        GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, touched, P.l1, P.ctrl, st));
+        GPSPCA_HIP(launch_gram(pl, P.l1, pl.red_split, Xk, with_x, P.g64, P.gram, P.ctrl, st));
     }
     if (pl.path) {
-        GPSPCA_HIP(launch_gram(pl, P.l1, pl.red_split, Xk, 2, P.g64, P.gram, P.ctrl, st));
         GPSPCA_HIP(launch_stop_path(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp,
                                     P.pstate, P.ctrl, st));
     } else {
-        GPSPCA_HIP(launch_gram(pl, P.l1, pl.red_split, Xk, pl.m > 1 ? 1 : 0, P.g64, P.gram,
-                               P.ctrl, st));
-        GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp, P.ctrl,
-                               st));
+        GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp,
+                               P.coef + 5 * (size_t)pl.m * pl.m, P.ctrl, st));
     }
     GPSPCA_HIP(launch_apply(pl, P.g64, Xk, P.coef, Xn, P.ctrl, st));
     return GPSPCA_OK;
@@ -389,7 +423,10 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
     }
     GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     GPSPCA_HIP(hipStreamSynchronize(st));
-    tl.collect(pl.fused_m1 ? "k_pass_m1" : pl.use_mfma ? "k_corr_mfma" : "k_corr");
+    tl.collect(pl.fused_m1 ? "k_pass_m1"
+                           : pl.use_vx ? "k_corr_vx"
+                           : pl.use_mv ? "k_corr_mv"
+                           : pl.use_mfma ? "k_corr_mfma" : "k_corr");
     *fin = *snap;
     return GPSPCA_OK;
 }

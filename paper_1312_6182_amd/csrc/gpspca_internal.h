@@ -22,7 +22,7 @@ struct Ctrl {
     int ndead;             // dead components at the last retraction
     int degenerate_seen;   // some retraction completed dead components / F = 0
     int max_iter;
-    int pad0;
+    int warm;              // the previous retraction's eigenvectors may seed the next
     double tol;
     double last_F;
 };
@@ -61,10 +61,16 @@ struct Plan {
     int nwave_part;        // objective partial slots per component (fpart[j * nwave_part + w])
     int red_split;         // split of the partial reduction
     int gram_rows, gram_grid;
+    int fused_gram;        // m <= 16: partial reduction and Gram in one kernel (64-row blocks)
+    int gram_blocks;       // number of Gram partials of a pass
     int fin_grid;
     int topm_grid;
     int vec4;              // float4 loads of A are legal
     int use_mfma;          // block correlation on the matrix cores (LDS DMA staging)
+    int mfma_stages;       // stages in flight of the matrix-core kernel
+    int use_vx;            // block correlation with X held in registers (m <= 8, p <= 10240)
+    int vx_threads, vx_kq;
+    int use_mv;            // block correlation on the matrix cores, A staged through registers
     int path;              // gamma path: independent single-unit columns (normalize, per-column stop)
     // workspace offsets (bytes)
     size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
@@ -81,6 +87,14 @@ hipError_t launch_pass_m1(const Plan& pl, const PassParams& pp, const float* x, 
 hipError_t launch_corr(const Plan& pl, const PassParams& pp, const float* X, float* S,
                        uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                        hipStream_t st);
+hipError_t launch_corr_vx(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                          uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st);
+int corr_mfma_stages(int m);
+int corr_mfma_blocks_per_cu(int m, int stages);
+hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                          uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st);
 hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, float* S,
                             uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                             hipStream_t st);
@@ -99,7 +113,12 @@ hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float
                        hipStream_t st);
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
-                       Ctrl* ctrl, hipStream_t st);
+                       double* vprev, Ctrl* ctrl, hipStream_t st);
+hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* touched,
+                              const float* X, int with_x, double* g64, double* gram,
+                              const Ctrl* ctrl, hipStream_t st);
+hipError_t launch_gram_sum(const Plan& pl, int nent, int ngram, const double* gram, double* coef,
+                           const Ctrl* ctrl, hipStream_t st);
 // gamma path: per-column objective, trace, stopping and normalization
 struct PathState {
     int frozen;            // 1 once this column's stopping rule fired

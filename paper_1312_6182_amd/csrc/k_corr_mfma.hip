@@ -7,10 +7,10 @@
 // Work decomposition (one wavefront per workgroup, no barriers):
 //   - each wave owns a contiguous range of n/W columns (+-1) and walks it in
 //     chunks of T = 4 tiles of 16 columns (64 columns);
-//   - the rows of a chunk are streamed in stages of 32 rows: 9 DMA
-//     instructions bring the 64 x 32 A tile into LDS (column-major with one
-//     16-byte pad slot per column, so that the MFMA operand reads are free of
-//     bank conflicts), 2 per component block bring the matching X rows;
+//   - the rows of a chunk are streamed in stages of 32 rows: 8 DMA
+//     instructions bring the 64 x 32 A tile into LDS (column-major, quads
+//     XOR-swizzled per column so that the MFMA operand reads are free of bank
+//     conflicts), 2 per component block bring the matching X rows;
 //     STAGES stages are in flight while the oldest is consumed;
 //   - each stage feeds v_mfma_f32_16x16x4_f32 with M = 16 columns, N = 16
 //     components, K = 4 rows: lane l supplies A[row 4(l/16)+t][col l%16] and
@@ -21,6 +21,9 @@
 // the compiler cannot count LDS DMA completions across the loop back-edge.
 #include "gpspca_internal.h"
 
+#include <algorithm>
+#include <cstdlib>
+
 namespace gpspca {
 
 typedef float f4m __attribute__((ext_vector_type(4)));
@@ -29,8 +32,14 @@ namespace {
 
 constexpr int kT = 4;          // column tiles of 16 per chunk
 constexpr int kQS = 8;         // row quads per stage (32 rows)
-constexpr int kSlot = kQS + 1; // padded 16-byte slots per column in LDS
-constexpr int kAStageBytes = 16 * kT * kSlot * 16;  // 9216
+constexpr int kAStageBytes = 16 * kT * kQS * 16;  // 8192: 64 columns x 8 quads x 16 B
+
+// LDS slot of (column c, quad q) within an A stage: quads are XOR-swizzled by
+// bits 1..3 of the column, so that the 16 columns read together by an MFMA
+// operand load fall on 16 distinct groups of 4 banks.
+__device__ __forceinline__ uint32_t a_slot(int c, int q) {
+    return (uint32_t)(16 * (c * kQS + (q ^ ((c >> 1) & 7))));
+}
 
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
@@ -86,7 +95,7 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
     if (ctrl->done) return;
     constexpr int XStageBytes = J * 2 * 1024;
     constexpr int StageBytes = kAStageBytes + XStageBytes;
-    constexpr int PER = 9 + 2 * J;  // DMA instructions per stage
+    constexpr int PER = 8 + 2 * J;  // DMA instructions per stage
     __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
 
@@ -119,15 +128,15 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
     const int xzero = ldx - 4;  // a quad of zero rows (ldx >= p + 4)
 
     for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kT) {
-        // A DMA source columns: slot L = 64 i + lane -> column L / 9, quad slot L % 9
-        const float* acol[kSlot];
-        int aq[kSlot];
+        // A DMA sources: slot L = 64 i + lane holds column L / 8 and the quad whose
+        // swizzled position is L % 8
+        const float* acol[kQS];
+        int aq[kQS];
 #pragma unroll
-        for (int i = 0; i < kSlot; ++i) {
+        for (int i = 0; i < kQS; ++i) {
             const int L = 64 * i + lane;
-            const int cl = L / kSlot;
-            int q = L % kSlot;
-            q = (q == kQS) ? kQS - 1 : q;  // pad slot: duplicate a real quad
+            const int cl = L / kQS;
+            const int q = (L % kQS) ^ ((cl >> 1) & 7);
             int64_t col = c0 + cl;
             col = (col < cend) ? col : cend - 1;
             acol[i] = pp.A + col * pp.lda;
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
             const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
             const int q0 = kQS * st;
 #pragma unroll
-            for (int i = 0; i < kSlot; ++i) {
+            for (int i = 0; i < kQS; ++i) {
                 int q = q0 + aq[i];
                 q = (q < nqf) ? q : nqf - 1;
                 dma16(acol[i] + 4 * q, sb + 1024 * i);
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
                 f4m av[kT], xv[J];
 #pragma unroll
                 for (int t = 0; t < kT; ++t)
-                    av[t] = lds_read16(sb + 16u * (uint32_t)((16 * t + lj) * kSlot + 4 * h + lk));
+                    av[t] = lds_read16(sb + a_slot(16 * t + lj, 4 * h + lk));
 #pragma unroll
                 for (int jb = 0; jb < J; ++jb)
                     xv[jb] = lds_read16(sb + kAStageBytes + 2048u * jb +
@@ -268,11 +277,199 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// k_corr_mv: the same matrix-core correlation for m <= 16, but A is staged
+// through registers instead of LDS DMA: one wave per SIMD can hold three
+// 16 KB stages in flight (A streamed as contiguous 512-byte column segments,
+// one per half-wave), and LDS only transposes the stage being consumed into
+// MFMA operand order.  All loads are ordinary vector loads, so the compiler
+// inserts every wait itself.
+//   chunk = 32 columns (2 MFMA tiles); stage = 128 rows (32 quads);
+//   LDS slot of (column i, quad q): i*512 + 16*(q ^ (i & 31)) (conflict-free
+//   for both the half-wave row writes and the 16-column operand reads).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kMvQ = 32;   // quads per stage
+constexpr int kMvC = 32;   // columns per chunk
+
+__device__ __forceinline__ uint32_t mv_slot(int i, int q) {
+    return (uint32_t)(i * 512 + 16 * (q ^ (i & 31)));
+}
+}  // namespace
+
+__global__ __launch_bounds__(64) void k_corr_mv(PassParams pp, const float* __restrict__ X,
+                                                float* __restrict__ S, uint8_t* __restrict__ act,
+                                                double* __restrict__ fpart,
+                                                int* __restrict__ nnzpart,
+                                                const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ __attribute__((aligned(16))) f4m tr[kMvC * kMvQ];  // 16 KB transpose buffer
+    const int lane = threadIdx.x;
+    const int p = pp.p, m = pp.m, ldx = pp.ldx;
+    const int nqf = p >> 2;
+    const int rem = p & 3;
+    const int nst = (nqf + kMvQ - 1) / kMvQ;
+    const bool l0 = pp.l0 != 0;
+    const int64_t n = pp.n;
+    const int64_t W = gridDim.x, w = blockIdx.x;
+    const int64_t cbeg = n * w / W;
+    const int64_t cend = n * (w + 1) / W;
+    const int lj = lane & 15, lk = lane >> 4;
+    const int half = lane >> 5, lq = lane & 31;
+    const float* xcol = X + (size_t)lj * ldx;
+    const int xzero = ldx - 4;
+    double f_acc = 0.0;
+    int nnz_acc = 0;
+    char* trb = reinterpret_cast<char*>(tr);
+
+    for (int64_t c0 = cbeg; c0 < cend; c0 += kMvC) {
+        const float* colp[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            int64_t col = c0 + 2 * c + half;
+            col = (col < cend) ? col : cend - 1;
+            colp[c] = pp.A + col * pp.lda;
+        }
+        auto load = [&](int st, f4m(&Ab)[16], f4m(&Xb)[8]) {
+            int q = kMvQ * st + lq;
+            q = (q < nqf) ? q : nqf - 1;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                Ab[c] = __builtin_nontemporal_load(reinterpret_cast<const f4m*>(colp[c] + 4 * q));
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const int qx = kMvQ * st + 4 * g + lk;
+                Xb[g] = *reinterpret_cast<const f4m*>(xcol + ((qx < nqf) ? 4 * qx : xzero));
+            }
+        };
+        f4m acc[2];
+        acc[0] = f4m{0.f, 0.f, 0.f, 0.f};
+        acc[1] = f4m{0.f, 0.f, 0.f, 0.f};
+        auto process = [&](const f4m(&Ab)[16], const f4m(&Xb)[8]) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int i = 2 * c + half;
+                *reinterpret_cast<f4m*>(trb + mv_slot(i, lq)) = Ab[c];
+            }
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const f4m a0 = *reinterpret_cast<const f4m*>(trb + mv_slot(lj, 4 * g + lk));
+                const f4m a1 = *reinterpret_cast<const f4m*>(trb + mv_slot(16 + lj, 4 * g + lk));
+#pragma unroll
+                for (int tm = 0; tm < 4; ++tm) {
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[tm], Xb[g][tm], acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[tm], Xb[g][tm], acc[1], 0, 0, 0);
+                }
+            }
+        };
+        // Three register stages in flight.  Loads and stages are unconditional so
+        // that the compiler can count the outstanding loads exactly (a stage past
+        // the last one loads clamped, already-cached addresses and pairs them with
+        // the zero quad of X, so it adds exactly 0).
+        f4m A0[16], A1[16], A2[16], X0[8], X1[8], X2[8];
+        if (nst > 0) {
+            load(0, A0, X0);
+            load(1, A1, X1);
+            for (int st = 0; st < nst; st += 3) {
+                load(st + 2, A2, X2);
+                process(A0, X0);
+                load(st + 3, A0, X0);
+                process(A1, X1);
+                load(st + 4, A1, X1);
+                process(A2, X2);
+            }
+        }
+
+        // ragged tail rows 4*nqf .. p-1
+        if (rem) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int64_t col = c0 + 16 * t + 4 * lk + v;
+                    col = (col < cend) ? col : cend - 1;
+                    const float* ac = pp.A + col * pp.lda;
+                    for (int r = 4 * nqf; r < p; ++r)
+                        acc[t][v] = __builtin_fmaf(ac[r], xcol[r], acc[t][v]);
+                }
+        }
+        // threshold, S, activity flags (lane: component lj, columns 16t + 4lk + v)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t col = c0 + 16 * t + 4 * lk + v;
+                const bool valid = col < cend && lj < m;
+                bool a = false;
+                if (valid) {
+                    float sv;
+                    double fv;
+                    a = threshold_m(l0, pp.mu[lj], pp.gam[lj], acc[t][v], sv, fv);
+                    S[col * m + lj] = sv;
+                    if (a) {
+                        f_acc += fv;
+                        nnz_acc += 1;
+                    }
+                }
+                const uint64_t bal = __ballot(a);
+                if (col < cend && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+            }
+    }
+    f_acc += __shfl_xor(f_acc, 16, 64);
+    nnz_acc += __shfl_xor(nnz_acc, 16, 64);
+    f_acc += __shfl_xor(f_acc, 32, 64);
+    nnz_acc += __shfl_xor(nnz_acc, 32, 64);
+    if (lane < 16 && lj < m) {
+        fpart[(int64_t)lj * W + w] = f_acc;
+        nnzpart[(int64_t)lj * W + w] = nnz_acc;
+    }
+}
+
+hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                          uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_corr_mv, dim3(pl.corr_grid), dim3(64), 0, st, pp, X, S, act, fpart,
+                       nnzpart, ctrl);
+    return hipGetLastError();
+}
+
+// Stages in flight of the matrix-core kernel for m <= 16: 3 (30 KB of LDS per
+// wave) or 4 (40 KB, four waves fill the 160 KB of a CU).
+int corr_mfma_stages(int m) {
+    if (m > 16) return m <= 32 ? 3 : 2;
+    const char* e = std::getenv("GPSPCA_MFMA_STAGES");
+    if (e && std::atoi(e) == 3) return 3;
+    if (e && std::atoi(e) == 4) return 4;
+    return 4;
+}
+
+// Waves per CU of the matrix-core kernels: what LDS allows, at most 4 (one per
+// SIMD; a fifth wave per CU lowers the DMA streaming rate).
+int corr_mfma_blocks_per_cu(int m, int stages) {
+    int nb = 0;
+    hipError_t e;
+    if (m <= 16 && stages == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 4>, 64, 0);
+    else if (m <= 16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 3>, 64, 0);
+    else if (m <= 32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<2, 3>, 64, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<4, 2>, 64, 0);
+    (void)hipGetLastError();
+    int cap = 4;
+    if (const char* s = std::getenv("GPSPCA_MFMA_WAVES_PER_CU")) cap = std::max(1, std::atoi(s));
+    if (e != hipSuccess || nb <= 0) nb = 1;
+    return std::min(nb, cap);
+}
+
 hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, float* S,
                             uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                             hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(64);
-    if (pl.m <= 16)
+    if (pl.m <= 16 && pl.mfma_stages == 4)
+        hipLaunchKernelGGL((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
+    else if (pl.m <= 16)
         hipLaunchKernelGGL((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 32)
         hipLaunchKernelGGL((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);

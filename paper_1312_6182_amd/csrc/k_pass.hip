@@ -373,6 +373,122 @@ __global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// k_corr_vx: correlation + threshold for m <= 8 with X held in registers.
+//   T threads; thread t owns row quads t + T*k (k < KQ) and keeps X on those
+//   rows (KQ x M float4) for the whole pass.  The workgroup walks its
+//   contiguous column range one column at a time: every wave-load is 1 KB of
+//   one column (contiguous, like a flat stream), the next column is loaded
+//   before the current one is reduced, the M partial dots are reduced by a
+//   transposed butterfly (lane groups of 64/M keep one component) and across
+//   the waves through LDS (one barrier per column), and thread j < M applies
+//   the threshold of component j.
+// ---------------------------------------------------------------------------
+template <int T, int KQ, int M, bool VEC>
+__global__ __launch_bounds__(T) void k_corr_vx(PassParams pp, const float* __restrict__ X,
+                                               float* __restrict__ S, uint8_t* __restrict__ act,
+                                               double* __restrict__ fpart,
+                                               int* __restrict__ nnzpart,
+                                               const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int NWV = T / 64;
+    constexpr int SHIFT = 6 - ilog2c(M);  // lanes per component after the butterfly
+    __shared__ float red[2][NWV][M];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int p = pp.p, nqf = p >> 2, m = pp.m, ldx = pp.ldx;
+    const int64_t cb = pp.n * (int64_t)blockIdx.x / gridDim.x;
+    const int64_t ce = pp.n * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    const bool l0 = pp.l0 != 0;
+    const int tail_t = nqf % T, tail_k = nqf / T;
+    const bool has_tail = (p & 3) != 0;
+
+    f4 xr[KQ][M];
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+        const int q = t + T * k;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            xr[k][j] = (4 * q < ldx) ? *reinterpret_cast<const f4*>(X + (size_t)j * ldx + 4 * q)
+                                     : zero4();
+    }
+    // component handled by this thread in the threshold step (t < M)
+    const int mj = t < M ? t : 0;
+    const double muj = pp.mu[mj], gamj = pp.gam[mj];
+    double f_acc = 0.0;
+    int nnz_acc = 0;
+
+    auto load_col = [&](int64_t c, f4(&dst)[KQ]) {
+        const float* col = pp.A + c * pp.lda;
+        if (nqf > 0) {
+#pragma unroll
+            for (int k = 0; k < KQ; ++k) {
+                const int q = t + T * k;
+                const int qc = q < nqf ? q : nqf - 1;
+                dst[k] = load_full<VEC>(col + 4 * qc);
+            }
+#pragma unroll
+            for (int k = 0; k < KQ; ++k)
+                if (t + T * k >= nqf) dst[k] = zero4();
+        } else {
+#pragma unroll
+            for (int k = 0; k < KQ; ++k) dst[k] = zero4();
+        }
+        if (has_tail && t == tail_t) {
+            const f4 v = load_quad<false>(col, nqf, nqf, p);
+#pragma unroll
+            for (int k = 0; k < KQ; ++k)
+                if (k == tail_k) dst[k] = v;
+        }
+    };
+
+    f4 a[KQ];
+    if (cb < ce) load_col(cb, a);
+    int it = 0;
+    for (int64_t c = cb; c < ce; ++c, ++it) {
+        float d[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < KQ; ++k) acc = dot4(a[k], xr[k][j], acc);
+            d[j] = acc;
+        }
+        f4 an[KQ];
+        const bool more = c + 1 < ce;
+        if (more) load_col(c + 1, an);
+        butterfly<32, M, M>(d, lane);
+        if ((lane & ((1 << SHIFT) - 1)) == 0) red[it & 1][wv][lane >> SHIFT] = d[0];
+        __syncthreads();
+        bool active = false;
+        if (t < M) {
+            float y = 0.f;
+#pragma unroll
+            for (int w = 0; w < NWV; ++w) y += red[it & 1][w][t];
+            if (t < m) {
+                float sv;
+                double fv;
+                active = threshold(l0, muj, gamj, y, sv, fv);
+                S[c * m + t] = sv;
+                if (active) {
+                    f_acc += fv;
+                    nnz_acc += 1;
+                }
+            }
+        }
+        const uint64_t bal = __ballot(active);
+        if (t == 0) act[c] = (bal & ((1ull << M) - 1ull)) ? 1 : 0;
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < KQ; ++k) a[k] = an[k];
+        }
+    }
+    if (t < m) {
+        fpart[(int64_t)t * gridDim.x + blockIdx.x] = f_acc;
+        nnzpart[(int64_t)t * gridDim.x + blockIdx.x] = nnz_acc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_backproj: G partial of column range cr over its active columns.
 //   grid (row blocks, column ranges); 256 threads, thread t owns quads
@@ -579,6 +695,49 @@ hipError_t launch_corr(const Plan& pl, const PassParams& pp, const float* X, flo
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+
+template <int T, int KQ, int M>
+static hipError_t launch_vx_t(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                              uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_corr_vx<T, KQ, M, true>), dim3(pl.corr_grid), dim3(T), 0, st, pp, X, S,
+                       act, fpart, nnzpart, ctrl);
+    return hipGetLastError();
+}
+
+template <int T, int M>
+static hipError_t launch_vx_kq(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                               uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                               hipStream_t st) {
+    switch (pl.vx_kq) {
+        case 1: return launch_vx_t<T, 1, M>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+        case 2: return launch_vx_t<T, 2, M>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+        case 3: return launch_vx_t<T, 3, M>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+        case 4: return launch_vx_t<T, 4, M>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+        case 5: return launch_vx_t<T, 5, M>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int M>
+static hipError_t launch_vx_m(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                              uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                              hipStream_t st) {
+    return pl.vx_threads == 256 ? launch_vx_kq<256, M>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st)
+                                : launch_vx_kq<512, M>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+}
+
+hipError_t launch_corr_vx(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                          uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st) {
+    switch (pl.corr_M) {
+        case 2: return launch_vx_m<2>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+        case 4: return launch_vx_m<4>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+        case 8: return launch_vx_m<8>(pl, pp, X, S, act, fpart, nnzpart, ctrl, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int M, bool VEC>

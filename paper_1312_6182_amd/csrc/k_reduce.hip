@@ -55,7 +55,7 @@ __global__ void k_ctrl_reset(Ctrl* ctrl, int max_iter, double tol) {
         ctrl->ndead = 0;
         ctrl->degenerate_seen = 0;
         ctrl->max_iter = max_iter;
-        ctrl->pad0 = 0;
+        ctrl->warm = 0;
         ctrl->tol = tol;
         ctrl->last_F = 0.0;
     }
@@ -176,16 +176,147 @@ hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float
     return hipGetLastError();
 }
 
+// Final fixed-order reduction of the per-row-block Gram partials into the
+// coefficient scratch: coef[2mm + e] = sum_g gram[g][e] for e < nent.
+__global__ __launch_bounds__(256) void k_gram_sum(int nent, int mm, int ngram,
+                                                  const double* __restrict__ gram,
+                                                  double* __restrict__ coef,
+                                                  const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= nent) return;
+    double s = 0.0;
+    const double* gp = gram + e;
+#pragma unroll 8
+    for (int g = 0; g < ngram; ++g) s += gp[(size_t)g * 3 * mm];
+    coef[2 * mm + e] = s;
+}
+
+hipError_t launch_gram_sum(const Plan& pl, int nent, int ngram, const double* gram, double* coef,
+                           const Ctrl* ctrl, hipStream_t st) {
+    const int mm = pl.m * pl.m;
+    hipLaunchKernelGGL(k_gram_sum, dim3((nent + 255) / 256), dim3(256), 0, st, nent, mm, ngram,
+                       gram, coef, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused partial reduction + Gram for m <= 16: one workgroup per 64 rows.
+// Thread (row rr, slice sl) sums the partials c = sl, sl+4, ... of its row for
+// every component, the four slices are added in order 0..3 (fixed order), the
+// row of G is written in FP64, and the block's contributions to G^T G, G^T X,
+// X^T X (or only the diagonal of G^T G, with_x == 2) go to gram[block].
+template <int MB>
+__global__ __launch_bounds__(256) void k_reduce_gram(const float* __restrict__ gpart,
+                                                     const int* __restrict__ touched, int npart,
+                                                     int m, int ldx, int p,
+                                                     const float* __restrict__ X, int with_x,
+                                                     double* __restrict__ g64,
+                                                     double* __restrict__ gram,
+                                                     const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int MP = MB + 1;
+    __shared__ double part[4][64][MP];
+    __shared__ double gt[64][MP];
+    __shared__ double xt[64][MP];
+    const int t = threadIdx.x, rr = t & 63, sl = t >> 6;
+    const int r0 = blockIdx.x * 64;
+    const int r = r0 + rr;
+    const int nr = (p - r0 < 64) ? p - r0 : 64;
+    const size_t stride = (size_t)m * ldx;
+    double g[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) g[j] = 0.0;
+    if (r < p) {
+        int c = sl;
+        if (!touched) {
+            for (; c + 12 < npart; c += 16) {
+                float v[4][MB];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int j = 0; j < MB; ++j)
+                        v[u][j] = (j < m) ? gpart[(size_t)(c + 4 * u) * stride + (size_t)j * ldx + r] : 0.f;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int j = 0; j < MB; ++j) g[j] += (double)v[u][j];
+            }
+        }
+        for (; c < npart; c += 4) {
+            if (touched && !touched[c]) continue;
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < m) g[j] += (double)gpart[(size_t)c * stride + (size_t)j * ldx + r];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MB; ++j) part[sl][rr][j] = g[j];
+    __syncthreads();
+    if (sl == 0) {
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+            const double v = ((part[0][rr][j] + part[1][rr][j]) + part[2][rr][j]) + part[3][rr][j];
+            gt[rr][j] = v;
+            if (r < p && j < m) g64[(size_t)j * p + r] = v;
+            xt[rr][j] = (with_x == 1 && r < p && j < m) ? (double)X[(size_t)j * ldx + r] : 0.0;
+        }
+    }
+    __syncthreads();
+    const int mm = m * m;
+    double* out = gram + (size_t)blockIdx.x * 3 * mm;
+    if (with_x == 2) {
+        for (int a = t; a < m; a += 256) {
+            double sgg = 0.0;
+            for (int k = 0; k < nr; ++k) sgg += gt[k][a] * gt[k][a];
+            out[a * m + a] = sgg;
+        }
+        return;
+    }
+    for (int e = t; e < 3 * mm; e += 256) {
+        const int which = e / mm, ab = e % mm, a = ab / m, b = ab % m;
+        double s2 = 0.0;
+        if (which == 0)
+            for (int k = 0; k < nr; ++k) s2 += gt[k][a] * gt[k][b];
+        else if (which == 1)
+            for (int k = 0; k < nr; ++k) s2 += gt[k][a] * xt[k][b];
+        else
+            for (int k = 0; k < nr; ++k) s2 += xt[k][a] * xt[k][b];
+        out[e] = s2;
+    }
+}
+
+hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* touched,
+                              const float* X, int with_x, double* g64, double* gram,
+                              const Ctrl* ctrl, hipStream_t st) {
+    const int grid = (int)((pl.p + 63) / 64);
+#define GPSPCA_RG(MB)                                                                        \
+    hipLaunchKernelGGL(k_reduce_gram<MB>, dim3(grid), dim3(256), 0, st, gpart, touched,     \
+                       pl.npart, pl.m, pl.ldx, (int)pl.p, X, with_x, g64, gram, ctrl)
+    if (pl.m <= 1) GPSPCA_RG(1);
+    else if (pl.m <= 2) GPSPCA_RG(2);
+    else if (pl.m <= 4) GPSPCA_RG(4);
+    else if (pl.m <= 8) GPSPCA_RG(8);
+    else GPSPCA_RG(16);
+#undef GPSPCA_RG
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Symmetric eigen-decomposition by the cyclic Jacobi method with a parallel
 // (round-robin) ordering: each step applies msz/2 disjoint plane rotations.
 // a (msz x msz, leading dim LDM, LDS) is diagonalized in place; v receives the
-// eigenvectors (columns).  Executed by the whole workgroup.
-__device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs) {
+// eigenvectors (columns).  With `warm`, v already holds an orthogonal V0 and a
+// holds V0^T M V0: the rotations continue from there (V <- V0 J ...).
+// Executed by the whole workgroup.
+__device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
+                           bool warm = false) {
     const int t = threadIdx.x, nt = blockDim.x;
-    for (int e = t; e < msz * msz; e += nt) {
-        const int i = e / msz, j = e % msz;
-        v[i * LDM + j] = (i == j) ? 1.0 : 0.0;
+    if (!warm) {
+        for (int e = t; e < msz * msz; e += nt) {
+            const int i = e / msz, j = e % msz;
+            v[i * LDM + j] = (i == j) ? 1.0 : 0.0;
+        }
     }
     __syncthreads();
     if (msz < 2) return;
@@ -292,21 +423,9 @@ struct StopShared {
     int nlive, ndead, rankdef, stop;
 };
 
-// Sum per-block Gram partials in fixed order into coef scratch:
-// coef[2mm..3mm) = G^T G, [3mm..4mm) = G^T X, [4mm..5mm) = X^T X.
-__device__ void sum_gram(int m, int ngram, const double* __restrict__ gram, double* coef) {
-    const int mm = m * m;
-    for (int e = threadIdx.x; e < 3 * mm; e += blockDim.x) {
-        double s = 0.0;
-        for (int g = 0; g < ngram; ++g) s += gram[(size_t)g * 3 * mm + e];
-        coef[2 * mm + e] = s;
-    }
-    __syncthreads();
-}
-
 // Retraction coefficients for the block forms with live set L and dead set D.
-__device__ void block_coefficients(int m, double* coef, StopShared& ss, double* A0, double* A1,
-                                   double* A2, double* red, Ctrl* ctrl) {
+__device__ void block_coefficients(int m, double* coef, double* vprev, StopShared& ss,
+                                   double* A0, double* A1, double* A2, Ctrl* ctrl) {
     const int t = threadIdx.x, nt = blockDim.x, mm = m * m;
     const double* GtG = coef + 2 * mm;
     const double* GtX = coef + 3 * mm;
@@ -316,12 +435,38 @@ __device__ void block_coefficients(int m, double* coef, StopShared& ss, double* 
     const int nl = ss.nlive, nd = ss.ndead;
     for (int e = t; e < 2 * mm; e += nt) coef[e] = 0.0;
     // W_L = (G_L^T G_L)^{-1/2}
+    const bool warm = (nd == 0) && ctrl->warm;
     for (int e = t; e < nl * nl; e += nt) {
         const int i = e / nl, j = e % nl;
         A0[i * LDM + j] = GtG[ss.live[i] * m + ss.live[j]];
+        if (warm) A1[i * LDM + j] = vprev[i * m + j];
     }
     __syncthreads();
-    jacobi_eig(A0, A1, nl, ss.rot, ss.prs);
+    if (warm) {
+        // A0 <- V0^T M V0 with the previous pass's eigenvectors V0: the Gram matrix
+        // changes little between passes, so this is nearly diagonal already
+        for (int e = t; e < nl * nl; e += nt) {
+            const int i = e / nl, j = e % nl;
+            double s2 = 0.0;
+            for (int k = 0; k < nl; ++k) s2 += A0[i * LDM + k] * A1[k * LDM + j];
+            A2[i * LDM + j] = s2;
+        }
+        __syncthreads();
+        for (int e = t; e < nl * nl; e += nt) {
+            const int i = e / nl, j = e % nl;
+            double s2 = 0.0;
+            for (int k = 0; k < nl; ++k) s2 += A1[k * LDM + i] * A2[k * LDM + j];
+            A0[i * LDM + j] = s2;
+        }
+        __syncthreads();
+    }
+    jacobi_eig(A0, A1, nl, ss.rot, ss.prs, warm);
+    if (nd == 0) {
+        for (int e = t; e < nl * nl; e += nt) {
+            const int i = e / nl, j = e % nl;
+            vprev[i * m + j] = A1[i * LDM + j];
+        }
+    }
     int rd1 = 0;
     inv_sqrt_from_eig(A0, A1, A2, nl, ss.lam, &ss.rankdef);
     rd1 = ss.rankdef;
@@ -389,6 +534,7 @@ __device__ void block_coefficients(int m, double* coef, StopShared& ss, double* 
     }
     if (t == 0) {
         ctrl->ndead = nd;
+        ctrl->warm = (nd == 0) ? 1 : 0;
         if (nd > 0 || rd1 || ss.rankdef) ctrl->degenerate_seen = 1;
     }
     __syncthreads();
@@ -396,13 +542,13 @@ __device__ void block_coefficients(int m, double* coef, StopShared& ss, double* 
 
 // One workgroup: objective, trace, stopping rule, retraction coefficients.
 __global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
-                       const int* __restrict__ nnzpart, int ngram, const double* __restrict__ gram,
+                       const int* __restrict__ nnzpart, double* __restrict__ vprev,
                        double* __restrict__ trace, double* __restrict__ coef,
                        double* __restrict__ fcomp, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ StopShared ss;
-    __shared__ double red[2 * 256];
-    __shared__ int redi[256];
+    __shared__ double red[512];
+    __shared__ int redi[512];
     extern __shared__ double dyn[];
     double* A0 = dyn;
     double* A1 = dyn + (size_t)m * LDM;
@@ -410,31 +556,38 @@ __global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
     const int t = threadIdx.x, nt = blockDim.x;
     const int k = ctrl->k;
 
-    for (int j = 0; j < m; ++j) {
-        double s = 0.0;
-        int c = 0;
-        const double* fj = fpart + (size_t)j * nwp;
-        const int* cj = nnzpart + (size_t)j * nwp;
+    // per-component objective and support size: tpc threads per component,
+    // each summing a strided slice, slices added in order (fixed order)
+    {
+        const int tpc = nt / m >= 1 ? nt / m : 1;
+        for (int j0 = 0; j0 < m; j0 += nt / tpc) {
+            const int j = j0 + t / tpc, sl = t % tpc;
+            double s = 0.0;
+            int c = 0;
+            if (j < m && t / tpc < nt / tpc) {
+                const double* fp = fpart + (size_t)j * nwp;
+                const int* cp = nnzpart + (size_t)j * nwp;
 #pragma unroll 8
-        for (int w = t; w < nwp; w += nt) {
-            s += fj[w];
-            c += cj[w];
-        }
-        red[t] = s;
-        redi[t] = c;
-        __syncthreads();
-        for (int h = nt / 2; h > 0; h >>= 1) {
-            if (t < h) {
-                red[t] += red[t + h];
-                redi[t] += redi[t + h];
+                for (int w = sl; w < nwp; w += tpc) {
+                    s += fp[w];
+                    c += cp[w];
+                }
+            }
+            red[t] = s;
+            redi[t] = c;
+            __syncthreads();
+            if (sl == 0 && j < m) {
+                double a = 0.0;
+                int b = 0;
+                for (int q = 0; q < tpc; ++q) {
+                    a += red[t + q];
+                    b += redi[t + q];
+                }
+                ss.fj[j] = a;
+                ss.nj[j] = b;
             }
             __syncthreads();
         }
-        if (t == 0) {
-            ss.fj[j] = red[0];
-            ss.nj[j] = redi[0];
-        }
-        __syncthreads();
     }
     if (t == 0) {
         double F = 0.0;
@@ -474,7 +627,6 @@ __global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
     __syncthreads();
     if (ss.stop) return;
 
-    sum_gram(m, ngram, gram, coef);
     const int mm = m * m;
     if (m == 1) {
         if (t == 0) {
@@ -491,16 +643,15 @@ __global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
         }
         __syncthreads();
     } else {
-        block_coefficients(m, coef, ss, A0, A1, A2, red, ctrl);
-        // finiteness of the coefficients
-        if (t == 0) {
-            int ok = 1;
-            for (int e = 0; e < 2 * mm; ++e) ok &= isfinite(coef[e]) ? 1 : 0;
-            if (!ok) {
-                ctrl->status = GPSPCA_ENONFINITE;
-                ctrl->done = 1;
-                ctrl->n_iter = k + 1;
-            }
+        block_coefficients(m, coef, vprev, ss, A0, A1, A2, ctrl);
+        // finiteness of the coefficients (every thread checks its share)
+        int bad = 0;
+        for (int e = t; e < 2 * mm; e += nt) bad |= isfinite(coef[e]) ? 0 : 1;
+        if (__syncthreads_or(bad) && t == 0) {
+            ctrl->status = GPSPCA_ENONFINITE;
+            ctrl->done = 1;
+            ctrl->n_iter = k + 1;
+            ctrl->warm = 0;
         }
         __syncthreads();
     }
@@ -509,13 +660,15 @@ __global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
 
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
-                       Ctrl* ctrl, hipStream_t st) {
-    const int threads = 256;
+                       double* vprev, Ctrl* ctrl, hipStream_t st) {
+    hipError_t e = launch_gram_sum(pl, 3 * pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st);
+    if (e != hipSuccess) return e;
+    const int threads = pl.m > 16 ? 512 : 256;
     const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
-                       nnzpart, pl.gram_grid, gram, trace, coef, fcomp, ctrl);
+                       nnzpart, vprev, trace, coef, fcomp, ctrl);
     return hipGetLastError();
 }
 
@@ -525,8 +678,7 @@ hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
 // x_j <- g_j / ||g_j||; a column whose rule fired is frozen (Psi_jj = 1), so
 // its x, and with it S, F and Z, stay those of its stopping pass.
 __global__ void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
-                            const int* __restrict__ nnzpart, int ngram,
-                            const double* __restrict__ gram, double* __restrict__ trace,
+                            const int* __restrict__ nnzpart, double* __restrict__ trace,
                             double* __restrict__ coef, double* __restrict__ fcomp,
                             PathState* __restrict__ ps, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
@@ -566,7 +718,7 @@ __global__ void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
         __syncthreads();
     }
     if (t == 0) nfrozen = 0;
-    for (int e = t; e < 2 * mm; e += nt) coef[e] = 0.0;
+    for (int e = t; e < 2 * mm; e += nt) coef[e] = 0.0;  // Omega, Psi (the summed Gram is at 2mm)
     __syncthreads();
     for (int j = t; j < m; j += nt) {
         const double F = fj[j];
@@ -596,8 +748,7 @@ __global__ void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
             st.last_F = F;
             ps[j] = st;
         }
-        double g2 = 0.0;
-        for (int g = 0; g < ngram; ++g) g2 += gram[(size_t)g * 3 * mm + (size_t)j * m + j];
+        const double g2 = coef[2 * mm + (size_t)j * m + j];
         if (st.frozen) {
             coef[mm + j * m + j] = 1.0;
             atomicAdd(&nfrozen, 1);
@@ -621,8 +772,10 @@ __global__ void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
 hipError_t launch_stop_path(const Plan& pl, const double* fpart, const int* nnzpart,
                             const double* gram, double* trace, double* coef, double* fcomp,
                             PathState* ps, Ctrl* ctrl, hipStream_t st) {
+    hipError_t e = launch_gram_sum(pl, pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_stop_path, dim3(1), dim3(256), 0, st, pl.m, pl.nwave_part, fpart,
-                       nnzpart, pl.gram_grid, gram, trace, coef, fcomp, ps, ctrl);
+                       nnzpart, trace, coef, fcomp, ps, ctrl);
     return hipGetLastError();
 }
 
@@ -644,15 +797,13 @@ hipError_t launch_bcast_col0(const Plan& pl, float* X, hipStream_t st) {
 
 // Column-wise normalization of a starting point (gamma path): Omega =
 // diag(1/||x_j||); a zero column fails with GPSPCA_EINVAL.
-__global__ void k_project_diag(int m, int ngram, const double* __restrict__ gram,
-                               double* __restrict__ coef, Ctrl* __restrict__ ctrl) {
+__global__ void k_project_diag(int m, double* __restrict__ coef, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     const int t = threadIdx.x, mm = m * m;
     for (int e = t; e < 2 * mm; e += blockDim.x) coef[e] = 0.0;
     __syncthreads();
     for (int j = t; j < m; j += blockDim.x) {
-        double g2 = 0.0;
-        for (int g = 0; g < ngram; ++g) g2 += gram[(size_t)g * 3 * mm + (size_t)j * m + j];
+        const double g2 = coef[2 * mm + (size_t)j * m + j];
         const double om = 1.0 / sqrt(g2);
         coef[j * m + j] = om;
         if (!(g2 > 0.0) || !isfinite(om)) {
@@ -665,15 +816,15 @@ __global__ void k_project_diag(int m, int ngram, const double* __restrict__ gram
 
 hipError_t launch_project_diag(const Plan& pl, const double* gram, double* coef, Ctrl* ctrl,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_project_diag, dim3(1), dim3(256), 0, st, pl.m, pl.gram_grid, gram, coef,
-                       ctrl);
+    hipError_t e = launch_gram_sum(pl, pl.m * pl.m, pl.gram_grid, gram, coef, ctrl, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_project_diag, dim3(1), dim3(256), 0, st, pl.m, coef, ctrl);
     return hipGetLastError();
 }
 
 // Projection of a starting point onto the feasible set: Omega = (G^T G)^{-1/2}
 // (or 1/||g||); a rank-deficient start fails with GPSPCA_EINVAL.
-__global__ void k_project(int m, int ngram, const double* __restrict__ gram,
-                          double* __restrict__ coef, Ctrl* __restrict__ ctrl) {
+__global__ void k_project(int m, double* __restrict__ coef, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ StopShared ss;
     __shared__ double red[2 * 256];
@@ -682,7 +833,6 @@ __global__ void k_project(int m, int ngram, const double* __restrict__ gram,
     double* A1 = dyn + (size_t)m * LDM;
     double* A2 = dyn + (size_t)2 * m * LDM;
     const int t = threadIdx.x, nt = blockDim.x, mm = m * m;
-    sum_gram(m, ngram, gram, coef);
     if (m == 1) {
         if (t == 0) {
             const double g2 = coef[2];
@@ -709,6 +859,7 @@ __global__ void k_project(int m, int ngram, const double* __restrict__ gram,
     }
     if (t == 0) {
         ctrl->ndead = 0;
+        ctrl->warm = 0;
         if (ss.rankdef) {
             ctrl->status = GPSPCA_EINVAL;
             ctrl->done = 1;
@@ -718,18 +869,19 @@ __global__ void k_project(int m, int ngram, const double* __restrict__ gram,
 
 hipError_t launch_project(const Plan& pl, const double* gram, double* coef, Ctrl* ctrl,
                           hipStream_t st) {
-    const int threads = pl.m <= 16 ? 64 : 256;
+    hipError_t e = launch_gram_sum(pl, pl.m * pl.m, pl.gram_grid, gram, coef, ctrl, st);
+    if (e != hipSuccess) return e;
+    const int threads = pl.m > 16 ? 512 : 256;
     const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_project), true);
     (void)lds_once;
-    hipLaunchKernelGGL(k_project, dim3(1), dim3(threads), shm, st, pl.m, pl.gram_grid, gram,
-                       coef, ctrl);
+    hipLaunchKernelGGL(k_project, dim3(1), dim3(threads), shm, st, pl.m, coef, ctrl);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // X_{k+1}[r, j] = sum_l G[r, l] Omega[l, j] + sum_l X_k[r, l] Psi[l, j]
-template <int MB>
+// grid (row blocks of 256, columns j): one output element per thread.
 __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
                                                const double* __restrict__ g64,
                                                const float* __restrict__ Xk,
@@ -737,53 +889,29 @@ __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
                                                float* __restrict__ Xn,
                                                const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    __shared__ double om[MB * MB];
-    __shared__ double ps[MB * MB];
-    const int t = threadIdx.x, mm = m * m;
+    __shared__ double om[kMaxM];
+    __shared__ double ps[kMaxM];
+    const int t = threadIdx.x, j = blockIdx.y, mm = m * m;
     const bool dead = ctrl->ndead > 0;
-    for (int e = t; e < mm; e += 256) {
-        om[e] = coef[e];
-        ps[e] = dead ? coef[mm + e] : 0.0;
+    for (int l = t; l < m; l += 256) {
+        om[l] = coef[l * m + j];
+        ps[l] = dead ? coef[mm + l * m + j] : 0.0;
     }
     __syncthreads();
     const int r = blockIdx.x * 256 + t;
     if (r >= p) return;
-    double acc[MB];
-#pragma unroll
-    for (int j = 0; j < MB; ++j) acc[j] = 0.0;
-    for (int l = 0; l < m; ++l) {
-        const double gl = g64[(size_t)l * p + r];
-#pragma unroll
-        for (int j = 0; j < MB; ++j)
-            if (j < m) acc[j] += gl * om[l * m + j];
-    }
-    if (dead) {
-        for (int l = 0; l < m; ++l) {
-            const double xl = (double)Xk[(size_t)l * ldx + r];
-#pragma unroll
-            for (int j = 0; j < MB; ++j)
-                if (j < m) acc[j] += xl * ps[l * m + j];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < MB; ++j)
-        if (j < m) Xn[(size_t)j * ldx + r] = (float)acc[j];
+    double acc = 0.0;
+    for (int l = 0; l < m; ++l) acc += g64[(size_t)l * p + r] * om[l];
+    if (dead)
+        for (int l = 0; l < m; ++l) acc += (double)Xk[(size_t)l * ldx + r] * ps[l];
+    Xn[(size_t)j * ldx + r] = (float)acc;
 }
 
 hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, const double* coef,
                         float* Xn, const Ctrl* ctrl, hipStream_t st) {
-    const int m = pl.m, p = (int)pl.p;
-    dim3 grid((p + 255) / 256);
-#define GPSPCA_APPLY(MB)                                                                        \
-    hipLaunchKernelGGL(k_apply<MB>, grid, dim3(256), 0, st, m, p, pl.ldx, g64, Xk, coef, Xn, ctrl)
-    if (m <= 1) GPSPCA_APPLY(1);
-    else if (m <= 2) GPSPCA_APPLY(2);
-    else if (m <= 4) GPSPCA_APPLY(4);
-    else if (m <= 8) GPSPCA_APPLY(8);
-    else if (m <= 16) GPSPCA_APPLY(16);
-    else if (m <= 32) GPSPCA_APPLY(32);
-    else GPSPCA_APPLY(64);
-#undef GPSPCA_APPLY
+    const int p = (int)pl.p;
+    hipLaunchKernelGGL(k_apply, dim3((p + 255) / 256, pl.m), dim3(256), 0, st, pl.m, p, pl.ldx,
+                       g64, Xk, coef, Xn, ctrl);
     return hipGetLastError();
 }
 

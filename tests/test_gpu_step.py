@@ -43,6 +43,7 @@ CASES = [
     (O.SL1, 1, 20996, 600, 0, 19),
     (O.BL0, 5, 1002, 37, 2, 20),
     (O.BL1, 2, 3, 500, 1, 21),
+    (O.BL0, 6, 12004, 400, 0, 22),   # m <= 8 with p > 10240: matrix-core path
 ]
 
 
@@ -95,3 +96,31 @@ def test_step_zero_gamma_dense_support(gpu, form):
     assert list(out.nnz) == [n] * m
     assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
     np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
+
+
+@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "valu"])
+@pytest.mark.parametrize("form,m", [(O.BL1, 4), (O.BL0, 8)])
+def test_every_correlation_kernel(gpu, kernel, form, m, monkeypatch):
+    """Force each block correlation kernel (registers-X, matrix cores through
+    registers, matrix cores through LDS DMA, plain vector ALU) on the same case:
+    one step and a 6-pass solve against the oracle."""
+    monkeypatch.setenv("GPSPCA_CORR_KERNEL", kernel)
+    p, n = 1003, 3001  # ragged row quad
+    A32, _, _ = W.planted_block(p, n, 3, 23, k=40)
+    A64 = A32.astype(np.float64)
+    mu = np.linspace(1.0, 0.7, m)
+    X0 = fp32_round(O.init(A64, m)[0])
+    g0 = W.gamma_absolute(A64, is_l0(form), 0.02 if is_l0(form) else 0.05)
+    gamma = pick_gamma(A64, form, m, mu, X0, g0, iters=6)
+    Ad = to_device(A32, lda=p + 1)  # lda % 4 == 0: every kernel is eligible
+    ref = O.step(A64, form, X0, gamma, mu=mu)
+    out = gpu.step(Ad, form, x_to_device(X0), gamma, mu=list(mu))
+    ties = tie_mask(A64, X0, form, gamma, mu)
+    S = out.S.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal((S != 0)[~ties], (ref["S"] != 0)[~ties])
+    assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
+    np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
+    rs = O.solve(A64, form, m, gamma, mu=mu, X0=X0, tol=0.0, max_iter=6)
+    res = gpu.solve(Ad, form, m, gamma, mu=list(mu), X0=x_to_device(X0), tol=0.0, max_iter=6)
+    assert rel(res.X.cpu().numpy(), rs["X"]) <= 1e-5
+    np.testing.assert_allclose(res.trace, rs["trace"], rtol=1e-5)
