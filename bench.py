@@ -15,7 +15,6 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -44,6 +43,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary workloads (BL0, m=64, m=1 and the 5000x50000 single-unit case)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after timing, run 3 plain device copies (x * 1) of this many MiB; their "
+                         "HBM counter readings calibrate FETCH_SIZE / WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -68,18 +70,43 @@ def kernel_source_hash(kernel: str) -> str:
 
 
 def traffic_from_profiles(kernel: str, workload_key: str):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload_key}.json")
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain-copy
+    calibration) from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload_key}.md")
     if not os.path.exists(path):
         return None
+    kv = {}
+    for line in open(path):
+        k, sep, v = line.partition(" = ")
+        if sep and " " not in k.strip():
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_hash") != kernel_source_hash(kernel):
+        return None
     try:
-        d = json.load(open(path))
-    except Exception:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
         return None
-    if d.get("kernel_hash") != kernel_source_hash(kernel):
-        return None
-    return d.get("bytes_per_launch")
+
+
+def algorithmic_bytes(kernel: str, p: int, n: int, m: int) -> float:
+    """HBM bytes one launch of the dominant kernel must move: per column a_i, its
+    p FP32 entries read and m FP32 thresholded values written (plus a 1-byte
+    activity flag for the block kernels); X (p x m FP32) read once."""
+    per_col = 4.0 * p + 4.0 * m + (0.0 if kernel == "k_pass_m1" else 1.0)
+    return n * per_col + 4.0 * p * m
+
+
+def copy_calibration(torch, mib: int):
+    """Plain device copies of known size (read 4N bytes, write 4N bytes each),
+    for scaling the HBM byte counters."""
+    src = torch.ones(mib * (1 << 18), dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: 3 x {mib} MiB read + {mib} MiB written", file=sys.stderr,
+          flush=True)
 
 
 def time_gpu(G, torch, Ad, form, m, gamma, steps, warmup):
@@ -161,8 +188,9 @@ def main():
     ms_per_step = ms / args.steps
     iters_per_s = 1000.0 / ms_per_step
     a_bytes = float(args.p) * args.n * 4.0
+    alg_bytes = algorithmic_bytes(kname, args.p, args.n, m)
     k_avg_ms = kms / max(1, launches)
-    achieved = a_bytes / (k_avg_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
     nnz = int(r.support_mask().sum().item())
     print(f"[bench] {args.steps} passes in {ms:.2f} ms; {kname} avg {k_avg_ms*1e3:.1f} us "
           f"({achieved:.0f} GB/s); final support {nnz}", file=sys.stderr, flush=True)
@@ -188,7 +216,7 @@ def main():
                         f"gamma={frac} max||a_i||{'^2' if l0 else ''}, mu=1, tol=0 (fixed passes)",
             "p": args.p, "n": args.n, "m": m, "form": args.form, "gamma": gamma,
         },
-        "hbm_gbps": a_bytes * args.steps / (ms * 1e-3) / 1e9,
+        "a_stream_gbps_whole_step": a_bytes * args.steps / (ms * 1e-3) / 1e9,
         "roofline": {
             "bound": "hbm",
             "kernel": kname,
@@ -197,7 +225,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": a_bytes,
+            "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_us": k_avg_ms * 1e3,
         },
         "final_support_nnz": nnz,
@@ -206,25 +234,29 @@ def main():
         extra = {}
         xs = max(5, args.steps // 3)
 
-        def rec(name, Adev, fid, mm, g, nbytes):
+        def rec(name, Adev, fid, mm, g):
             r2, ms2, kms2, l2, kn2 = time_gpu(G, torch, Adev, fid, mm, g, xs, 2)
+            pp, nn = Adev.shape
             extra[name] = {"iters_per_s": 1000.0 * xs / ms2, "kernel": kn2,
-                           "kernel_gbps": nbytes / (kms2 / max(1, l2) * 1e-3) / 1e9,
+                           "kernel_gbps": algorithmic_bytes(kn2, pp, nn, mm)
+                           / (kms2 / max(1, l2) * 1e-3) / 1e9,
                            "ms_per_step": ms2 / xs}
             print(f"[bench] extra {name}: {extra[name]}", file=sys.stderr, flush=True)
 
         if args.p == 10000 and args.n == 100000:
-            rec("c3_BL0_m8", Ad, 3, 8, 0.01 * cmax * cmax, a_bytes)
-            rec("c3_BL1_m64", Ad, 2, 64, 0.05 * cmax, a_bytes)
-            rec("c3_SL1_m1", Ad, 0, 1, 0.05 * cmax, a_bytes)
+            rec("c3_BL0_m8", Ad, 3, 8, 0.01 * cmax * cmax)
+            rec("c3_BL1_m64", Ad, 2, 64, 0.05 * cmax)
+            rec("c3_SL1_m1", Ad, 0, 1, 0.05 * cmax)
         A2, _, _, _ = W.planted_single(5000, 50000, args.seed, k=500)
         c2max = column_norm_max(A2)
         A2d = torch.from_numpy(np.ascontiguousarray(A2.T)).cuda().t()
-        rec("c2_SL1_f0.05", A2d, 0, 1, 0.05 * c2max, 5000 * 50000 * 4.0)
-        rec("c2_SL0_f0.01", A2d, 1, 1, 0.01 * c2max * c2max, 5000 * 50000 * 4.0)
-        rec("c2_SL1_f0.01_dense", A2d, 0, 1, 0.01 * c2max, 5000 * 50000 * 4.0)
+        rec("c2_SL1_f0.05", A2d, 0, 1, 0.05 * c2max)
+        rec("c2_SL0_f0.01", A2d, 1, 1, 0.01 * c2max * c2max)
+        rec("c2_SL1_f0.01_dense", A2d, 0, 1, 0.01 * c2max)
         del A2d
         out["extra"] = extra
+    if args.copy_calibration_mib > 0:
+        copy_calibration(torch, args.copy_calibration_mib)
     if not args.no_cpu:
         print("[bench] timing the oracle on host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(A32, form_id, m, gamma, args.cpu_seconds)
