@@ -47,14 +47,19 @@ def lib():
             L.orc_column_norms.argtypes = [P, i64, i64, i64, P]
             L.orc_top_m.argtypes = [P, i64, i32, P]
             L.orc_polar.argtypes = [P, i64, i32, P, P, P]
-            L.orc_pass.argtypes = [P, i64, i64, i64, i32, i32, d, P, P, P, P, P, P, P]
+            L.orc_pass.argtypes = [P, i64, i64, i64, i32, i32, d, P, P, P, P, P, P, P, P]
             L.orc_retract.argtypes = [i64, i32, P, P, P, P, P]
             L.orc_project.argtypes = [i64, i32, P, P]
             L.orc_init.argtypes = [P, i64, i64, i64, i32, P, P]
-            L.orc_solve.argtypes = [P, i64, i64, i64, i32, i32, d, P, P, d, i32, P, P, P, P, P]
+            L.orc_solve.argtypes = [P, i64, i64, i64, i32, i32, d, P, P, P, d, i32, P, P, P, P, P]
+            L.orc_encode.argtypes = [P, i64, i32, P]
+            L.orc_decode.argtypes = [P, i64, i32, P]
+            L.orc_quantize.argtypes = [P, i64, i64, i64, i32, P, i64, P]
+            L.orc_dequantize.argtypes = [P, i64, i64, i64, i32, P, P]
             L.orc_set_num_threads.argtypes = [i32]
             for name in ("orc_column_norms", "orc_top_m", "orc_polar", "orc_pass", "orc_retract",
-                         "orc_project", "orc_init", "orc_solve", "orc_num_threads"):
+                         "orc_project", "orc_init", "orc_solve", "orc_num_threads", "orc_encode",
+                         "orc_decode", "orc_quantize", "orc_dequantize"):
                 getattr(L, name).restype = i32
             L.orc_set_num_threads.restype = None
             _lib = L
@@ -120,8 +125,16 @@ def polar(G):
     return X, sv, bool(rd.value)
 
 
-def step(A, form: int, X, gamma: float, mu=None):
-    """One pass at X.  Returns dict(Y, S, G, f, nnz, F)."""
+def _mask(mask, n, m):
+    if mask is None:
+        return None
+    mk = np.asfortranarray(np.asarray(mask, dtype=np.uint8).reshape(n, m))
+    return mk
+
+
+def step(A, form: int, X, gamma: float, mu=None, mask=None):
+    """One pass at X.  Returns dict(Y, S, G, f, nnz, F).  mask (n x m bool, or
+    None) forces s_ij = 0 where it is False (pass on a frozen support)."""
     A, p, n, lda = _matrix(A)
     X = np.asfortranarray(np.asarray(X, dtype=np.float64).reshape(p, -1))
     m = X.shape[1]
@@ -131,7 +144,8 @@ def step(A, form: int, X, gamma: float, mu=None):
     G = np.empty((p, m), order="F")
     f = np.empty(m)
     nnz = np.empty(m, dtype=np.int64)
-    rc = lib().orc_pass(_ptr(A), p, n, lda, form, m, float(gamma), _ptr(muv), _ptr(X),
+    mk = _mask(mask, n, m)
+    rc = lib().orc_pass(_ptr(A), p, n, lda, form, m, float(gamma), _ptr(muv), _ptr(X), _ptr(mk),
                         _ptr(Y), _ptr(S), _ptr(G), _ptr(f), _ptr(nnz))
     if rc:
         raise OracleError(rc, "orc_pass")
@@ -175,8 +189,9 @@ def init(A, m: int):
 
 
 def solve(A, form: int, m: int, gamma: float, mu=None, X0=None, tol: float = 1e-4,
-          max_iter: int = 1000):
-    """Full solve.  Returns dict(X, Z, support, trace, n_iter, status)."""
+          max_iter: int = 1000, mask=None):
+    """Full solve.  Returns dict(X, Z, support, trace, n_iter, status).  With a
+    mask (n x m bool), every pass is restricted to that frozen support."""
     A, p, n, lda = _matrix(A)
     muv = None if mu is None else np.ascontiguousarray(mu, dtype=np.float64)
     X0v = None if X0 is None else np.asfortranarray(np.asarray(X0, dtype=np.float64).reshape(p, -1))
@@ -185,10 +200,61 @@ def solve(A, form: int, m: int, gamma: float, mu=None, X0=None, tol: float = 1e-
     sup = np.empty((n, m), dtype=np.uint8, order="F")
     trace = np.zeros(max_iter)
     nit = ctypes.c_int(0)
-    rc = lib().orc_solve(_ptr(A), p, n, lda, form, m, float(gamma), _ptr(muv), _ptr(X0v),
+    mk = _mask(mask, n, m)
+    rc = lib().orc_solve(_ptr(A), p, n, lda, form, m, float(gamma), _ptr(muv), _ptr(X0v), _ptr(mk),
                          float(tol), int(max_iter), _ptr(X), _ptr(Z), _ptr(sup), _ptr(trace),
                          ctypes.byref(nit))
     if rc < 0:
         raise OracleError(rc, "orc_solve")
     k = nit.value
     return dict(X=X, Z=Z, support=sup.astype(bool), trace=trace[:k].copy(), n_iter=k, status=rc)
+
+
+# ---------------------------------------------------------------- storage
+BF16, E4M3 = 1, 2
+
+
+def encode(v, to: int) -> np.ndarray:
+    """Element-wise bfloat16 (to=1, uint16 codes) or e4m3fn (to=2, uint8 codes)
+    rounding of FP32 values, no scaling."""
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.float32).ravel())
+    out = np.empty(v.size, dtype=np.uint16 if to == BF16 else np.uint8)
+    rc = lib().orc_encode(_ptr(v), v.size, int(to), _ptr(out))
+    if rc:
+        raise OracleError(rc, "orc_encode")
+    return out
+
+
+def decode(c, to: int) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.uint16 if to == BF16 else np.uint8).ravel())
+    out = np.empty(c.size)
+    rc = lib().orc_decode(_ptr(c), c.size, int(to), _ptr(out))
+    if rc:
+        raise OracleError(rc, "orc_decode")
+    return out
+
+
+def quantize(A32, to: int, ldq: int | None = None):
+    """Codes (ldq x n column-major array, rows >= p unspecified) and per-column
+    scales of the FP32 matrix A32 (p x n)."""
+    A32 = np.asfortranarray(np.asarray(A32, dtype=np.float32))
+    p, n = A32.shape
+    ldq = p if ldq is None else int(ldq)
+    codes = np.zeros((ldq, n), dtype=np.uint16 if to == BF16 else np.uint8, order="F")
+    scale = np.empty(n, dtype=np.float32)
+    rc = lib().orc_quantize(_ptr(A32), p, n, p, int(to), _ptr(codes), ldq, _ptr(scale))
+    if rc:
+        raise OracleError(rc, "orc_quantize")
+    return codes, scale
+
+
+def dequantize(codes, to: int, scale, p: int) -> np.ndarray:
+    """FP64 (p x n) matrix of code_value * scale_i."""
+    codes = np.asfortranarray(codes)
+    ldq, n = codes.shape
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float32)
+    out = np.empty((p, n), order="F")
+    rc = lib().orc_dequantize(_ptr(codes), p, n, ldq, int(to), _ptr(sc), _ptr(out))
+    if rc:
+        raise OracleError(rc, "orc_dequantize")
+    return out

@@ -210,9 +210,12 @@ static int threshold(int l0, double mu, double gamma, double y, double* s, doubl
  *   G   p x m gradient direction, G = A S N    (column-major, leading dim p)
  *   f   m per-component objective terms; F = sum_j f_j
  *   nnz m per-component support sizes
+ * mask (n x m, may be NULL) restricts the pass to a frozen support: where
+ * mask[j*n + i] == 0 the thresholded value is forced to 0 (refinement on a
+ * support found by a reduced-precision run).
  */
 int orc_pass(const double* A, int64_t p, int64_t n, int64_t lda, int form, int m,
-             double gamma, const double* mu, const double* X,
+             double gamma, const double* mu, const double* X, const unsigned char* mask,
              double* Y, double* S, double* G, double* f, int64_t* nnz) {
     if (!A || !X || !G || !f || p < 1 || n < 1 || lda < p || m < 1) return ORC_EINVAL;
     const int l0 = is_l0(form);
@@ -236,6 +239,7 @@ int orc_pass(const double* A, int64_t p, int64_t n, int64_t lda, int form, int m
                 const double muj = mu ? mu[j] : 1.0;
                 double s, fj;
                 int act = threshold(l0, muj, gamma, yv[j], &s, &fj);
+                if (mask && !mask[(int64_t)j * n + i]) { act = 0; s = 0.0; }
                 if (Y) Y[(int64_t)j * n + i] = yv[j];
                 if (S) S[(int64_t)j * n + i] = s;
                 if (act) {
@@ -379,7 +383,8 @@ int orc_init(const double* A, int64_t p, int64_t n, int64_t lda, int m, double* 
  * F_0..F_k); *n_iter = k + 1.  Returns the status.
  */
 int orc_solve(const double* A, int64_t p, int64_t n, int64_t lda, int form, int m,
-              double gamma, const double* mu, const double* X0, double tol, int max_iter,
+              double gamma, const double* mu, const double* X0, const unsigned char* mask,
+              double tol, int max_iter,
               double* X, double* Z, unsigned char* support, double* trace, int* n_iter) {
     if (!A || !X || !trace || !n_iter) return ORC_EINVAL;
     if (p < 1 || n < 1 || lda < p) return ORC_EINVAL;
@@ -413,7 +418,7 @@ int orc_solve(const double* A, int64_t p, int64_t n, int64_t lda, int form, int 
 
     int degenerate_seen = 0, converged = 0, k = 0;
     for (k = 0; k < max_iter; ++k) {
-        rc = orc_pass(A, p, n, lda, form, m, gamma, muv, Xk, NULL, S, G, f, nnz);
+        rc = orc_pass(A, p, n, lda, form, m, gamma, muv, Xk, mask, NULL, S, G, f, nnz);
         if (rc != ORC_OK) goto done;
         double F = 0.0;
         for (int j = 0; j < m; ++j) F += f[j];
@@ -446,4 +451,141 @@ int orc_solve(const double* A, int64_t p, int64_t n, int64_t lda, int form, int 
 done:
     free(muv); free(Xk); free(Xn); free(G); free(S); free(f); free(nnz);
     return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Reduced-precision storage of A (test reference for the quantized path).
+ *
+ * The paper computes in full precision; storing A in 16 or 8 bits is an
+ * extension whose readings are:
+ *  - bfloat16: the FP32 value rounded to 8 significant bits, ties to the even
+ *    significand (subnormal FP32 values round to multiples of 2^-133, the
+ *    bfloat16 subnormal spacing); column scale 1.
+ *  - OCP float8 e4m3fn (4 exponent bits, bias 7, 3 mantissa bits, no
+ *    infinities, largest finite 448, smallest normal 2^-6, subnormal spacing
+ *    2^-9): column i is scaled by scale_i = max_r |a_ri| / 448 computed in
+ *    FP32 (1 for a zero column), each a_ri / scale_i (FP32 division) is rounded
+ *    to the nearest e4m3 value, ties to even, and saturated at +-448.
+ * The dequantized matrix holds code_value * scale_i, exact in FP64.
+ * ------------------------------------------------------------------------ */
+
+/* Nearest multiple of 2^q to v (|v| small enough to be exact), ties to even. */
+static double round_to_quantum(double v, int q) {
+    return ldexp(nearbyint(ldexp(v, -q)), q);
+}
+
+uint16_t orc_bf16_code(float v) {
+    const double a = fabs((double)v);
+    double r;
+    if (a == 0.0) {
+        r = 0.0;
+    } else if (a < ldexp(1.0, -126)) {
+        r = round_to_quantum(a, -133);
+    } else {
+        int e;
+        frexp(a, &e);                      /* a = f 2^e, 0.5 <= f < 1 */
+        r = round_to_quantum(a, e - 8);    /* 8 significant bits */
+    }
+    float rf = (float)r;                   /* exact (or +inf past the top binade) */
+    if (v < 0 || (v == 0 && signbit(v))) rf = -rf;
+    uint32_t u;
+    memcpy(&u, &rf, 4);
+    return (uint16_t)(u >> 16);
+}
+
+double orc_bf16_value(uint16_t c) {
+    uint32_t u = (uint32_t)c << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+uint8_t orc_e4m3_code(float v) {
+    const uint8_t sign = (v < 0 || (v == 0 && signbit(v))) ? 0x80 : 0x00;
+    const double a = fabs((double)v);
+    if (a >= 448.0) return sign | 0x7E;
+    if (a < ldexp(1.0, -6)) {
+        /* subnormal range: multiples of 2^-9 (a result of 8 * 2^-9 is the
+         * smallest normal, whose code is also 8) */
+        const double k = nearbyint(ldexp(a, 9));
+        return sign | (uint8_t)k;
+    }
+    int e;
+    frexp(a, &e);
+    int E = e - 1;                         /* 2^E <= a < 2^(E+1) */
+    double k = nearbyint(ldexp(a, 3 - E)); /* significand in eighths: 8..16 */
+    if (k == 16.0) { k = 8.0; E += 1; }
+    return sign | (uint8_t)(((E + 7) << 3) | ((int)k - 8));
+}
+
+double orc_e4m3_value(uint8_t c) {
+    const int e = (c >> 3) & 15, mt = c & 7;
+    double v = (e == 0) ? ldexp((double)mt, -9) : ldexp((double)(8 + mt), e - 10);
+    return (c & 0x80) ? -v : v;
+}
+
+/*
+ * Quantize the FP32 matrix A (p x n, leading dim lda) to `to` (1 = bfloat16,
+ * 2 = e4m3fn) into codes (leading dim ldq >= p, uint16 or uint8 elements) and
+ * scale (n floats; all 1 for bfloat16).
+ */
+int orc_quantize(const float* A, int64_t p, int64_t n, int64_t lda, int to, void* codes,
+                 int64_t ldq, float* scale) {
+    if (!A || !codes || !scale || p < 1 || n < 1 || lda < p || ldq < p) return ORC_EINVAL;
+    if (to != 1 && to != 2) return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const float* a = A + i * lda;
+        if (to == 1) {
+            uint16_t* q = (uint16_t*)codes + i * ldq;
+            for (int64_t r = 0; r < p; ++r) q[r] = orc_bf16_code(a[r]);
+            scale[i] = 1.0f;
+        } else {
+            uint8_t* q = (uint8_t*)codes + i * ldq;
+            float mx = 0.0f;
+            for (int64_t r = 0; r < p; ++r) {
+                const float t = fabsf(a[r]);
+                if (t > mx) mx = t;
+            }
+            const float sc = (mx > 0.0f) ? mx / 448.0f : 1.0f;
+            for (int64_t r = 0; r < p; ++r) q[r] = orc_e4m3_code(a[r] / sc);
+            scale[i] = sc;
+        }
+    }
+    return ORC_OK;
+}
+
+/* FP64 matrix of the dequantized values code_value * scale_i (leading dim p). */
+int orc_dequantize(const void* codes, int64_t p, int64_t n, int64_t ldq, int to,
+                   const float* scale, double* out) {
+    if (!codes || !out || p < 1 || n < 1 || ldq < p) return ORC_EINVAL;
+    if (to != 1 && to != 2) return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double sc = scale ? (double)scale[i] : 1.0;
+        for (int64_t r = 0; r < p; ++r) {
+            const double v = (to == 1) ? orc_bf16_value(((const uint16_t*)codes)[i * ldq + r])
+                                       : orc_e4m3_value(((const uint8_t*)codes)[i * ldq + r]);
+            out[i * p + r] = v * sc;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Element-wise codes and values (no column scaling), for checks. */
+int orc_encode(const float* v, int64_t cnt, int to, void* out) {
+    if (!v || !out || cnt < 0 || (to != 1 && to != 2)) return ORC_EINVAL;
+    for (int64_t k = 0; k < cnt; ++k) {
+        if (to == 1) ((uint16_t*)out)[k] = orc_bf16_code(v[k]);
+        else ((uint8_t*)out)[k] = orc_e4m3_code(v[k]);
+    }
+    return ORC_OK;
+}
+
+int orc_decode(const void* c, int64_t cnt, int to, double* out) {
+    if (!c || !out || cnt < 0 || (to != 1 && to != 2)) return ORC_EINVAL;
+    for (int64_t k = 0; k < cnt; ++k)
+        out[k] = (to == 1) ? orc_bf16_value(((const uint16_t*)c)[k])
+                           : orc_e4m3_value(((const uint8_t*)c)[k]);
+    return ORC_OK;
 }
