@@ -89,11 +89,14 @@ def traffic_from_profiles(kernel: str, workload_key: str):
         return None
 
 
-def algorithmic_bytes(kernel: str, p: int, n: int, m: int) -> float:
+def algorithmic_bytes(kernel: str, p: int, n: int, m: int, elem_bytes: int = 4,
+                      scaled: bool = False) -> float:
     """HBM bytes one launch of the dominant kernel must move: per column a_i, its
-    p FP32 entries read and m FP32 thresholded values written (plus a 1-byte
-    activity flag for the block kernels); X (p x m FP32) read once."""
-    per_col = 4.0 * p + 4.0 * m + (0.0 if kernel == "k_pass_m1" else 1.0)
+    p entries read (4, 2 or 1 bytes each, plus a 4-byte scale for e4m3) and m FP32
+    thresholded values written (plus a 1-byte activity flag for the block
+    kernels); X (p x m FP32) read once."""
+    per_col = (elem_bytes * p + (4.0 if scaled else 0.0) + 4.0 * m
+               + (0.0 if kernel == "k_pass_m1" else 1.0))
     return n * per_col + 4.0 * p * m
 
 
@@ -107,6 +110,44 @@ def copy_calibration(torch, mib: int):
     torch.cuda.synchronize()
     print(f"[bench] copy calibration: 3 x {mib} MiB read + {mib} MiB written", file=sys.stderr,
           flush=True)
+
+
+def gamma_path_leg(G, torch, W, Ad, A32, cmax, passes, K=32):
+    """32 single-unit problems (gamma fractions log-spaced 0.01 .. 0.5) sharing each
+    pass over A, with A stored in FP32, bfloat16 and e4m3fn (+ per-column scales):
+    passes/s, solve-iterations/s (K x passes/s) and the correlation kernel's rate."""
+    p, n = Ad.shape
+    fr = W.gamma_fractions(K)
+    res = {}
+    for name, dt in (("f32", None), ("bf16", torch.bfloat16), ("e4m3", torch.float8_e4m3fn)):
+        if dt is None:
+            Aq, sc, es = Ad, None, 4
+        else:
+            Aq, sc = G.quantize(Ad, dt)
+            es = 2 if dt == torch.bfloat16 else 1
+        for form, fname in ((0, "SL1"), (1, "SL0")):
+            gam = [float(f * (cmax * cmax if form == 1 else cmax)) for f in fr]
+            w = G.solve_path(Aq, form, gam, tol=0.0, max_iter=2, col_scale=sc)
+            torch.cuda.synchronize()
+            G.profile_read()
+            G.profile_enable(True)
+            t0 = time.perf_counter()
+            r = G.solve_path(Aq, form, gam, X0=w.X, tol=0.0, max_iter=passes, col_scale=sc)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            G.profile_enable(False)
+            kms, launches, kname = G.profile_read()
+            kb = algorithmic_bytes(kname, p, n, K, es, dt == torch.float8_e4m3fn)
+            res[f"{name}_{fname}"] = {
+                "passes_per_s": passes / el, "solve_iters_per_s": K * passes / el,
+                "kernel": kname, "kernel_us": 1e3 * kms / max(1, launches),
+                "kernel_gbps": kb / (kms / max(1, launches) * 1e-3) / 1e9,
+                "a_bytes_per_pass": float(p) * n * es}
+            print(f"[bench] gamma path {name} {fname}: {res[f'{name}_{fname}']}", file=sys.stderr,
+                  flush=True)
+            del r, w
+        del Aq, sc
+    return res
 
 
 def time_gpu(G, torch, Ad, form, m, gamma, steps, warmup):
@@ -255,6 +296,8 @@ def main():
         rec("c2_SL1_f0.01_dense", A2d, 0, 1, 0.01 * c2max)
         del A2d
         out["extra"] = extra
+    if not args.no_extra and args.p == 10000 and args.n == 100000:
+        out["c4_gamma_path"] = gamma_path_leg(G, torch, W, Ad, A32, cmax, max(5, args.steps // 5))
     if args.copy_calibration_mib > 0:
         copy_calibration(torch, args.copy_calibration_mib)
     if not args.no_cpu:

@@ -51,10 +51,14 @@ extern "C" {
 #define GPSPCA_BL1 2
 #define GPSPCA_BL0 3
 
-/* Storage types of A. */
+/* Storage types of A.  The paper stores A in full precision; 16- and 8-bit
+ * storage is an extension that moves 2 or 1 bytes per element per pass while
+ * the arithmetic stays FP32 (see gpspca_quantize for the rounding). */
 #define GPSPCA_F32 0
-#define GPSPCA_BF16 1     /* bfloat16, value = bf16 * col_scale[i] (scale optional) */
-#define GPSPCA_F8E4M3 2   /* OCP float8 e4m3fn, value = fp8 * col_scale[i] (scale required) */
+#define GPSPCA_BF16 1     /* bfloat16 codes; value = bf16 * col_scale[i] (scale optional);
+                             lda a multiple of 8, data 16-byte aligned */
+#define GPSPCA_F8E4M3 2   /* OCP float8 e4m3fn codes; value = e4m3 * col_scale[i] (scale
+                             required); lda a multiple of 16, data 16-byte aligned */
 
 /* Status codes. */
 #define GPSPCA_OK 0
@@ -73,11 +77,12 @@ extern "C" {
 typedef struct gpspca_matrix {
     const void* data;        /* device, column-major p x n */
     int64_t p;               /* rows (samples), >= 1 */
-    int64_t n;               /* columns (variables), >= 1 */
+    int64_t n;               /* columns (variables), 1 <= n < 2^31 */
     int64_t lda;             /* leading dimension in elements, >= p */
     int32_t dtype;           /* GPSPCA_F32 | GPSPCA_BF16 | GPSPCA_F8E4M3 */
     int32_t reserved;
-    const float* col_scale;  /* device, n FP32 per-column scales, or NULL (= 1) */
+    const float* col_scale;  /* device, n FP32 per-column scales (BF16: optional, F8E4M3:
+                                required, F32: must be NULL) */
 } gpspca_matrix;
 
 /* Bytes of device workspace that gpspca_solve needs for this problem.
@@ -155,10 +160,115 @@ int gpspca_solve_path(const gpspca_matrix* A, int form, int K, const double* gam
                       int* n_iter, int* status);
 
 /*
+ * Refinement on a frozen support (for results of a reduced-precision solve).
+ * Runs passes of the iteration of gpspca_solve on the FP32 matrix A in which
+ * s_ij is forced to 0 wherever bit (i % 32) of word (j * ceil(n/32) + i/32) of
+ * `support_in` (device, as written by gpspca_solve) is clear; only the
+ * columns with a bit set are read.  X0 (device p x m, required) is the start,
+ * typically the reduced-precision result; it is projected like gpspca_solve's
+ * X0.  tol, max_iter, the workspace (gpspca_workspace_bytes of the same
+ * problem) and the outputs are those of gpspca_solve.  A must be F32
+ * (GPSPCA_EDTYPE otherwise).  Synchronizes `stream`.
+ */
+int gpspca_refine(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
+                  const uint32_t* support_in, const float* X0, double tol, int max_iter,
+                  void* workspace, size_t ws_bytes, void* stream,
+                  float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter);
+
+/* The same for a gamma path: K single-unit problems, problem k restricted to
+ * its own support words (k * ceil(n/32) ...), started from column k of X0.
+ * Workspace: gpspca_path_workspace_bytes(A, K, max_iter).  Outputs as in
+ * gpspca_solve_path. */
+int gpspca_refine_path(const gpspca_matrix* A, int form, int K, const double* gammas,
+                       const uint32_t* support_in, const float* X0, double tol, int max_iter,
+                       void* workspace, size_t ws_bytes, void* stream,
+                       float* X, float* Z, uint32_t* support, double* obj_trace,
+                       int* n_iter, int* status);
+
+/*
+ * Reduced-precision copy of an FP32 matrix A (device) into `out` (device,
+ * column-major, leading dimension ldq >= p elements; ldq a multiple of 8 for
+ * BF16 and of 16 for F8E4M3 if the result is to be solved on; rows p..ldq-1 are
+ * left untouched).
+ *  to = GPSPCA_BF16:    out = bfloat16(a_ri), rounded to nearest even; if
+ *                       col_scale is not NULL it receives n ones.
+ *  to = GPSPCA_F8E4M3:  col_scale[i] = max_r |a_ri| / 448 in FP32 (1 for a
+ *                       zero column); out = e4m3fn(a_ri / col_scale[i]) rounded
+ *                       to nearest even and saturated at +-448 (col_scale
+ *                       required, device, n floats).
+ * Stream-ordered; does not synchronize.
+ */
+int gpspca_quantize(const gpspca_matrix* A, int to, void* out, int64_t ldq, float* col_scale,
+                    void* stream);
+
+/*
  * Column norms ||a_i||_2 of A (FP64 accumulation) into device `norms` (n doubles).
  * Stream-ordered; does not synchronize.
  */
 int gpspca_column_norms(const gpspca_matrix* A, double* norms, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Solve server: continuous batching of independent solves on one GPU.
+ *
+ * The method solves one problem at a time; a service answers many, on many
+ * matrices.  The server keeps `slots` solves in flight (one HIP stream and one
+ * host worker thread each), admitting a waiting request as soon as a slot and
+ * device memory are free, so requests that arrive while others run overlap on
+ * the device.  All device memory comes from one caller-provided arena (device,
+ * 256-byte aligned, owned by the caller until gpspca_server_destroy returns):
+ * 64 MB of upload staging per slot, the rest shared by resident matrices and
+ * per-request workspaces.  A matrix is uploaded (host to device) on the first
+ * admitted request that needs it and stays resident, with its column norms, for
+ * later requests; when memory is needed, resident matrices that no admitted
+ * request uses are evicted, least recently used first.  Admission is in arrival
+ * order, except that a request that does not fit yet may be passed by later
+ * ones a bounded number of times.  Every result equals what gpspca_solve
+ * returns for the same problem from the default start.
+ * ------------------------------------------------------------------------ */
+typedef struct gpspca_server gpspca_server;
+
+typedef struct gpspca_result {
+    int status;               /* status of the solve (as gpspca_solve) */
+    int n_iter;
+    int m;
+    int uploaded;             /* 1 if this request uploaded its matrix */
+    int64_t p, n;
+    const float* X;           /* host p x m (leading dim p), owned by the server */
+    const float* Z;           /* host n x m */
+    const uint32_t* support;  /* host ceil(n/32) x m words, as gpspca_solve */
+    const double* obj_trace;  /* host n_iter entries */
+    double t_submit, t_admit, t_done;  /* seconds since the server was created */
+} gpspca_result;
+
+typedef struct gpspca_stats {
+    int64_t waiting, running, completed, uploads, evictions;
+    size_t resident_bytes, free_bytes, arena_bytes;
+} gpspca_stats;
+
+/* slots: 1..16 concurrent solves.  arena_bytes >= slots * 64 MB + 64 MB. */
+int gpspca_server_create(void* arena, size_t arena_bytes, int slots, gpspca_server** out);
+/* Register a host FP32 matrix (p x n, column-major, leading dim ld >= p) that the
+ * caller keeps unchanged until it is unregistered; store_dtype GPSPCA_F32 or
+ * GPSPCA_BF16 (quantized on the device at upload, as gpspca_quantize). */
+int gpspca_server_register(gpspca_server* s, const float* host, int64_t p, int64_t n, int64_t ld,
+                           int store_dtype, uint64_t* matrix_id);
+/* Fails while the matrix has pending requests. */
+int gpspca_server_unregister(gpspca_server* s, uint64_t matrix_id);
+/* Queue a solve (arguments as gpspca_solve, default start); returns at once.
+ * GPSPCA_ENOMEM if the request could not fit even in an empty arena. */
+int gpspca_server_submit(gpspca_server* s, uint64_t matrix_id, int form, int m, double gamma,
+                         const double* mu, double tol, int max_iter, uint64_t* request_id);
+/* 0 and *out filled when the request is done, 1 while it is pending, < 0 on
+ * error.  The result's arrays stay valid until gpspca_server_release. */
+int gpspca_server_poll(gpspca_server* s, uint64_t request_id, gpspca_result* out);
+/* Blocks until the request is done, then as gpspca_server_poll. */
+int gpspca_server_wait(gpspca_server* s, uint64_t request_id, gpspca_result* out);
+/* Frees a finished request's host results. */
+int gpspca_server_release(gpspca_server* s, uint64_t request_id);
+int gpspca_server_stats(gpspca_server* s, gpspca_stats* out);
+/* Waits for every submitted request, stops the workers and frees the server
+ * (the arena is the caller's again). */
+int gpspca_server_destroy(gpspca_server* s);
 
 /* Message describing the last non-OK status returned on the calling thread. */
 const char* gpspca_last_error(void);

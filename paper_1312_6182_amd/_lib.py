@@ -50,6 +50,10 @@ SIGNATURES = {
     "gpspca_column_norms": (_I, [_MP, _P, _P]),
     "gpspca_path_workspace_bytes": (_SZ, [_MP, _I, _I]),
     "gpspca_solve_path": (_I, [_MP, _I, _I, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P, _P]),
+    "gpspca_refine": (_I, [_MP, _I, _I, _D, _P, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P]),
+    "gpspca_refine_path": (_I, [_MP, _I, _I, _P, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P,
+                                _P]),
+    "gpspca_quantize": (_I, [_MP, _I, _P, _I64, _P, _P]),
     "gpspca_last_error": (ctypes.c_char_p, []),
     "gpspca_version": (ctypes.c_char_p, []),
     "gpspca_profile_enable": (_I, [_I]),

@@ -161,9 +161,10 @@ def step(A: torch.Tensor, form: int, X: torch.Tensor, gamma: float,
     return StepResult(S=St.t(), G=Gt.t(), f=list(f), nnz=list(nnz))
 
 
-def column_norms(A: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+def column_norms(A: torch.Tensor, stream: Optional[torch.cuda.Stream] = None,
+                 col_scale: Optional[torch.Tensor] = None) -> torch.Tensor:
     lib = L.load()
-    M = matrix(A)
+    M = matrix(A, col_scale)
     out = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
     L.check(lib.gpspca_column_norms(ctypes.byref(M), out.data_ptr(), _stream_ptr(stream)),
             "gpspca_column_norms")
@@ -227,6 +228,92 @@ def solve_path(A: torch.Tensor, form: int, gammas: Sequence[float],
                                ws.data_ptr(), ws.numel(), _stream_ptr(stream), Xt.data_ptr(),
                                Zt.data_ptr(), sup.data_ptr(), tr, nit, sts)
     L.check(rc, "gpspca_solve_path")
+    traces = [list(tr[k * max_iter:k * max_iter + nit[k]]) for k in range(K)]
+    return PathResult(X=Xt.t(), Z=Zt.t(), support=sup, traces=traces, n_iter=list(nit),
+                      status=list(sts), rc=rc)
+
+
+def quantize(A: torch.Tensor, dtype: torch.dtype, stream: Optional[torch.cuda.Stream] = None):
+    """Reduced-precision copy of the FP32 device matrix A (p, n) (gpspca_quantize).
+
+    dtype torch.bfloat16 (round to nearest even, scale 1) or torch.float8_e4m3fn
+    (per-column scale max|a|/448, round to nearest even, saturating).  Returns
+    (Aq, scale): Aq is a (p, n) column-major view with a leading dimension padded
+    to a multiple of 16 elements; scale is an (n,) FP32 tensor (None for bfloat16)."""
+    lib = L.load()
+    if dtype not in (torch.bfloat16, torch.float8_e4m3fn):
+        raise ValueError("dtype must be torch.bfloat16 or torch.float8_e4m3fn")
+    M = matrix(A)
+    p, n = A.shape
+    ldq = (p + 15) // 16 * 16
+    store = torch.zeros((n, ldq), dtype=dtype, device=A.device)
+    scale = torch.empty(n, dtype=torch.float32, device=A.device) \
+        if dtype == torch.float8_e4m3fn else None
+    to = L.BF16 if dtype == torch.bfloat16 else L.F8E4M3
+    L.check(lib.gpspca_quantize(ctypes.byref(M), to, store.data_ptr(), ldq,
+                                None if scale is None else scale.data_ptr(), _stream_ptr(stream)),
+            "gpspca_quantize")
+    return store[:, :p].t(), scale
+
+
+def refine(A: torch.Tensor, form: int, m: int, gamma: float, support: torch.Tensor,
+           X0: torch.Tensor, mu: Optional[Sequence[float]] = None, tol: float = 0.0,
+           max_iter: int = 5, stream: Optional[torch.cuda.Stream] = None) -> SolveResult:
+    """FP32 passes restricted to a frozen support (gpspca_refine): `support` is the
+    (m, ceil(n/32)) int32 word tensor of a previous result, X0 its (p, m) iterate."""
+    lib = L.load()
+    M = matrix(A)
+    p, n = A.shape
+    dev = A.device
+    nb = workspace_bytes(A, form, m, max_iter)
+    ws = _workspace(nb, dev)
+    Xt = torch.empty((m, p), dtype=torch.float32, device=dev)
+    Zt = torch.empty((m, n), dtype=torch.float32, device=dev)
+    sup = torch.empty((m, (n + 31) // 32), dtype=torch.int32, device=dev)
+    sin = support.contiguous()
+    X0c = X0.reshape(p, -1).t().contiguous().to(torch.float32)
+    if sin.shape != (m, (n + 31) // 32) or X0c.shape != (m, p):
+        raise ValueError("support must be (m, ceil(n/32)) words and X0 (p, m)")
+    trace = (ctypes.c_double * max_iter)()
+    nit = ctypes.c_int(0)
+    rc = lib.gpspca_refine(ctypes.byref(M), form, m, float(gamma), _mu_array(mu, m),
+                           sin.data_ptr(), X0c.data_ptr(), float(tol), int(max_iter),
+                           ws.data_ptr(), ws.numel(), _stream_ptr(stream), Xt.data_ptr(),
+                           Zt.data_ptr(), sup.data_ptr(), trace, ctypes.byref(nit))
+    L.check(rc, "gpspca_refine")
+    k = nit.value
+    return SolveResult(X=Xt.t(), Z=Zt.t(), support=sup, trace=list(trace[:k]), n_iter=k,
+                       status=rc)
+
+
+def refine_path(A: torch.Tensor, form: int, gammas: Sequence[float], support: torch.Tensor,
+                X0: torch.Tensor, tol: float = 0.0, max_iter: int = 5,
+                stream: Optional[torch.cuda.Stream] = None) -> PathResult:
+    """gpspca_refine_path: each of the K problems restricted to its own support."""
+    lib = L.load()
+    M = matrix(A)
+    p, n = A.shape
+    K = len(gammas)
+    nb = lib.gpspca_path_workspace_bytes(ctypes.byref(M), K, max_iter)
+    if nb == 0:
+        raise L.GpspcaError(L.EINVAL, L.last_error())
+    ws = _workspace(int(nb), A.device)
+    Xt = torch.empty((K, p), dtype=torch.float32, device=A.device)
+    Zt = torch.empty((K, n), dtype=torch.float32, device=A.device)
+    sup = torch.empty((K, (n + 31) // 32), dtype=torch.int32, device=A.device)
+    sin = support.contiguous()
+    X0c = X0.t().contiguous().to(torch.float32)
+    if sin.shape != (K, (n + 31) // 32) or X0c.shape != (K, p):
+        raise ValueError("support must be (K, ceil(n/32)) words and X0 (p, K)")
+    g = (ctypes.c_double * K)(*[float(v) for v in gammas])
+    tr = (ctypes.c_double * (K * max_iter))()
+    nit = (ctypes.c_int * K)()
+    sts = (ctypes.c_int * K)()
+    rc = lib.gpspca_refine_path(ctypes.byref(M), form, K, g, sin.data_ptr(), X0c.data_ptr(),
+                                float(tol), int(max_iter), ws.data_ptr(), ws.numel(),
+                                _stream_ptr(stream), Xt.data_ptr(), Zt.data_ptr(),
+                                sup.data_ptr(), tr, nit, sts)
+    L.check(rc, "gpspca_refine_path")
     traces = [list(tr[k * max_iter:k * max_iter + nit[k]]) for k in range(K)]
     return PathResult(X=Xt.t(), Z=Zt.t(), support=sup, traces=traces, n_iter=list(nit),
                       status=list(sts), rc=rc)

@@ -16,7 +16,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgpspca.so")
-SOURCES = ["k_pass.hip", "k_corr_mfma.hip", "k_reduce.hip", "k_init_fin.hip", "gpspca_abi.cpp"]
+SCHED_LIB = os.path.join(HERE, "libgpspca_sched.so")
+SOURCES = ["k_pass.hip", "k_corr_mfma.hip", "k_quant.hip", "k_reduce.hip", "k_init_fin.hip",
+           "gpspca_abi.cpp", "serve.cpp"]
 ARCH = "gfx950"
 
 
@@ -59,9 +61,22 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_sched()
     if verbose:
         print("built", LIB)
     return LIB
+
+
+def build_sched() -> str:
+    """Host-only build of the server's scheduler (no HIP), for CPU tests."""
+    tmp = SCHED_LIB + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall",
+           os.path.join(CSRC, "serve_sim.cpp"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed for serve_sim.cpp:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SCHED_LIB)
+    return SCHED_LIB
 
 
 if __name__ == "__main__":

@@ -26,7 +26,7 @@ namespace gpspca {
 
 static thread_local std::string g_err;
 
-static int fail(int code, const std::string& msg) {
+int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
@@ -65,15 +65,30 @@ static int check_matrix(const gpspca_matrix* A) {
     if (A->p < 1 || A->n < 1) return fail(GPSPCA_EINVAL, "p and n must be >= 1");
     if (A->p > (int64_t)1 << 30) return fail(GPSPCA_EINVAL, "p must be <= 2^30");
     if (A->lda < A->p) return fail(GPSPCA_EINVAL, "lda must be >= p");
-    if (A->dtype != GPSPCA_F32) {
-        if (A->dtype == GPSPCA_BF16 || A->dtype == GPSPCA_F8E4M3)
-            return fail(GPSPCA_EDTYPE, "reduced-precision storage is not supported by this entry point");
-        return fail(GPSPCA_EDTYPE, "unknown dtype");
+    if (A->n >= ((int64_t)1 << 31)) return fail(GPSPCA_EINVAL, "n must be < 2^31");
+    switch (A->dtype) {
+        case GPSPCA_F32:
+            if (A->col_scale)
+                return fail(GPSPCA_EINVAL, "col_scale applies to BF16 / F8E4M3 storage only");
+            break;
+        case GPSPCA_BF16:
+        case GPSPCA_F8E4M3: {
+            const int64_t q = A->dtype == GPSPCA_BF16 ? 8 : 16;
+            if (A->lda % q != 0)
+                return fail(GPSPCA_EINVAL, "lda of BF16 (F8E4M3) storage must be a multiple of 8 (16)");
+            if ((reinterpret_cast<uintptr_t>(A->data) & 15) != 0)
+                return fail(GPSPCA_EINVAL, "BF16 / F8E4M3 data must be 16-byte aligned");
+            if (A->dtype == GPSPCA_F8E4M3 && !A->col_scale)
+                return fail(GPSPCA_EINVAL, "F8E4M3 storage needs col_scale");
+            break;
+        }
+        default:
+            return fail(GPSPCA_EDTYPE, "unknown dtype");
     }
     return GPSPCA_OK;
 }
 
-static int check_problem(const gpspca_matrix* A, int form, int m, double gamma, const double* mu) {
+int check_problem(const gpspca_matrix* A, int form, int m, double gamma, const double* mu) {
     int rc = check_matrix(A);
     if (rc) return rc;
     if (form < GPSPCA_SL1 || form > GPSPCA_BL0) return fail(GPSPCA_EINVAL, "unknown formulation");
@@ -92,9 +107,11 @@ static int check_problem(const gpspca_matrix* A, int form, int m, double gamma, 
 
 // ----------------------------------------------------------------------- plan
 static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int ncu, Plan* pl,
-                      int path = 0) {
+                      int path = 0, int restricted = 0) {
     std::memset(pl, 0, sizeof(Plan));
     pl->path = path;
+    pl->restricted = restricted;
+    pl->dtype = A->dtype;
     pl->p = A->p;
     pl->n = A->n;
     pl->lda = A->lda;
@@ -107,8 +124,9 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->ldx = (int)align_up((size_t)A->p + 4, 32);
     pl->vec4 = ((A->lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A->data) & 15) == 0);
     const int64_t nq = cdiv(A->p, 4);
+    const bool f32 = A->dtype == GPSPCA_F32;
 
-    pl->fused_m1 = (m == 1 && A->p <= 20480 && !path) ? 1 : 0;
+    pl->fused_m1 = (m == 1 && A->p <= 20480 && !path && f32 && !restricted) ? 1 : 0;
     if (pl->fused_m1) {
         const int cand[4] = {64, 256, 512, 1024};
         int T = 1024;
@@ -125,17 +143,25 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     } else {
         // correlation kernel: register-resident X for m <= 4, matrix cores otherwise
         // (GPSPCA_CORR_KERNEL=vx|mv|mfma|valu forces one, for tests and benchmarks)
-        const char* force = std::getenv("GPSPCA_CORR_KERNEL");
-        const std::string fk = force ? force : "";
+        const char* force = (f32 && !restricted) ? std::getenv("GPSPCA_CORR_KERNEL") : nullptr;
+        const std::string fk = force ? force : (restricted ? "valu" : "");
         const bool vx_ok = pl->vec4 && m >= 2 && m <= 8 && A->p <= 10240 && A->p >= 4 && !path;
         const bool mv_ok = pl->vec4 && m <= 16 && A->p >= 4;
         if (fk == "vx" && vx_ok) pl->use_vx = 1;
         else if (fk == "mv" && mv_ok) pl->use_mv = 1;
         else if (fk == "mfma" && pl->vec4) pl->use_mfma = 1;
         else if (fk == "valu") {}
+        else if (!f32) pl->use_q = 1;
         else if (vx_ok && m <= 4) pl->use_vx = 1;
         else pl->use_mfma = pl->vec4;
-        if (pl->use_vx) {
+        if (pl->use_q) {
+            // 16/8-bit storage: bfloat16 matrix cores, one wavefront per workgroup
+            pl->corr_M = 16;
+            const int per_cu = corr_q_blocks_per_cu(A->dtype, m);
+            int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, cdiv(A->n, 16));
+            pl->corr_grid = (int)std::max<int64_t>(1, grid);
+            pl->nwave_part = pl->corr_grid;
+        } else if (pl->use_vx) {
             // X rows in registers: one workgroup per CU (512 threads) or two (256)
             pl->corr_M = m <= 2 ? 2 : m <= 4 ? 4 : 8;
             pl->vx_threads = (cdiv(nq, 256) <= 5) ? 256 : 512;
@@ -209,6 +235,7 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->o_invn = take(sizeof(double) * M);
     pl->o_fcomp = take(sizeof(double) * 2 * M);
     pl->o_pstate = take(path ? sizeof(PathState) * M : 1);
+    pl->o_list = take(sizeof(int) * (N + 64));  // frozen-support column list + its count
     pl->total = o;
 }
 
@@ -234,6 +261,8 @@ struct Ptrs {
     double* invn;
     double* fcomp;
     PathState* pstate;
+    int* list;
+    int* nlist;
 };
 
 static Ptrs carve(const Plan& pl, void* ws) {
@@ -261,6 +290,8 @@ static Ptrs carve(const Plan& pl, void* ws) {
     P.invn = reinterpret_cast<double*>(b + pl.o_invn);
     P.fcomp = reinterpret_cast<double*>(b + pl.o_fcomp);
     P.pstate = reinterpret_cast<PathState*>(b + pl.o_pstate);
+    P.list = reinterpret_cast<int*>(b + pl.o_list);
+    P.nlist = P.list + pl.n;
     return P;
 }
 
@@ -268,7 +299,9 @@ static PassParams make_params(const gpspca_matrix* A, const Plan& pl, double gam
                               const double* mu, const double* gammas = nullptr) {
     PassParams pp;
     std::memset(&pp, 0, sizeof(pp));
-    pp.A = static_cast<const float*>(A->data);
+    if (A->dtype == GPSPCA_BF16) pp.Abf = static_cast<const uint16_t*>(A->data);
+    else if (A->dtype == GPSPCA_F8E4M3) pp.Af8 = static_cast<const uint8_t*>(A->data);
+    else pp.A = static_cast<const float*>(A->data);
     pp.scale = A->col_scale;
     pp.lda = A->lda;
     pp.n = A->n;
@@ -349,6 +382,8 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
             GPSPCA_HIP(launch_corr_vx(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         else if (pl.use_mv)
             GPSPCA_HIP(launch_corr_mv(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+        else if (pl.use_q)
+            GPSPCA_HIP(launch_corr_q(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         else if (pl.use_mfma)
             GPSPCA_HIP(launch_corr_mfma(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         else
@@ -426,6 +461,7 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
     tl.collect(pl.fused_m1 ? "k_pass_m1"
                            : pl.use_vx ? "k_corr_vx"
                            : pl.use_mv ? "k_corr_mv"
+                           : pl.use_q ? "k_corr_q"
                            : pl.use_mfma ? "k_corr_mfma" : "k_corr");
     *fin = *snap;
     return GPSPCA_OK;
@@ -437,6 +473,144 @@ static const char* status_text(int s) {
         case GPSPCA_ENONFINITE: return "objective or ascent direction became non-finite";
         default: return "device error";
     }
+}
+
+
+// One driver for every iteration entry point.
+//  path = 0: one problem (form, m, gamma, mu); path = 1: m independent
+//  single-unit problems with their own gammas[j] (a gamma path).
+//  mask != nullptr: frozen-support passes (X0 required): only the columns with
+//  a support bit are read and s_ij = 0 wherever bit (i, j) is clear.
+//  norms_in != nullptr: device column norms of A for the default start (the
+//  server caches them with a resident matrix).
+int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
+               const double* gammas, int path, const uint32_t* mask, const float* X0,
+               double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
+               float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
+               int* status_out, const double* norms_in) {
+    int ncu = 0;
+    int rc = device_cus(&ncu);
+    if (rc) return rc;
+    const int pform = path ? (form == GPSPCA_SL0 ? GPSPCA_BL0 : GPSPCA_BL1) : form;
+    Plan pl;
+    make_plan(A, pform, m, max_iter, ncu, &pl, path, mask ? 1 : 0);
+    if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
+    const Ptrs P = carve(pl, workspace);
+    PassParams pp = make_params(A, pl, gamma, mu, gammas);
+    const int64_t words = cdiv(A->n, 32);
+
+    GPSPCA_HIP(launch_ctrl_reset(P.ctrl, max_iter, tol, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad, st));
+    if (path) GPSPCA_HIP(launch_fill_zero(P.pstate, sizeof(PathState) * m, st));
+    if (mask) {
+        GPSPCA_HIP(launch_fill_zero(P.S, sizeof(float) * (size_t)A->n * m, st));
+        GPSPCA_HIP(launch_fill_zero(P.act, align_up((size_t)A->n, 4), st));
+        GPSPCA_HIP(launch_mask_list(mask, words, m, A->n, P.list, P.nlist, st));
+        pp.list = P.list;
+        pp.nlist = P.nlist;
+        pp.mask = mask;
+        pp.mask_words = words;
+    }
+
+    // start: project X0 (or the default start) onto the feasible set
+    if (X0) {
+        GPSPCA_HIP(launch_load_g64(pl, X0, (int)A->p, P.g64, st));
+        if (path) {
+            // every column normalized on its own
+            GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 2, P.g64, P.gram, P.ctrl, st));
+            GPSPCA_HIP(launch_project_diag(pl, P.gram, P.coef, P.ctrl, st));
+        } else {
+            GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
+            GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
+        }
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+    } else if (path) {
+        // all columns start at the normalized column of largest norm
+        Plan p1;
+        make_plan(A, GPSPCA_SL1, 1, 1, ncu, &p1);
+        p1.ldx = pl.ldx;
+        p1.gram_grid = pl.gram_grid;
+        p1.gram_rows = pl.gram_rows;
+        p1.topm_grid = pl.topm_grid;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
+        if (!norms_in) GPSPCA_HIP(launch_colnorm(pp, A->dtype, P.norms, grid, st));
+        GPSPCA_HIP(launch_topm(p1, norms_in ? norms_in : P.norms, P.cand_v, P.cand_i, P.idx, st));
+        PassParams pp1 = pp;
+        pp1.m = 1;
+        GPSPCA_HIP(launch_gather(p1, pp1, P.idx, P.g64, st));
+        GPSPCA_HIP(launch_gram(p1, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
+        GPSPCA_HIP(launch_project(p1, P.gram, P.coef, P.ctrl, st));
+        GPSPCA_HIP(launch_apply(p1, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+        GPSPCA_HIP(launch_bcast_col0(pl, P.x[0], st));
+    } else {
+        // the m columns of largest norm (ties to the lower index)
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
+        if (!norms_in) GPSPCA_HIP(launch_colnorm(pp, A->dtype, P.norms, grid, st));
+        GPSPCA_HIP(launch_topm(pl, norms_in ? norms_in : P.norms, P.cand_v, P.cand_i, P.idx, st));
+        GPSPCA_HIP(launch_gather(pl, pp, P.idx, P.g64, st));
+        GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
+        GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+    }
+
+    Ctrl fin;
+    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin);
+    if (rc) return rc;
+    if (fin.status < 0) return fail(fin.status, status_text(fin.status));
+    if (fin.n_iter < 1) return fail(GPSPCA_EDEVICE, "solve ended without a pass");
+
+    const float* Xf = P.x[(fin.n_iter - 1) & 1];
+    GPSPCA_HIP(launch_copy_x(pl, Xf, X, st));
+    GPSPCA_HIP(launch_finalize(pl, P.S, P.fin, P.invn, Z, support, st));
+    std::vector<PathState> ps(path ? m : 0);
+    if (path)
+        GPSPCA_HIP(hipMemcpyAsync(ps.data(), P.pstate, sizeof(PathState) * m,
+                                  hipMemcpyDeviceToHost, st));
+    if (obj_trace) {
+        const size_t cnt = path ? (size_t)m * max_iter : (size_t)fin.n_iter;
+        GPSPCA_HIP(hipMemcpyAsync(obj_trace, P.trace, sizeof(double) * cnt,
+                                  hipMemcpyDeviceToHost, st));
+    }
+    GPSPCA_HIP(hipStreamSynchronize(st));
+    if (!path) {
+        if (n_iter) *n_iter = fin.n_iter;
+        if (fin.status != GPSPCA_OK)
+            g_err = fin.status == GPSPCA_MAXITER ? "stopped at max_iter" : "degenerate components";
+        return fin.status;
+    }
+    int worst = GPSPCA_OK;
+    for (int j = 0; j < m; ++j) {
+        if (n_iter) n_iter[j] = ps[j].n_iter;
+        if (status_out) status_out[j] = ps[j].status;
+        if (ps[j].status < 0) worst = ps[j].status;
+        else if (worst >= 0 && ps[j].status > worst) worst = ps[j].status;
+    }
+    if (worst < 0) return fail(worst, status_text(worst));
+    return worst;
+}
+
+static int check_run(double tol, int max_iter, const float* X, const void* workspace) {
+    if (!std::isfinite(tol) || tol < 0.0) return fail(GPSPCA_EINVAL, "tol must be finite and >= 0");
+    if (max_iter < 1) return fail(GPSPCA_EINVAL, "max_iter must be >= 1");
+    if (!X) return fail(GPSPCA_EINVAL, "X is NULL");
+    if (!workspace) return fail(GPSPCA_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(GPSPCA_EINVAL, "workspace must be 256-byte aligned");
+    return GPSPCA_OK;
+}
+
+static int check_path(const gpspca_matrix* A, int form, int K, const double* gammas) {
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    if (form != GPSPCA_SL1 && form != GPSPCA_SL0)
+        return fail(GPSPCA_EINVAL, "a gamma path takes a single-unit formulation");
+    if (K < 1 || K > kMaxM) return fail(GPSPCA_EINVAL, "need 1 <= K <= GPSPCA_MAX_M");
+    if (!gammas) return fail(GPSPCA_EINVAL, "gammas is NULL");
+    for (int j = 0; j < K; ++j)
+        if (!std::isfinite(gammas[j]) || gammas[j] < 0.0)
+            return fail(GPSPCA_EINVAL, "gammas must be finite and >= 0");
+    return GPSPCA_OK;
 }
 
 }  // namespace gpspca
@@ -459,7 +633,10 @@ size_t gpspca_workspace_bytes(const gpspca_matrix* A, int form, int m, int max_i
     if (device_cus(&ncu) != GPSPCA_OK) return 0;
     Plan pl;
     make_plan(A, form, m, max_iter, ncu, &pl);
-    return pl.total;
+    if (A->dtype != GPSPCA_F32) return pl.total;
+    Plan pr;  // frozen-support passes (gpspca_refine) on the same matrix
+    make_plan(A, form, m, max_iter, ncu, &pr, 0, 1);
+    return std::max(pl.total, pr.total);
 }
 
 int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
@@ -468,58 +645,28 @@ int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const do
                  int* n_iter) {
     int rc = check_problem(A, form, m, gamma, mu);
     if (rc) return rc;
-    if (!std::isfinite(tol) || tol < 0.0) return fail(GPSPCA_EINVAL, "tol must be finite and >= 0");
-    if (max_iter < 1) return fail(GPSPCA_EINVAL, "max_iter must be >= 1");
-    if (!X) return fail(GPSPCA_EINVAL, "X is NULL");
-    if (!workspace) return fail(GPSPCA_EINVAL, "workspace is NULL");
-    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
-        return fail(GPSPCA_EINVAL, "workspace must be 256-byte aligned");
+    rc = check_run(tol, max_iter, X, workspace);
+    if (rc) return rc;
     if (!X0 && m > A->n) return fail(GPSPCA_EINVAL, "default start needs m <= n");
+    return solve_core(A, form, m, gamma, mu, nullptr, 0, nullptr, X0, tol, max_iter, workspace,
+                      ws_bytes, static_cast<hipStream_t>(stream), X, Z, support, obj_trace,
+                      n_iter, nullptr, nullptr);
+}
 
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int ncu = 0;
-    rc = device_cus(&ncu);
+int gpspca_refine(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
+                  const uint32_t* support_in, const float* X0, double tol, int max_iter,
+                  void* workspace, size_t ws_bytes, void* stream, float* X, float* Z,
+                  uint32_t* support, double* obj_trace, int* n_iter) {
+    int rc = check_problem(A, form, m, gamma, mu);
     if (rc) return rc;
-    Plan pl;
-    make_plan(A, form, m, max_iter, ncu, &pl);
-    if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
-    const Ptrs P = carve(pl, workspace);
-    const PassParams pp = make_params(A, pl, gamma, mu);
-
-    // start: project X0 (or the top-m norm columns) onto the feasible set
-    GPSPCA_HIP(launch_ctrl_reset(P.ctrl, max_iter, tol, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad, st));
-    if (X0) {
-        GPSPCA_HIP(launch_load_g64(pl, X0, (int)A->p, P.g64, st));
-    } else {
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
-        GPSPCA_HIP(launch_colnorm(pp, P.norms, grid, st));
-        GPSPCA_HIP(launch_topm(pl, P.norms, P.cand_v, P.cand_i, P.idx, st));
-        GPSPCA_HIP(launch_gather(pl, pp, P.idx, P.g64, st));
-    }
-    GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
-    GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
-    GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
-
-    Ctrl fin;
-    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin);
+    if (A->dtype != GPSPCA_F32) return fail(GPSPCA_EDTYPE, "refinement runs on FP32 storage");
+    rc = check_run(tol, max_iter, X, workspace);
     if (rc) return rc;
-    if (fin.status < 0) return fail(fin.status, status_text(fin.status));
-    if (fin.n_iter < 1) return fail(GPSPCA_EDEVICE, "solve ended without a pass");
-
-    const float* Xf = P.x[(fin.n_iter - 1) & 1];
-    GPSPCA_HIP(launch_copy_x(pl, Xf, X, st));
-    GPSPCA_HIP(launch_finalize(pl, P.S, P.fin, P.invn, Z, support, st));
-    if (obj_trace)
-        GPSPCA_HIP(hipMemcpyAsync(obj_trace, P.trace, sizeof(double) * fin.n_iter,
-                                  hipMemcpyDeviceToHost, st));
-    GPSPCA_HIP(hipStreamSynchronize(st));
-    if (n_iter) *n_iter = fin.n_iter;
-    if (fin.status != GPSPCA_OK) {
-        g_err = fin.status == GPSPCA_MAXITER ? "stopped at max_iter" : "degenerate components";
-    }
-    return fin.status;
+    if (!support_in) return fail(GPSPCA_EINVAL, "support is NULL");
+    if (!X0) return fail(GPSPCA_EINVAL, "refinement needs X0");
+    return solve_core(A, form, m, gamma, mu, nullptr, 0, support_in, X0, tol, max_iter,
+                      workspace, ws_bytes, static_cast<hipStream_t>(stream), X, Z, support,
+                      obj_trace, n_iter, nullptr, nullptr);
 }
 
 int gpspca_step(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
@@ -579,91 +726,54 @@ size_t gpspca_path_workspace_bytes(const gpspca_matrix* A, int K, int max_iter) 
     if (device_cus(&ncu) != GPSPCA_OK) return 0;
     Plan pl;
     make_plan(A, GPSPCA_BL1, K, max_iter, ncu, &pl, 1);
-    return pl.total;
+    Plan pr;
+    make_plan(A, GPSPCA_BL1, K, max_iter, ncu, &pr, 1, 1);
+    return std::max(pl.total, pr.total);
 }
 
 int gpspca_solve_path(const gpspca_matrix* A, int form, int K, const double* gammas,
                       const float* X0, double tol, int max_iter, void* workspace,
                       size_t ws_bytes, void* stream, float* X, float* Z, uint32_t* support,
                       double* obj_trace, int* n_iter, int* status) {
+    int rc = check_path(A, form, K, gammas);
+    if (rc) return rc;
+    rc = check_run(tol, max_iter, X, workspace);
+    if (rc) return rc;
+    return solve_core(A, form, K, 0.0, nullptr, gammas, 1, nullptr, X0, tol, max_iter, workspace,
+                      ws_bytes, static_cast<hipStream_t>(stream), X, Z, support, obj_trace,
+                      n_iter, status, nullptr);
+}
+
+int gpspca_refine_path(const gpspca_matrix* A, int form, int K, const double* gammas,
+                       const uint32_t* support_in, const float* X0, double tol, int max_iter,
+                       void* workspace, size_t ws_bytes, void* stream, float* X, float* Z,
+                       uint32_t* support, double* obj_trace, int* n_iter, int* status) {
+    int rc = check_path(A, form, K, gammas);
+    if (rc) return rc;
+    if (A->dtype != GPSPCA_F32) return fail(GPSPCA_EDTYPE, "refinement runs on FP32 storage");
+    rc = check_run(tol, max_iter, X, workspace);
+    if (rc) return rc;
+    if (!support_in) return fail(GPSPCA_EINVAL, "support is NULL");
+    if (!X0) return fail(GPSPCA_EINVAL, "refinement needs X0");
+    return solve_core(A, form, K, 0.0, nullptr, gammas, 1, support_in, X0, tol, max_iter,
+                      workspace, ws_bytes, static_cast<hipStream_t>(stream), X, Z, support,
+                      obj_trace, n_iter, status, nullptr);
+}
+
+int gpspca_quantize(const gpspca_matrix* A, int to, void* out, int64_t ldq, float* col_scale,
+                    void* stream) {
     int rc = check_matrix(A);
     if (rc) return rc;
-    if (form != GPSPCA_SL1 && form != GPSPCA_SL0)
-        return fail(GPSPCA_EINVAL, "a gamma path takes a single-unit formulation");
-    if (K < 1 || K > kMaxM) return fail(GPSPCA_EINVAL, "need 1 <= K <= GPSPCA_MAX_M");
-    if (!gammas) return fail(GPSPCA_EINVAL, "gammas is NULL");
-    for (int j = 0; j < K; ++j)
-        if (!std::isfinite(gammas[j]) || gammas[j] < 0.0)
-            return fail(GPSPCA_EINVAL, "gammas must be finite and >= 0");
-    if (!std::isfinite(tol) || tol < 0.0) return fail(GPSPCA_EINVAL, "tol must be finite and >= 0");
-    if (max_iter < 1) return fail(GPSPCA_EINVAL, "max_iter must be >= 1");
-    if (!X) return fail(GPSPCA_EINVAL, "X is NULL");
-    if (!workspace) return fail(GPSPCA_EINVAL, "workspace is NULL");
-    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
-        return fail(GPSPCA_EINVAL, "workspace must be 256-byte aligned");
-
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int ncu = 0;
-    rc = device_cus(&ncu);
-    if (rc) return rc;
-    Plan pl;
-    make_plan(A, form == GPSPCA_SL0 ? GPSPCA_BL0 : GPSPCA_BL1, K, max_iter, ncu, &pl, 1);
-    if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
-    const Ptrs P = carve(pl, workspace);
-    const PassParams pp = make_params(A, pl, 0.0, nullptr, gammas);
-
-    GPSPCA_HIP(launch_ctrl_reset(P.ctrl, max_iter, tol, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad, st));
-    GPSPCA_HIP(launch_fill_zero(P.pstate, sizeof(PathState) * K, st));
-    if (X0) {
-        // every column normalized on its own
-        GPSPCA_HIP(launch_load_g64(pl, X0, (int)A->p, P.g64, st));
-        GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 2, P.g64, P.gram, P.ctrl, st));
-        GPSPCA_HIP(launch_project_diag(pl, P.gram, P.coef, P.ctrl, st));
-        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
-    } else {
-        // all columns start at the normalized column of largest norm
-        Plan p1;
-        make_plan(A, GPSPCA_SL1, 1, 1, ncu, &p1);
-        p1.ldx = pl.ldx;
-        p1.gram_grid = pl.gram_grid;
-        p1.gram_rows = pl.gram_rows;
-        p1.topm_grid = pl.topm_grid;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
-        GPSPCA_HIP(launch_colnorm(pp, P.norms, grid, st));
-        GPSPCA_HIP(launch_topm(p1, P.norms, P.cand_v, P.cand_i, P.idx, st));
-        PassParams pp1 = pp;
-        pp1.m = 1;
-        GPSPCA_HIP(launch_gather(p1, pp1, P.idx, P.g64, st));
-        GPSPCA_HIP(launch_gram(p1, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
-        GPSPCA_HIP(launch_project(p1, P.gram, P.coef, P.ctrl, st));
-        GPSPCA_HIP(launch_apply(p1, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
-        GPSPCA_HIP(launch_bcast_col0(pl, P.x[0], st));
-    }
-    Ctrl fin;
-    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin);
-    if (rc) return rc;
-    if (fin.status < 0) return fail(fin.status, status_text(fin.status));
-    if (fin.n_iter < 1) return fail(GPSPCA_EDEVICE, "solve ended without a pass");
-    std::vector<PathState> ps(K);
-    const float* Xf = P.x[(fin.n_iter - 1) & 1];
-    GPSPCA_HIP(launch_copy_x(pl, Xf, X, st));
-    GPSPCA_HIP(launch_finalize(pl, P.S, P.fin, P.invn, Z, support, st));
-    GPSPCA_HIP(hipMemcpyAsync(ps.data(), P.pstate, sizeof(PathState) * K, hipMemcpyDeviceToHost, st));
-    if (obj_trace)
-        GPSPCA_HIP(hipMemcpyAsync(obj_trace, P.trace, sizeof(double) * K * max_iter,
-                                  hipMemcpyDeviceToHost, st));
-    GPSPCA_HIP(hipStreamSynchronize(st));
-    int worst = GPSPCA_OK;
-    for (int j = 0; j < K; ++j) {
-        if (n_iter) n_iter[j] = ps[j].n_iter;
-        if (status) status[j] = ps[j].status;
-        if (ps[j].status < 0) worst = ps[j].status;
-        else if (worst >= 0 && ps[j].status > worst) worst = ps[j].status;
-    }
-    if (worst < 0) return fail(worst, status_text(worst));
-    return worst;
+    if (A->dtype != GPSPCA_F32) return fail(GPSPCA_EDTYPE, "quantize takes an FP32 matrix");
+    if (to != GPSPCA_BF16 && to != GPSPCA_F8E4M3)
+        return fail(GPSPCA_EDTYPE, "quantize targets BF16 or F8E4M3");
+    if (!out) return fail(GPSPCA_EINVAL, "out is NULL");
+    if (ldq < A->p) return fail(GPSPCA_EINVAL, "ldq must be >= p");
+    if (to == GPSPCA_F8E4M3 && !col_scale)
+        return fail(GPSPCA_EINVAL, "F8E4M3 needs col_scale");
+    GPSPCA_HIP(launch_quantize(static_cast<const float*>(A->data), A->lda, (int)A->p, A->n, to,
+                               out, ldq, col_scale, static_cast<hipStream_t>(stream)));
+    return GPSPCA_OK;
 }
 
 int gpspca_column_norms(const gpspca_matrix* A, double* norms, void* stream) {
@@ -677,7 +787,7 @@ int gpspca_column_norms(const gpspca_matrix* A, double* norms, void* stream) {
     make_plan(A, GPSPCA_SL1, 1, 1, ncu, &pl);
     const PassParams pp = make_params(A, pl, 0.0, nullptr);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
-    GPSPCA_HIP(launch_colnorm(pp, norms, grid, static_cast<hipStream_t>(stream)));
+    GPSPCA_HIP(launch_colnorm(pp, A->dtype, norms, grid, static_cast<hipStream_t>(stream)));
     return GPSPCA_OK;
 }
 

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/gpspca.h"
 
 namespace gpspca {
@@ -43,6 +45,12 @@ struct PassParams {
     float muf[kMaxM];      // mu_j in FP32 (for the back-projection weights)
     double mu[kMaxM];      // mu_j in FP64 (for the threshold)
     double gam[kMaxM];     // gamma of component j (all equal, except on a gamma path)
+    // frozen-support passes (refinement): only the columns list[0 .. *nlist-1]
+    // are visited, and s_ij = 0 wherever bit (i, j) of mask is clear
+    const int* list;       // ascending column indices, or nullptr (all columns)
+    const int* nlist;      // device count of list entries
+    const uint32_t* mask;  // mask[j * mask_words + i / 32] bit i % 32, or nullptr
+    int64_t mask_words;
 };
 
 // Layout of the caller's workspace for one solve (byte offsets).
@@ -66,6 +74,9 @@ struct Plan {
     int fin_grid;
     int topm_grid;
     int vec4;              // float4 loads of A are legal
+    int dtype;             // storage of A (GPSPCA_F32 | BF16 | F8E4M3)
+    int use_q;             // 16/8-bit storage: bfloat16 matrix-core correlation
+    int restricted;        // frozen-support passes over a column list (VALU correlation)
     int use_mfma;          // block correlation on the matrix cores (LDS DMA staging)
     int mfma_stages;       // stages in flight of the matrix-core kernel
     int use_vx;            // block correlation with X held in registers (m <= 8, p <= 10240)
@@ -75,7 +86,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
         o_l1, o_g64, o_gram, o_coef, o_norms, o_cand_v, o_cand_i, o_idx, o_fin, o_invn, o_fcomp,
-        o_pstate;
+        o_pstate, o_list;
     size_t total;
 };
 
@@ -101,7 +112,17 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
 hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
                            const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                            hipStream_t st);
-hipError_t launch_colnorm(const PassParams& pp, double* norms, int grid, hipStream_t st);
+hipError_t launch_colnorm(const PassParams& pp, int dtype, double* norms, int grid,
+                          hipStream_t st);
+hipError_t launch_mask_list(const uint32_t* mask, int64_t words, int m, int64_t n, int* list,
+                            int* nlist, hipStream_t st);
+// reduced-precision storage (k_quant.hip)
+hipError_t launch_quantize(const float* A, int64_t lda, int p, int64_t n, int to, void* out,
+                           int64_t ldq, float* scale, hipStream_t st);
+int corr_q_blocks_per_cu(int dtype, int m);
+hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                         uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                         hipStream_t st);
 
 // reductions, retraction, stop test (k_reduce.hip)
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t st);
@@ -152,5 +173,14 @@ hipError_t launch_copy_x(const Plan& pl, const float* Xint, float* Xout, hipStre
 // Offsets of the coefficient block (doubles) written by the stop / projection kernels.
 inline size_t coef_omega(int m) { return 0; }
 inline size_t coef_psi(int m) { return (size_t)m * m; }
+
+// ---- host driver (gpspca_abi.cpp), shared with the server (serve.cpp) ----
+int fail(int code, const std::string& msg);
+int check_problem(const gpspca_matrix* A, int form, int m, double gamma, const double* mu);
+int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
+               const double* gammas, int path, const uint32_t* mask, const float* X0,
+               double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
+               float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
+               int* status_out, const double* norms_in);
 
 }  // namespace gpspca

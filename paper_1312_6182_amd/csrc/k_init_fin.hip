@@ -9,6 +9,7 @@
 // zero), the support as packed bit words, and X copied out of the internal
 // padded buffer.
 #include "gpspca_internal.h"
+#include "storage.h"
 
 namespace gpspca {
 
@@ -91,20 +92,28 @@ hipError_t launch_topm(const Plan& pl, const double* norms, double* cand_v, int6
     return hipGetLastError();
 }
 
-// g64[j*p + r] = A[r, idx[j]] in FP64.
-__global__ void k_gather(PassParams pp, const int64_t* __restrict__ idx, double* __restrict__ g64) {
+// g64[j*p + r] = A[r, idx[j]] in FP64 (dequantized and scaled for 16/8-bit storage).
+__global__ void k_gather(PassParams pp, int dtype, const int64_t* __restrict__ idx,
+                         double* __restrict__ g64) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)pp.m * pp.p) return;
     const int j = (int)(e / pp.p), r = (int)(e % pp.p);
     const int64_t c = idx[j];
-    g64[e] = (double)pp.A[c * pp.lda + r];
+    double v;
+    if (dtype == GPSPCA_BF16)
+        v = (double)bf16_value(pp.Abf[c * pp.lda + r]) * (double)column_scale(pp, c);
+    else if (dtype == GPSPCA_F8E4M3)
+        v = (double)e4m3_value(pp.Af8[c * pp.lda + r]) * (double)column_scale(pp, c);
+    else
+        v = (double)pp.A[c * pp.lda + r];
+    g64[e] = v;
 }
 
 hipError_t launch_gather(const Plan& pl, const PassParams& pp, const int64_t* idx, double* g64,
                          hipStream_t st) {
     const int64_t ne = (int64_t)pl.m * pl.p;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pp, idx,
-                       g64);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pp,
+                       pl.dtype, idx, g64);
     return hipGetLastError();
 }
 
@@ -187,6 +196,64 @@ hipError_t launch_copy_x(const Plan& pl, const float* Xint, float* Xout, hipStre
     const int64_t ne = (int64_t)pl.m * pl.p;
     hipLaunchKernelGGL(k_copy_x, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pl.m,
                        (int)pl.p, pl.ldx, Xint, Xout);
+    return hipGetLastError();
+}
+
+}  // namespace gpspca
+
+namespace gpspca {
+
+// Ascending list of the columns whose support bit is set for at least one
+// component (the columns a frozen-support pass has to read).  One workgroup;
+// each thread owns one 32-column word per round, and a workgroup prefix sum of
+// the word populations places the thread's columns.
+__global__ __launch_bounds__(1024) void k_mask_list(const uint32_t* __restrict__ mask,
+                                                    int64_t words, int m, int64_t n,
+                                                    int* __restrict__ list,
+                                                    int* __restrict__ nlist) {
+    __shared__ int wave_tot[16];
+    __shared__ int base_s;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) base_s = 0;
+    __syncthreads();
+    for (int64_t w0 = 0; w0 < words; w0 += 1024) {
+        const int64_t wi = w0 + t;
+        uint32_t u = 0;
+        if (wi < words) {
+            for (int j = 0; j < m; ++j) u |= mask[(int64_t)j * words + wi];
+            if (wi == words - 1 && (n & 31)) u &= (1u << (n & 31)) - 1u;
+        }
+        const int c = __popc(u);
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) wave_tot[wv] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < 16; ++w) {
+            const int v = wave_tot[w];
+            if (w < wv) before += v;
+            total += v;
+        }
+        int pos = base_s + before + incl - c;
+        while (u) {
+            const int b = __ffs(u) - 1;
+            list[pos++] = (int)(wi * 32 + b);
+            u &= u - 1u;
+        }
+        __syncthreads();
+        if (t == 0) base_s += total;
+        __syncthreads();
+    }
+    if (t == 0) *nlist = base_s;
+}
+
+hipError_t launch_mask_list(const uint32_t* mask, int64_t words, int m, int64_t n, int* list,
+                            int* nlist, hipStream_t st) {
+    hipLaunchKernelGGL(k_mask_list, dim3(1), dim3(1024), 0, st, mask, words, m, n, list, nlist);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@
 //              second pass; workgroups own a (row block, column range) tile.
 //  k_colnorm   ||a_i|| in FP64 (default start).
 #include "gpspca_internal.h"
+#include "storage.h"
 
 namespace gpspca {
 
@@ -283,7 +284,9 @@ __global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * 4;
-    const int64_t cb = pp.n * wave / nw, ce = pp.n * (wave + 1) / nw;
+    // columns visited: all n, or the frozen-support list
+    const int64_t nv = pp.list ? (int64_t)*pp.nlist : pp.n;
+    const int64_t cb = nv * wave / nw, ce = nv * (wave + 1) / nw;
     const int p = pp.p, nqf = p >> 2;
     const int m = pp.m;
     const int mg = (m - j0 < M) ? m - j0 : M;  // real components in this launch
@@ -305,7 +308,8 @@ __global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float
         const float* colp[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int64_t c = (c0 + b < ce) ? c0 + b : ce - 1;
+            const int64_t v = (c0 + b < ce) ? c0 + b : ce - 1;
+            const int64_t c = pp.list ? (int64_t)pp.list[v] : v;
             colp[b] = pp.A + c * pp.lda;
         }
         float acc[V];
@@ -340,13 +344,17 @@ __global__ __launch_bounds__(256) void k_corr(PassParams pp, int j0, const float
         }
         butterfly<32, V, V>(acc, lane);
         const float y = acc[0];
-        const int64_t col = c0 + ob;
-        const bool valid = rep && (col < ce) && (oj < mg);
+        const bool valid = rep && (c0 + ob < ce) && (oj < mg);
+        const int64_t col = !valid ? 0 : pp.list ? (int64_t)pp.list[c0 + ob] : c0 + ob;
         bool active = false;
         if (valid) {
             float s;
             double fv;
             active = threshold(l0, muj, pp.gam[j0 + oj], y, s, fv);
+            if (pp.mask && !((pp.mask[(int64_t)(j0 + oj) * pp.mask_words + (col >> 5)] >> (col & 31)) & 1u)) {
+                active = false;
+                s = 0.f;
+            }
             S[col * m + j0 + oj] = s;
             if (active) {
                 f_acc += fv;
@@ -494,7 +502,7 @@ __global__ __launch_bounds__(T) void k_corr_vx(PassParams pp, const float* __res
 //   grid (row blocks, column ranges); 256 threads, thread t owns quads
 //   qbase + t + 256 k (k < KQ2) of the row block; U active columns per step.
 // ---------------------------------------------------------------------------
-template <int M, int KQ2, bool VEC>
+template <int M, int KQ2, bool VEC, int ST>
 __global__ __launch_bounds__(256) void k_backproj(PassParams pp, int j0,
                                                   const float* __restrict__ S,
                                                   const uint8_t* __restrict__ act,
@@ -537,14 +545,19 @@ __global__ __launch_bounds__(256) void k_backproj(PassParams pp, int j0,
             for (int u = 0; u < U; ++u) {
                 const int li = (e + u < total) ? list[e + u] : list[e];
                 const int64_t col = base + li;
-                const float* colp = pp.A + col * pp.lda;
+                const void* colv = column_ptr<ST>(pp, col);
+                const float sc = (ST == kStF32) ? 1.0f : column_scale(pp, col);
 #pragma unroll
                 for (int j = 0; j < M; ++j)
-                    w[u][j] = (j < mg) ? pp.muf[j0 + j] * S[col * m + j0 + j] : 0.f;
+                    w[u][j] = (j < mg) ? pp.muf[j0 + j] * S[col * m + j0 + j] * sc : 0.f;
 #pragma unroll
                 for (int k = 0; k < KQ2; ++k) {
                     const int q = qbase + t + 256 * k;
-                    a[u][k] = (q < nq) ? load_quad<VEC>(colp, q, nqf, p) : zero4();
+                    if constexpr (ST == kStF32)
+                        a[u][k] = (q < nq) ? load_quad<VEC>(static_cast<const float*>(colv), q, nqf, p)
+                                           : zero4();
+                    else
+                        a[u][k] = (q < nq) ? load_quad_st<ST>(colv, q, nqf, p) : zero4();
                 }
             }
 #pragma unroll
@@ -585,7 +598,7 @@ __global__ __launch_bounds__(256) void k_backproj(PassParams pp, int j0,
 // k_colnorm: ||a_i||_2 with FP64 accumulation; one wavefront per column range,
 // four columns in flight.
 // ---------------------------------------------------------------------------
-template <bool VEC>
+template <bool VEC, int ST>
 __global__ __launch_bounds__(256) void k_colnorm(PassParams pp, double* __restrict__ norms) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -595,17 +608,21 @@ __global__ __launch_bounds__(256) void k_colnorm(PassParams pp, double* __restri
     constexpr int C = 4;
     for (int64_t c0 = cb; c0 < ce; c0 += C) {
         double s[C];
-        const float* colp[C];
+        const void* colp[C];
 #pragma unroll
         for (int b = 0; b < C; ++b) {
             s[b] = 0.0;
             const int64_t c = (c0 + b < ce) ? c0 + b : ce - 1;
-            colp[b] = pp.A + c * pp.lda;
+            colp[b] = column_ptr<ST>(pp, c);
         }
         for (int q = lane; q < nq; q += 64) {
 #pragma unroll
             for (int b = 0; b < C; ++b) {
-                const f4 a = load_quad<VEC>(colp[b], q, nqf, p);
+                f4 a;
+                if constexpr (ST == kStF32)
+                    a = load_quad<VEC>(static_cast<const float*>(colp[b]), q, nqf, p);
+                else
+                    a = load_quad_st<ST>(colp[b], q, nqf, p);
                 s[b] += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z +
                         (double)a.w * a.w;
             }
@@ -613,7 +630,10 @@ __global__ __launch_bounds__(256) void k_colnorm(PassParams pp, double* __restri
 #pragma unroll
         for (int b = 0; b < C; ++b) {
             const double tot = wave_allreduce_sum(s[b]);
-            if (lane == 0 && c0 + b < ce) norms[c0 + b] = sqrt(tot);
+            if (lane == 0 && c0 + b < ce) {
+                const double sc = (ST == kStF32) ? 1.0 : (double)column_scale(pp, c0 + b);
+                norms[c0 + b] = sc * sqrt(tot);
+            }
         }
     }
 }
@@ -740,27 +760,27 @@ hipError_t launch_corr_vx(const Plan& pl, const PassParams& pp, const float* X, 
     }
 }
 
-template <int M, bool VEC>
+template <int M, bool VEC, int ST>
 static hipError_t launch_bp_t(const Plan& pl, const PassParams& pp, int j0, const float* S,
                               const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                               hipStream_t st) {
-    hipLaunchKernelGGL((k_backproj<M, 2, VEC>), dim3(pl.bp_rb, pl.bp_cr), dim3(256), 0, st, pp,
-                       j0, S, act, gpart, touched, pl.bp_cr, ctrl);
+    hipLaunchKernelGGL((k_backproj<M, 2, VEC, ST>), dim3(pl.bp_rb, pl.bp_cr), dim3(256), 0, st,
+                       pp, j0, S, act, gpart, touched, pl.bp_cr, ctrl);
     return hipGetLastError();
 }
 
-template <bool VEC>
+template <bool VEC, int ST>
 static hipError_t launch_bp_v(const Plan& pl, const PassParams& pp, int j0, const float* S,
                               const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                               hipStream_t st) {
     const int r = pl.m - j0;
     const int mb = r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 16;
     switch (mb) {
-        case 1: return launch_bp_t<1, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
-        case 2: return launch_bp_t<2, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
-        case 4: return launch_bp_t<4, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
-        case 8: return launch_bp_t<8, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
-        default: return launch_bp_t<16, VEC>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 1: return launch_bp_t<1, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 2: return launch_bp_t<2, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 4: return launch_bp_t<4, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 8: return launch_bp_t<8, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        default: return launch_bp_t<16, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
     }
 }
 
@@ -769,19 +789,33 @@ hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
                            const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                            hipStream_t st) {
     for (int j0 = 0; j0 < pl.m; j0 += 16) {
-        hipError_t e = pl.vec4 ? launch_bp_v<true>(pl, pp, j0, S, act, gpart, touched, ctrl, st)
-                               : launch_bp_v<false>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        hipError_t e;
+        if (pl.dtype == GPSPCA_BF16)
+            e = launch_bp_v<true, kStBF16>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        else if (pl.dtype == GPSPCA_F8E4M3)
+            e = launch_bp_v<true, kStF8>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        else if (pl.vec4)
+            e = launch_bp_v<true, kStF32>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        else
+            e = launch_bp_v<false, kStF32>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_colnorm(const PassParams& pp, double* norms, int grid, hipStream_t st) {
-    const bool vec = ((pp.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(pp.A) & 15) == 0);
-    if (vec)
-        hipLaunchKernelGGL((k_colnorm<true>), dim3(grid), dim3(256), 0, st, pp, norms);
-    else
-        hipLaunchKernelGGL((k_colnorm<false>), dim3(grid), dim3(256), 0, st, pp, norms);
+hipError_t launch_colnorm(const PassParams& pp, int dtype, double* norms, int grid,
+                          hipStream_t st) {
+    if (dtype == GPSPCA_BF16) {
+        hipLaunchKernelGGL((k_colnorm<true, kStBF16>), dim3(grid), dim3(256), 0, st, pp, norms);
+    } else if (dtype == GPSPCA_F8E4M3) {
+        hipLaunchKernelGGL((k_colnorm<true, kStF8>), dim3(grid), dim3(256), 0, st, pp, norms);
+    } else {
+        const bool vec = ((pp.lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(pp.A) & 15) == 0);
+        if (vec)
+            hipLaunchKernelGGL((k_colnorm<true, kStF32>), dim3(grid), dim3(256), 0, st, pp, norms);
+        else
+            hipLaunchKernelGGL((k_colnorm<false, kStF32>), dim3(grid), dim3(256), 0, st, pp, norms);
+    }
     return hipGetLastError();
 }
 

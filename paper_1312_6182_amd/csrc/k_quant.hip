@@ -1,0 +1,444 @@
+// Reduced-precision storage of A on gfx950: the quantizer and the correlation
+// kernel of the bfloat16 / e4m3fn path.
+//
+// Storage (an extension of the paper's method, which stores A in full
+// precision): bfloat16 codes with scale 1, or e4m3fn codes with the per-column
+// scale max_r |a_ri| / 448.  The correlation of a quantized column is
+// scale_i * sum_r value(q_ri) x_rj, accumulated in FP32.
+//
+// k_corr_q streams the codes through LDS exactly like the FP32 matrix-core
+// kernel (one wave per workgroup, 64 columns per chunk, 8 swizzled 16-byte
+// slots per column per stage, direct global->LDS DMA), but each slot now holds
+// 8 (bfloat16) or 16 (e4m3) rows, and the products run on the bfloat16 matrix
+// cores (v_mfma_f32_16x16x32_bf16):
+//   - A codes are bfloat16 operands as loaded (e4m3 codes are widened to
+//     bfloat16, which holds every e4m3 value exactly);
+//   - X (FP32) is split as x = hi + mid + lo with three bfloat16 parts, so
+//     the three products reproduce x to about 2^-24 relative: the dot product
+//     keeps FP32 accuracy although A moves 2 or 1 bytes per element;
+//   - the contraction index is permuted consistently on both operands: lane
+//     group g of a 32-row step takes 8 consecutive rows of its slot.
+#include "storage.h"
+
+#include <algorithm>
+#include <cstdlib>
+
+namespace gpspca {
+
+typedef float f4q __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8q __attribute__((ext_vector_type(8)));
+typedef uint32_t u4q __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// --------------------------------------------------------------- quantizer
+// bfloat16, round to nearest even on the FP32 bit pattern (A is finite).
+__device__ __forceinline__ uint32_t bf16_rne(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// e4m3fn, round to nearest even, saturating at +-448.  Normal results: the
+// FP32 exponent is rebiased (127 -> 7) and the 20 dropped mantissa bits are
+// rounded on the bit pattern (a carry moves into the exponent field);
+// subnormal results (|v| < 2^-6) are multiples of 2^-9.
+__device__ __forceinline__ uint32_t e4m3_rne(float v) {
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    const uint32_t mag = u & 0x7FFFFFFFu;
+    uint32_t code;
+    if (mag >= 0x43E00000u) {                 // |v| >= 448
+        code = 0x7Eu;
+    } else if (mag >= 0x3C800000u) {          // |v| >= 2^-6
+        uint32_t x = mag - (120u << 23);
+        x += 0x7FFFFu + ((x >> 20) & 1u);
+        code = x >> 20;
+        code = code < 0x7Eu ? code : 0x7Eu;
+    } else {
+        code = (uint32_t)__builtin_rintf(__uint_as_float(mag) * 512.0f);
+    }
+    return sign | code;
+}
+
+template <int TO>
+__global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ A, int64_t lda,
+                                                  int p, int64_t n, void* __restrict__ out,
+                                                  int64_t ldq, float* __restrict__ scale) {
+    const int lane = threadIdx.x & 63;
+    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= n) return;
+    const float* a = A + col * lda;
+    if constexpr (TO == kStBF16) {
+        uint16_t* q = static_cast<uint16_t*>(out) + col * ldq;
+        for (int r = lane; r < p; r += 64) q[r] = (uint16_t)bf16_rne(a[r]);
+        if (scale && lane == 0) scale[col] = 1.0f;
+    } else {
+        float mx = 0.f;
+        for (int r = lane; r < p; r += 64) mx = fmaxf(mx, fabsf(a[r]));
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        const float sc = mx > 0.f ? mx / 448.0f : 1.0f;
+        uint8_t* q = static_cast<uint8_t*>(out) + col * ldq;
+        for (int r = lane; r < p; r += 64) q[r] = (uint8_t)e4m3_rne(a[r] / sc);
+        if (lane == 0) scale[col] = sc;
+    }
+}
+
+// ------------------------------------------------------- correlation kernel
+constexpr int kTq = 4;                       // column tiles of 16 per chunk
+constexpr int kAStageQ = 16 * kTq * 8 * 16;  // 8192 B: 64 columns x 8 slots x 16 B
+
+__device__ __forceinline__ uint32_t q_slot(int c, int s) {
+    return (uint32_t)(16 * (c * 8 + (s ^ ((c >> 1) & 7))));
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N <= 63, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void wait_lgkm() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void tie(f4q& v) { asm volatile("" : "+v"(v)); }
+
+__device__ __forceinline__ f4q lds16(uint32_t addr) {
+    f4q v;
+    asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(addr) : "memory");
+    return v;
+}
+
+__device__ __forceinline__ void dma(const void* g, uint32_t lds) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                     (void __attribute__((address_space(3)))*)(uintptr_t)lds, 16,
+                                     0, 0);
+}
+
+// Upper halves of two FP32 words packed as two bfloat16 (exact for values that
+// are bfloat16 numbers).
+__device__ __forceinline__ uint32_t pack_hi(float lo, float hi) {
+    return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x07060302u);
+}
+
+// 8 e4m3 codes (two words) -> 8 bfloat16 operands.
+__device__ __forceinline__ bf8q widen8(uint32_t w0, uint32_t w1) {
+    const qf2 a = e4m3_pair(w0, false), b = e4m3_pair(w0, true);
+    const qf2 c = e4m3_pair(w1, false), d = e4m3_pair(w1, true);
+    u4q r = u4q{pack_hi(a.x, a.y), pack_hi(b.x, b.y), pack_hi(c.x, c.y), pack_hi(d.x, d.y)};
+    return __builtin_bit_cast(bf8q, r);
+}
+
+// x = hi + mid + lo (each part bfloat16, rounded to nearest).
+__device__ __forceinline__ void split3(const float (&x)[8], bf8q& hi, bf8q& mid, bf8q& lo) {
+    float r[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        hi[e] = (__bf16)x[e];
+        r[e] = x[e] - (float)hi[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        mid[e] = (__bf16)r[e];
+        r[e] = r[e] - (float)mid[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lo[e] = (__bf16)r[e];
+}
+
+__device__ __forceinline__ bool thresh_q(bool l0, double mu, double gamma, float y, float& s,
+                                         double& fv) {
+    const double yd = (double)y;
+    if (l0) {
+        const double my = mu * yd;
+        const double q = my * my - gamma;
+        if (q > 0.0) { s = (float)my; fv = q; return true; }
+    } else {
+        const double t = mu * fabs(yd) - gamma;
+        if (t > 0.0) { s = (float)(yd > 0.0 ? t : -t); fv = t * t; return true; }
+    }
+    s = 0.f;
+    fv = 0.0;
+    return false;
+}
+
+}  // namespace
+
+// ST: kStBF16 | kStF8;  J: component blocks of 16;  STAGES: stages in flight.
+template <int ST, int J, int STAGES>
+__global__ __launch_bounds__(64) void k_corr_q(PassParams pp, const float* __restrict__ X,
+                                               float* __restrict__ S, uint8_t* __restrict__ act,
+                                               double* __restrict__ fpart,
+                                               int* __restrict__ nnzpart,
+                                               const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int ES = (ST == kStBF16) ? 2 : 1;     // bytes per element
+    constexpr int EPS = 16 / ES;                     // rows per 16-byte slot
+    constexpr int XQ = 2 * EPS;                      // X row quads per stage (8 slots)
+    constexpr int XDMA = XQ / 4;                     // X DMA instructions per block
+    constexpr int XBlk = XQ * 16 * 16;               // X bytes per component block
+    constexpr int StageBytes = kAStageQ + J * XBlk;
+    constexpr int PER = 8 + J * XDMA;
+    constexpr int G8 = EPS / 8;                      // 8-row operand groups per slot
+    __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
+    const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
+
+    const int lane = threadIdx.x;
+    const int p = pp.p, m = pp.m, ldx = pp.ldx;
+    const int nsf = p / EPS;                 // full slots per column
+    const int nst = (nsf + 7) / 8;           // stages
+    const int rows_main = nsf * EPS;
+    const bool l0 = pp.l0 != 0;
+    const int64_t n = pp.n;
+    const int64_t W = gridDim.x, w = blockIdx.x;
+    const int64_t cbeg = n * w / W, cend = n * (w + 1) / W;
+    const int lj = lane & 15, lk = lane >> 4;
+    const uint8_t* Ab = (ST == kStBF16) ? reinterpret_cast<const uint8_t*>(pp.Abf) : pp.Af8;
+    const int64_t colbytes = pp.lda * ES;
+
+    double f_acc[J];
+    int nnz_acc[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) { f_acc[jb] = 0.0; nnz_acc[jb] = 0; }
+
+    const float* xcol[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
+    const int xzero = ldx - 4;
+    const int nxq = nsf * (EPS / 4);         // X row quads covered by full slots
+
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kTq) {
+        const uint8_t* acol[8];
+        int aslot[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int L = 64 * i + lane;
+            const int cl = L >> 3;
+            aslot[i] = (L & 7) ^ ((cl >> 1) & 7);
+            int64_t col = c0 + cl;
+            col = (col < cend) ? col : cend - 1;
+            acol[i] = Ab + col * colbytes;
+        }
+        auto issue = [&](int st) {
+            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int s = 8 * st + aslot[i];
+                s = (s < nsf) ? s : nsf - 1;
+                dma(acol[i] + 16 * s, sb + 1024 * i);
+            }
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+                for (int i = 0; i < XDMA; ++i) {
+                    const int q = XQ * st + 4 * i + lk;
+                    const int off = (q < nxq) ? 4 * q : xzero;
+                    dma(xcol[jb] + off, sb + kAStageQ + XBlk * jb + 1024 * i);
+                }
+        };
+
+        f4q acc[kTq][J];
+#pragma unroll
+        for (int t = 0; t < kTq; ++t)
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4q{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+        for (int s = 0; s < STAGES - 1; ++s)
+            if (s < nst) issue(s);
+
+        for (int st = 0; st < nst; ++st) {
+            if (st + STAGES - 1 < nst) issue(st + STAGES - 1);
+            const int ahead = (nst - 1 - st < STAGES - 1) ? nst - 1 - st : STAGES - 1;
+            if constexpr (STAGES >= 3) {
+                if (ahead >= 2) wait_vm<2 * PER>();
+                else if (ahead == 1) wait_vm<PER>();
+                else wait_vm<0>();
+            } else {
+                if (ahead >= 1) wait_vm<PER>();
+                else wait_vm<0>();
+            }
+            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int slot = 4 * h + lk;
+                f4q araw[kTq];
+#pragma unroll
+                for (int t = 0; t < kTq; ++t) araw[t] = lds16(sb + q_slot(16 * t + lj, slot));
+                f4q xr[J][EPS / 4];
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+                    for (int u = 0; u < EPS / 4; ++u)
+                        xr[jb][u] = lds16(sb + kAStageQ + XBlk * jb +
+                                          16u * (uint32_t)(((EPS / 4) * slot + u) * 16 + lj));
+                wait_lgkm();
+#pragma unroll
+                for (int t = 0; t < kTq; ++t) tie(araw[t]);
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+                    for (int u = 0; u < EPS / 4; ++u) tie(xr[jb][u]);
+#pragma unroll
+                for (int g = 0; g < G8; ++g) {
+                    bf8q xh[J], xm[J], xl[J];
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb) {
+                        float xv[8];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            xv[e] = xr[jb][2 * g][e];
+                            xv[4 + e] = xr[jb][2 * g + 1][e];
+                        }
+                        split3(xv, xh[jb], xm[jb], xl[jb]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < kTq; ++t) {
+                        bf8q aop;
+                        if constexpr (ST == kStBF16) {
+                            aop = __builtin_bit_cast(bf8q, araw[t]);
+                        } else {
+                            const u4q wv = __builtin_bit_cast(u4q, araw[t]);
+                            aop = widen8(wv[2 * g], wv[2 * g + 1]);
+                        }
+#pragma unroll
+                        for (int jb = 0; jb < J; ++jb) {
+                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xh[jb], acc[t][jb], 0, 0, 0);
+                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xm[jb], acc[t][jb], 0, 0, 0);
+                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xl[jb], acc[t][jb], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+
+        // ragged tail rows rows_main .. p-1 (fewer than one slot), FP32 FMA
+        if (rows_main < p) {
+#pragma unroll
+            for (int t = 0; t < kTq; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int64_t col = c0 + 16 * t + 4 * lk + v;
+                    col = (col < cend) ? col : cend - 1;
+                    const uint8_t* ac = Ab + col * colbytes;
+                    for (int r = rows_main; r < p; ++r) {
+                        const float a = (ST == kStBF16)
+                                            ? bf16_value(reinterpret_cast<const uint16_t*>(ac)[r])
+                                            : e4m3_value(ac[r]);
+#pragma unroll
+                        for (int jb = 0; jb < J; ++jb)
+                            acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
+                    }
+                }
+        }
+
+        // scale, threshold, S, activity flags
+#pragma unroll
+        for (int t = 0; t < kTq; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t col = c0 + 16 * t + 4 * lk + v;
+                const bool cvalid = col < cend;
+                const float sc = cvalid ? column_scale(pp, col) : 1.0f;
+                bool any = false;
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb) {
+                    const int comp = 16 * jb + lj;
+                    if (cvalid && comp < m) {
+                        float s;
+                        double fv;
+                        const bool a = thresh_q(l0, pp.mu[comp], pp.gam[comp],
+                                                sc * acc[t][jb][v], s, fv);
+                        S[col * m + comp] = s;
+                        if (a) {
+                            f_acc[jb] += fv;
+                            nnz_acc[jb] += 1;
+                            any = true;
+                        }
+                    }
+                }
+                const uint64_t bal = __ballot(any);
+                if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+            }
+    }
+
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) {
+        double f = f_acc[jb];
+        int c = nnz_acc[jb];
+        f += __shfl_xor(f, 16, 64);
+        c += __shfl_xor(c, 16, 64);
+        f += __shfl_xor(f, 32, 64);
+        c += __shfl_xor(c, 32, 64);
+        const int comp = 16 * jb + lj;
+        if (lane < 16 && comp < m) {
+            fpart[(int64_t)comp * W + w] = f;
+            nnzpart[(int64_t)comp * W + w] = c;
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_quantize(const float* A, int64_t lda, int p, int64_t n, int to, void* out,
+                           int64_t ldq, float* scale, hipStream_t st) {
+    const dim3 grid((unsigned)((n + 3) / 4)), block(256);
+    if (to == GPSPCA_BF16)
+        hipLaunchKernelGGL(k_quantize<kStBF16>, grid, block, 0, st, A, lda, p, n, out, ldq, scale);
+    else
+        hipLaunchKernelGGL(k_quantize<kStF8>, grid, block, 0, st, A, lda, p, n, out, ldq, scale);
+    return hipGetLastError();
+}
+
+// Stages and component blocks of the quantized kernel for (storage, m).
+static void corr_q_shape(int st, int m, int* J, int* stages) {
+    *J = m <= 16 ? 1 : m <= 32 ? 2 : 4;
+    if (st == GPSPCA_BF16) *stages = (*J <= 2) ? 3 : 2;
+    else *stages = 2;
+}
+
+template <int ST, int J, int S>
+static int occ_q() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_q<ST, J, S>, 64, 0) != hipSuccess)
+        nb = 1;
+    (void)hipGetLastError();
+    return nb;
+}
+
+int corr_q_blocks_per_cu(int st, int m) {
+    int J, S;
+    corr_q_shape(st, m, &J, &S);
+    int nb;
+    if (st == GPSPCA_BF16) {
+        if (J == 1) nb = occ_q<kStBF16, 1, 3>();
+        else if (J == 2) nb = occ_q<kStBF16, 2, 3>();
+        else nb = occ_q<kStBF16, 4, 2>();
+    } else {
+        if (J == 1) nb = occ_q<kStF8, 1, 2>();
+        else if (J == 2) nb = occ_q<kStF8, 2, 2>();
+        else nb = occ_q<kStF8, 4, 2>();
+    }
+    int cap = 4;
+    if (const char* s = std::getenv("GPSPCA_MFMA_WAVES_PER_CU")) cap = std::max(1, std::atoi(s));
+    return std::max(1, std::min(nb, cap));
+}
+
+hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, float* S,
+                         uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                         hipStream_t st) {
+    int J, Sg;
+    corr_q_shape(pl.dtype, pl.m, &J, &Sg);
+    const dim3 grid(pl.corr_grid), block(64);
+#define GPSPCA_CQ(STT, JJ, SS) \
+    hipLaunchKernelGGL((k_corr_q<STT, JJ, SS>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl)
+    if (pl.dtype == GPSPCA_BF16) {
+        if (J == 1) GPSPCA_CQ(kStBF16, 1, 3);
+        else if (J == 2) GPSPCA_CQ(kStBF16, 2, 3);
+        else GPSPCA_CQ(kStBF16, 4, 2);
+    } else {
+        if (J == 1) GPSPCA_CQ(kStF8, 1, 2);
+        else if (J == 2) GPSPCA_CQ(kStF8, 2, 2);
+        else GPSPCA_CQ(kStF8, 4, 2);
+    }
+#undef GPSPCA_CQ
+    return hipGetLastError();
+}
+
+}  // namespace gpspca

@@ -827,7 +827,6 @@ hipError_t launch_project_diag(const Plan& pl, const double* gram, double* coef,
 __global__ void k_project(int m, double* __restrict__ coef, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ StopShared ss;
-    __shared__ double red[2 * 256];
     extern __shared__ double dyn[];
     double* A0 = dyn;
     double* A1 = dyn + (size_t)m * LDM;

@@ -34,7 +34,53 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_binding_covers_every_declared_symbol():
-    assert set(_declared_functions()) == set(L.SIGNATURES)
+    from paper_1312_6182_amd import serve as SV
+    assert set(_declared_functions()) == set(L.SIGNATURES) | set(SV.SIGNATURES)
+
+
+def test_reduced_precision_and_server_validation():
+    """Argument checks of the quantizer, refinement and server entry points
+    (all rejected on the host, before any HIP call)."""
+    from paper_1312_6182_amd import serve as SV
+    lib = SV._lib()
+    buf = (ctypes.c_float * 64)()
+    M = L.Matrix()
+    M.data = ctypes.addressof(buf)
+    M.p, M.n, M.lda, M.dtype = 4, 4, 4, L.F32
+    out = (ctypes.c_uint8 * 64)()
+    assert lib.gpspca_quantize(ctypes.byref(M), L.F32, ctypes.addressof(out), 4, None, None) == L.EDTYPE
+    assert lib.gpspca_quantize(ctypes.byref(M), L.F8E4M3, ctypes.addressof(out), 4, None, None) == L.EINVAL
+    assert lib.gpspca_quantize(ctypes.byref(M), L.BF16, ctypes.addressof(out), 3, None, None) == L.EINVAL
+    # BF16 storage needs lda % 8 == 0; F8E4M3 needs a scale
+    Mq = L.Matrix()
+    Mq.data = ctypes.addressof(out) + (-ctypes.addressof(out)) % 16
+    Mq.p, Mq.n, Mq.lda, Mq.dtype = 4, 4, 4, L.BF16
+    assert lib.gpspca_workspace_bytes(ctypes.byref(Mq), L.SL1, 1, 10) == 0
+    Mq.dtype, Mq.lda = L.F8E4M3, 16
+    assert lib.gpspca_workspace_bytes(ctypes.byref(Mq), L.SL1, 1, 10) == 0
+    assert "col_scale" in L.last_error()
+    # F32 storage takes no scale
+    M.col_scale = ctypes.addressof(buf)
+    assert lib.gpspca_workspace_bytes(ctypes.byref(M), L.SL1, 1, 10) == 0
+    M.col_scale = None
+    # refinement needs a support and a start
+    x = (ctypes.c_float * 4)()
+    sup = (ctypes.c_uint32 * 4)()
+    nit = ctypes.c_int(0)
+    ws = (ctypes.c_uint8 * 1024)()
+    wsp = ctypes.addressof(ws) + (-ctypes.addressof(ws)) % 256
+    assert lib.gpspca_refine(ctypes.byref(M), L.SL1, 1, 0.1, None, None, ctypes.addressof(x), 0.0,
+                             5, wsp, 512, None, ctypes.addressof(x), None, None, None,
+                             ctypes.byref(nit)) == L.EINVAL
+    assert lib.gpspca_refine(ctypes.byref(M), L.SL1, 1, 0.1, None, ctypes.addressof(sup), None,
+                             0.0, 5, wsp, 512, None, ctypes.addressof(x), None, None, None,
+                             ctypes.byref(nit)) == L.EINVAL
+    # server: arena and slots are checked first
+    h = ctypes.c_void_p()
+    assert lib.gpspca_server_create(None, 1 << 30, 2, ctypes.byref(h)) == L.EINVAL
+    assert lib.gpspca_server_create(wsp, 1 << 30, 0, ctypes.byref(h)) == L.EINVAL
+    assert lib.gpspca_server_create(wsp, 1 << 20, 2, ctypes.byref(h)) == L.ENOMEM
+    assert not h.value
 
 
 def test_version_string():

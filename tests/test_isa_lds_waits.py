@@ -1,4 +1,4 @@
-"""Static check of the matrix-core correlation kernel's gfx950 assembly.
+"""Static check of the matrix-core correlation kernels' gfx950 assembly.
 
 Its LDS reads are inline asm (the compiler cannot count the direct
 global->LDS DMA completions across the stage loop, so the waits are explicit).
@@ -13,7 +13,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "paper_1312_6182_amd", "csrc", "k_corr_mfma.hip")
+CSRC = os.path.join(ROOT, "paper_1312_6182_amd", "csrc")
 
 
 def _regs(tok):
@@ -59,20 +59,24 @@ def test_checker_flags_a_consumer_before_the_wait():
 
 @pytest.mark.skipif(not (os.path.exists("/opt/rocm/bin/hipcc") or shutil.which("hipcc")),
                     reason="hipcc not installed")
-def test_mfma_kernel_waits_before_consuming_lds_reads(tmp_path):
+@pytest.mark.parametrize("src,kernel,mfma,count", [
+    ("k_corr_mfma.hip", "k_corr_mfma", "v_mfma_f32_16x16x4_f32", 4),
+    ("k_quant.hip", "k_corr_q", "v_mfma_f32_16x16x32_bf16", 6),
+])
+def test_mfma_kernel_waits_before_consuming_lds_reads(tmp_path, src, kernel, mfma, count):
     hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shutil.which("hipcc")
     out = tmp_path / "k.s"
     cmd = [hipcc, "-x", "hip", "-S", "--cuda-device-only", "--offload-arch=gfx950", "-O3",
            "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), SRC, "-o", str(out)]
+           "-I", os.path.join(ROOT, "include"), os.path.join(CSRC, src), "-o", str(out)]
     subprocess.run(cmd, check=True, capture_output=True)
     asm = out.read_text()
-    names = re.findall(r"^(_Z\S*k_corr_mfma\S*):", asm, re.M)
-    assert len(names) >= 3
+    names = re.findall(r"^(_Z\S*" + kernel + r"\S*):", asm, re.M)
+    assert len(names) >= count
     for name in names:
         i = asm.find(name + ":")
         j = asm.find(".Lfunc_end", i)
         body = asm[i:j].split("\n")
-        assert any("v_mfma_f32_16x16x4_f32" in l for l in body)
+        assert any(mfma in l for l in body)
         assert any("global_load_lds_dwordx4" in l for l in body)
         assert lds_read_hazards(body) == [], name
