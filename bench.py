@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary workloads (BL0, m=64, m=1 and the 5000x50000 single-unit case)")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving mix at its full sizes (p up to 20000, n up to 200000) instead "
+                         "of the default p up to 5000, n up to 50000")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run 3 plain device copies (x * 1) of this many MiB; their "
                          "HBM counter readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -148,6 +152,72 @@ def gamma_path_leg(G, torch, W, Ad, A32, cmax, passes, K=32):
             del r, w
         del Aq, sc
     return res
+
+
+def serving_leg(W, count, full, slots=8, arena_gb=8, seed=1000):
+    """The serving mix through the solve server: every request a default-start
+    solve (tol 1e-4, up to 1000 passes) on a planted-spike matrix (k =
+    max(10, n/100), beta = 5 sqrt(n)).  A closed-loop run (all requests at once)
+    gives the saturation rate in solves/s; an open-loop run with Poisson
+    arrivals at 0.75x that rate gives the latency percentiles (finish - arrival,
+    including the upload of a matrix that is not resident).  Each run starts
+    from an empty arena."""
+    from paper_1312_6182_amd.serve import Server
+    p_max, n_max = (20000, 200000) if full else (5000, 50000)
+    reqs = W.serving_requests(count, seed, p_max=p_max, n_max=n_max)
+    t = time.perf_counter()
+    mats = {}
+    for r in reqs:
+        key = r["matrix_seed"]
+        if key not in mats:
+            A, _, _, _ = W.planted_single(r["p"], r["n"], key, k=max(10, r["n"] // 100),
+                                          beta=5.0 * (r["n"] ** 0.5))
+            cmax = float(np.sqrt(np.einsum("ij,ij->j", A, A, dtype=np.float64).max()))
+            mats[key] = (A, cmax, r["dtype"])
+    gen_s = time.perf_counter() - t
+    distinct_gb = sum(A.nbytes / (2 if dt == "bf16" else 1) for A, _, dt in mats.values()) / 1e9
+
+    def run(rate):
+        rng = np.random.default_rng(seed + 1)
+        with Server(arena_gb << 30, slots=slots) as srv:
+            ids = {k: srv.register(A, store=dt) for k, (A, _, dt) in mats.items()}
+            t0 = time.perf_counter()
+            at = 0.0
+            rids = []
+            for r in reqs:
+                if rate:
+                    at += float(rng.exponential(1.0 / rate))
+                    delay = t0 + at - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                A, cmax, _ = mats[r["matrix_seed"]]
+                g = r["frac"] * (cmax * cmax if r["form"] in (1, 3) else cmax)
+                rids.append(srv.submit(ids[r["matrix_seed"]], r["form"], r["m"], g,
+                                       tol=1e-4, max_iter=1000))
+            res = [srv.wait(x) for x in rids]
+            el = time.perf_counter() - t0
+            st = srv.stats()
+        lat = np.array([x.latency for x in res])
+        return {"solves_per_s": len(res) / el, "seconds": el,
+                "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "mean_passes": float(np.mean([x.n_iter for x in res])),
+                "uploads": st["uploads"], "evictions": st["evictions"],
+                "status_counts": {str(s): int(c) for s, c in
+                                  zip(*np.unique([x.status for x in res], return_counts=True))}}
+
+    closed = run(None)
+    print(f"[bench] serving closed loop: {closed}", file=sys.stderr, flush=True)
+    rate = 0.75 * closed["solves_per_s"]
+    opened = run(rate)
+    print(f"[bench] serving open loop at {rate:.1f}/s: {opened}", file=sys.stderr, flush=True)
+    return {"workload": f"{count} requests, p log-uniform [200, {p_max}], n log-uniform "
+                        f"[2000, {n_max}], forms uniform, m in (1, 4, 16), gamma fraction "
+                        f"U[0.01, 0.5], FP32 or bf16 storage, half repeat an earlier matrix; "
+                        f"{len(mats)} distinct matrices ({distinct_gb:.1f} GB stored), "
+                        f"{slots} slots, {arena_gb} GB arena",
+            "generation_s": gen_s, "saturation": closed,
+            "open_loop": dict(opened, arrival_rate_per_s=rate)}
 
 
 def time_gpu(G, torch, Ad, form, m, gamma, steps, warmup):
@@ -298,6 +368,10 @@ def main():
         out["extra"] = extra
     if not args.no_extra and args.p == 10000 and args.n == 100000:
         out["c4_gamma_path"] = gamma_path_leg(G, torch, W, Ad, A32, cmax, max(5, args.steps // 5))
+    if not args.no_extra and args.serve_requests > 0:
+        del Ad, At
+        torch.cuda.empty_cache()
+        out["c5_serving"] = serving_leg(W, args.serve_requests, args.serve_full)
     if args.copy_calibration_mib > 0:
         copy_calibration(torch, args.copy_calibration_mib)
     if not args.no_cpu:

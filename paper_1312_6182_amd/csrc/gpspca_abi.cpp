@@ -150,6 +150,7 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         if (fk == "vx" && vx_ok) pl->use_vx = 1;
         else if (fk == "mv" && mv_ok) pl->use_mv = 1;
         else if (fk == "mfma" && pl->vec4) pl->use_mfma = 1;
+        else if (fk == "rd" && pl->vec4) pl->use_mfma = pl->use_rd = 1;
         else if (fk == "valu") {}
         else if (!f32) pl->use_q = 1;
         else if (vx_ok && m <= 4) pl->use_vx = 1;
@@ -174,7 +175,13 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
             // one wavefront per workgroup; as many per CU as the LDS stages allow
             pl->corr_M = 16;
             pl->mfma_stages = corr_mfma_stages(m);
-            const int per_cu = pl->use_mv ? 4 : corr_mfma_blocks_per_cu(m, pl->mfma_stages);
+            pl->rd_depth = corr_rd_depth();
+            int per_cu = pl->use_mv ? 4 : corr_mfma_blocks_per_cu(m, pl->mfma_stages);
+            if (pl->use_rd) {
+                per_cu = 4;
+                if (const char* w = std::getenv("GPSPCA_MFMA_WAVES_PER_CU"))
+                    per_cu = std::max(1, std::atoi(w));
+            }
             int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, cdiv(A->n, 16));
             pl->corr_grid = (int)std::max<int64_t>(1, grid);
             pl->nwave_part = pl->corr_grid;
@@ -236,6 +243,9 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->o_fcomp = take(sizeof(double) * 2 * M);
     pl->o_pstate = take(path ? sizeof(PathState) * M : 1);
     pl->o_list = take(sizeof(int) * (N + 64));  // frozen-support column list + its count
+    const bool xil = pl->use_mfma || pl->use_q;   // interleaved copies of X for the DMA kernels
+    pl->o_xil0 = take(xil ? sizeof(float) * L * (size_t)pl->mpad : 1);
+    pl->o_xil1 = take(xil ? sizeof(float) * L * (size_t)pl->mpad : 1);
     pl->total = o;
 }
 
@@ -263,6 +273,7 @@ struct Ptrs {
     PathState* pstate;
     int* list;
     int* nlist;
+    float* xil[2];
 };
 
 static Ptrs carve(const Plan& pl, void* ws) {
@@ -292,6 +303,8 @@ static Ptrs carve(const Plan& pl, void* ws) {
     P.pstate = reinterpret_cast<PathState*>(b + pl.o_pstate);
     P.list = reinterpret_cast<int*>(b + pl.o_list);
     P.nlist = P.list + pl.n;
+    P.xil[0] = reinterpret_cast<float*>(b + pl.o_xil0);
+    P.xil[1] = reinterpret_cast<float*>(b + pl.o_xil1);
     return P;
 }
 
@@ -383,9 +396,14 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
         else if (pl.use_mv)
             GPSPCA_HIP(launch_corr_mv(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         else if (pl.use_q)
-            GPSPCA_HIP(launch_corr_q(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+            GPSPCA_HIP(launch_corr_q(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
+                                     P.ctrl, st));
+        else if (pl.use_rd)
+            GPSPCA_HIP(launch_corr_rd(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
+                                      P.ctrl, st));
         else if (pl.use_mfma)
-            GPSPCA_HIP(launch_corr_mfma(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+            GPSPCA_HIP(launch_corr_mfma(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
+                                        P.ctrl, st));
         else
             GPSPCA_HIP(launch_corr(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         GPSPCA_HIP(tl.end(st));
@@ -405,7 +423,8 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
         GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp,
                                P.coef + 5 * (size_t)pl.m * pl.m, P.ctrl, st));
     }
-    GPSPCA_HIP(launch_apply(pl, P.g64, Xk, P.coef, Xn, P.ctrl, st));
+    GPSPCA_HIP(launch_apply(pl, P.g64, Xk, P.coef, Xn,
+                            (pl.use_mfma || pl.use_q) ? P.xil[(k + 1) & 1] : nullptr, P.ctrl, st));
     return GPSPCA_OK;
 }
 
@@ -462,6 +481,7 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
                            : pl.use_vx ? "k_corr_vx"
                            : pl.use_mv ? "k_corr_mv"
                            : pl.use_q ? "k_corr_q"
+                           : pl.use_rd ? "k_corr_rd"
                            : pl.use_mfma ? "k_corr_mfma" : "k_corr");
     *fin = *snap;
     return GPSPCA_OK;
@@ -524,7 +544,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
             GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
             GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
         }
-        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
     } else if (path) {
         // all columns start at the normalized column of largest norm
         Plan p1;
@@ -541,7 +561,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
         GPSPCA_HIP(launch_gather(p1, pp1, P.idx, P.g64, st));
         GPSPCA_HIP(launch_gram(p1, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
         GPSPCA_HIP(launch_project(p1, P.gram, P.coef, P.ctrl, st));
-        GPSPCA_HIP(launch_apply(p1, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+        GPSPCA_HIP(launch_apply(p1, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
         GPSPCA_HIP(launch_bcast_col0(pl, P.x[0], st));
     } else {
         // the m columns of largest norm (ties to the lower index)
@@ -551,7 +571,12 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
         GPSPCA_HIP(launch_gather(pl, pp, P.idx, P.g64, st));
         GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
         GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
-        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], P.ctrl, st));
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
+    }
+
+    if (pl.use_mfma || pl.use_q) {
+        GPSPCA_HIP(launch_fill_zero(P.xil[1], sizeof(float) * pl.ldx * pl.mpad, st));
+        GPSPCA_HIP(launch_x_interleave(pl, P.x[0], P.xil[0], st));
     }
 
     Ctrl fin;
@@ -691,6 +716,7 @@ int gpspca_step(const gpspca_matrix* A, int form, int m, double gamma, const dou
     GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
     GPSPCA_HIP(hipMemcpy2DAsync(P.x[0], sizeof(float) * pl.ldx, Xin, sizeof(float) * A->p,
                                 sizeof(float) * A->p, m, hipMemcpyDeviceToDevice, st));
+    if (pl.use_mfma || pl.use_q) GPSPCA_HIP(launch_x_interleave(pl, P.x[0], P.xil[0], st));
     TimedLaunches tl;
     rc = enqueue_pass(pl, pp, P, 0, st, tl);
     if (rc) return rc;

@@ -79,6 +79,8 @@ struct Plan {
     int restricted;        // frozen-support passes over a column list (VALU correlation)
     int use_mfma;          // block correlation on the matrix cores (LDS DMA staging)
     int mfma_stages;       // stages in flight of the matrix-core kernel
+    int use_rd;            // matrix-core correlation with register-direct operand loads
+    int rd_depth;          // its software-pipeline depth (stages of 32 rows)
     int use_vx;            // block correlation with X held in registers (m <= 8, p <= 10240)
     int vx_threads, vx_kq;
     int use_mv;            // block correlation on the matrix cores, A staged through registers
@@ -86,7 +88,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
         o_l1, o_g64, o_gram, o_coef, o_norms, o_cand_v, o_cand_i, o_idx, o_fin, o_invn, o_fcomp,
-        o_pstate, o_list;
+        o_pstate, o_list, o_xil0, o_xil1;
     size_t total;
 };
 
@@ -102,11 +104,17 @@ hipError_t launch_corr_vx(const Plan& pl, const PassParams& pp, const float* X, 
                           uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st);
 int corr_mfma_stages(int m);
+int corr_rd_depth();
+hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                          float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st);
 int corr_mfma_blocks_per_cu(int m, int stages);
 hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, float* S,
                           uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st);
-hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, float* S,
+// Xil: X in the row-quad-interleaved layout of launch_x_interleave.
+hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                            float* S,
                             uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                             hipStream_t st);
 hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
@@ -120,7 +128,8 @@ hipError_t launch_mask_list(const uint32_t* mask, int64_t words, int m, int64_t 
 hipError_t launch_quantize(const float* A, int64_t lda, int p, int64_t n, int to, void* out,
                            int64_t ldq, float* scale, hipStream_t st);
 int corr_q_blocks_per_cu(int dtype, int m);
-hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, float* S,
+hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                         float* S,
                          uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                          hipStream_t st);
 
@@ -156,8 +165,14 @@ hipError_t launch_project_diag(const Plan& pl, const double* gram, double* coef,
                                hipStream_t st);
 hipError_t launch_project(const Plan& pl, const double* gram, double* coef, Ctrl* ctrl,
                           hipStream_t st);
+// X (component-major, leading dim ldx) -> Xil: blocks of 16 components, each
+// block row-quad-major, Xil[((b * ldx/4 + q) * 16 + c) * 4 + e] = X[16b + c][4q + e],
+// so that the matrix-core kernels stage 4 row quads x 16 components of X with
+// one contiguous 1 KB read.
+hipError_t launch_x_interleave(const Plan& pl, const float* X, float* Xil, hipStream_t st);
+// Xil_n (may be NULL): also write X_{k+1} in the interleaved layout.
 hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, const double* coef,
-                        float* Xn, const Ctrl* ctrl, hipStream_t st);
+                        float* Xn, float* Xil_n, const Ctrl* ctrl, hipStream_t st);
 hipError_t launch_load_g64(const Plan& pl, const float* X0, int ldx0, double* g64,
                            hipStream_t st);
 

@@ -5,13 +5,17 @@
 //   of each y_ij, S and a per-column activity flag, objective partials.
 //
 // Work decomposition (one wavefront per workgroup, no barriers):
-//   - each wave owns a contiguous range of n/W columns (+-1) and walks it in
-//     chunks of T = 4 tiles of 16 columns (64 columns);
+//   - each wave owns a contiguous range of whole tiles of 16 columns (the
+//     same number of tiles, +-1, for every wave) and walks it in chunks of up
+//     to 4 tiles (64 columns); a shorter last chunk issues DMA and matrix-core
+//     work for its own tiles only;
 //   - the rows of a chunk are streamed in stages of 32 rows: 8 DMA
 //     instructions bring the 64 x 32 A tile into LDS (column-major, quads
 //     XOR-swizzled per column so that the MFMA operand reads are free of bank
 //     conflicts), 2 per component block bring the matching X rows;
-//     STAGES stages are in flight while the oldest is consumed;
+//     STAGES stages are in flight while the oldest is consumed (X comes from
+//     a row-quad-interleaved copy, so each of its DMA instructions reads one
+//     contiguous 1 KB);
 //   - each stage feeds v_mfma_f32_16x16x4_f32 with M = 16 columns, N = 16
 //     components, K = 4 rows: lane l supplies A[row 4(l/16)+t][col l%16] and
 //     X[row 4(l/16)+t][comp l%16] for t = 0..3 (one 16-byte LDS read each);
@@ -84,9 +88,185 @@ __device__ __forceinline__ bool threshold_m(bool l0, double mu, double gamma, fl
 
 }  // namespace
 
+// One chunk of NT tiles of 16 columns (NT <= 4) starting at column c0: stream
+// its rows through the LDS stages, multiply on the matrix cores, threshold.
+// Columns at or past cend are clamped to cend - 1 and their results dropped.
+template <int NT, int J, int STAGES>
+__device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int64_t cend,
+                                           uint32_t lbase, const float* const* xcol,
+                                           const float* __restrict__ Xil, double* f_acc,
+                                           int* nnz_acc, float* __restrict__ S,
+                                           uint8_t* __restrict__ act) {
+    constexpr int XStageBytes = J * 2 * 1024;
+    constexpr int StageBytes = kAStageBytes + XStageBytes;
+    constexpr int ADMA = 2 * NT;           // A DMA instructions per stage (8 columns each)
+    constexpr int PER = ADMA + 2 * J;      // DMA instructions per stage
+    const int lane = threadIdx.x;
+    const int lj = lane & 15, lk = lane >> 4;
+    const int p = pp.p, m = pp.m;
+    const int nqf = p >> 2;
+    const int nqx = pp.ldx >> 2;           // quads of the X buffers; the last is zero
+    const int nst = (nqf + kQS - 1) / kQS;
+    const bool l0 = pp.l0 != 0;
+
+    // A DMA sources: slot L = 64 i + lane holds column L / 8 and the quad whose
+    // swizzled position is L % 8
+    const float* acol[ADMA];
+    int aq[ADMA];
+#pragma unroll
+    for (int i = 0; i < ADMA; ++i) {
+        const int L = 64 * i + lane;
+        const int cl = L / kQS;
+        aq[i] = (L % kQS) ^ ((cl >> 1) & 7);
+        int64_t col = c0 + cl;
+        col = (col < cend) ? col : cend - 1;
+        acol[i] = pp.A + col * pp.lda;
+    }
+    auto issue = [&](int st) {
+        const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+        const int q0 = kQS * st;
+#pragma unroll
+        for (int i = 0; i < ADMA; ++i) {
+            int q = q0 + aq[i];
+            q = (q < nqf) ? q : nqf - 1;
+            dma16(acol[i] + 4 * q, sb + 1024 * i);
+        }
+        // X: 4 row quads x 16 components per instruction, one contiguous 1 KB
+        // of the interleaved copy (rows past the full quads read the zero quad)
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                int q = q0 + 4 * i + lk;
+                q = (q < nqf) ? q : nqx - 1;
+                dma16(Xil + ((size_t)(jb * nqx + q) * 16 + lj) * 4,
+                      sb + kAStageBytes + 1024 * (2 * jb + i));
+            }
+    };
+
+    f4m acc[NT][J];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4m{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int s = 0; s < STAGES - 1; ++s)
+        if (s < nst) issue(s);
+
+    for (int st = 0; st < nst; ++st) {
+        if (st + STAGES - 1 < nst) issue(st + STAGES - 1);
+        const int ahead = (nst - 1 - st < STAGES - 1) ? nst - 1 - st : STAGES - 1;
+        if constexpr (STAGES >= 4) {
+            if (ahead >= 3) wait_vmcnt<3 * PER>();
+            else if (ahead == 2) wait_vmcnt<2 * PER>();
+            else if (ahead == 1) wait_vmcnt<PER>();
+            else wait_vmcnt<0>();
+        } else if constexpr (STAGES == 3) {
+            if (ahead >= 2) wait_vmcnt<2 * PER>();
+            else if (ahead == 1) wait_vmcnt<PER>();
+            else wait_vmcnt<0>();
+        } else {
+            if (ahead >= 1) wait_vmcnt<PER>();
+            else wait_vmcnt<0>();
+        }
+        const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+        // both halves of the stage are read before the first multiplies, so the
+        // second half's LDS latency hides behind the first half's MFMAs
+        f4m av[2][NT], xv[2][J];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                av[h][t] = lds_read16(sb + a_slot(16 * t + lj, 4 * h + lk));
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+                xv[h][jb] = lds_read16(sb + kAStageBytes + 2048u * jb +
+                                       16u * (uint32_t)((4 * h + lk) * 16 + lj));
+            if (h == 0) {
+                // wait for the first half's reads before the second half's are issued
+                wait_lgkm0();
+#pragma unroll
+                for (int t = 0; t < NT; ++t) after_wait(av[0][t]);
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb) after_wait(xv[0][jb]);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the second half's reads ahead of the MFMAs
+#pragma unroll
+        for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        av[0][t][tm], xv[0][jb][tm], acc[t][jb], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);  // the first half's MFMAs stay before the wait
+        wait_lgkm0();
+#pragma unroll
+        for (int t = 0; t < NT; ++t) after_wait(av[1][t]);
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) after_wait(xv[1][jb]);
+#pragma unroll
+        for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                        av[1][t][tm], xv[1][jb][tm], acc[t][jb], 0, 0, 0);
+    }
+
+    // ragged tail rows 4*nqf .. p-1 (p % 4 of them)
+    if (p & 3) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int64_t col = c0 + 16 * t + 4 * lk + v;
+                col = (col < cend) ? col : cend - 1;
+                const float* ac = pp.A + col * pp.lda;
+                for (int r = 4 * nqf; r < p; ++r) {
+                    const float a = ac[r];
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb)
+                        acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
+                }
+            }
+    }
+
+    // threshold, S, activity flags
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t col = c0 + 16 * t + 4 * lk + v;
+            const bool cvalid = col < cend;
+            bool any = false;
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb) {
+                const int comp = 16 * jb + lj;
+                if (cvalid && comp < m) {
+                    float s;
+                    double fv;
+                    const bool a = threshold_m(l0, pp.mu[comp], pp.gam[comp], acc[t][jb][v], s, fv);
+                    S[col * m + comp] = s;
+                    if (a) {
+                        f_acc[jb] += fv;
+                        nnz_acc[jb] += 1;
+                        any = true;
+                    }
+                }
+            }
+            const uint64_t bal = __ballot(any);
+            if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+        }
+}
+
 // J: component blocks of 16 (m <= 16 J);  STAGES: stages in flight.
 template <int J, int STAGES>
 __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __restrict__ X,
+                                                  const float* __restrict__ Xil,
                                                   float* __restrict__ S,
                                                   uint8_t* __restrict__ act,
                                                   double* __restrict__ fpart,
@@ -95,169 +275,42 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
     if (ctrl->done) return;
     constexpr int XStageBytes = J * 2 * 1024;
     constexpr int StageBytes = kAStageBytes + XStageBytes;
-    constexpr int PER = 8 + 2 * J;  // DMA instructions per stage
     __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
 
     const int lane = threadIdx.x;
-    const int p = pp.p, m = pp.m, ldx = pp.ldx;
-    const int nqf = p >> 2;
-    const int rem = p & 3;
-    const int nst = (nqf + kQS - 1) / kQS;
-    const bool l0 = pp.l0 != 0;
+    const int m = pp.m, ldx = pp.ldx;
     const int64_t n = pp.n;
     const int64_t W = gridDim.x, w = blockIdx.x;
-    // exact column partition: every wave streams the same number of columns
-    // (+-1), so HBM traffic is balanced; a partial last chunk repeats its last
-    // column, which costs L2 hits, not HBM reads
-    const int64_t cbeg = n * w / W;
-    const int64_t cend = n * (w + 1) / W;
+    // partition in whole tiles of 16 columns: every wave gets the same number
+    // of tiles (+-1) and issues DMA and matrix-core work only for those, so no
+    // wave streams clamped duplicate columns except in the last tile of A
+    const int64_t ntile = (n + 15) / 16;
+    const int64_t cbeg = 16 * (ntile * w / W);
+    const int64_t cend = std::min<int64_t>(n, 16 * (ntile * (w + 1) / W));
 
-    const int lj = lane & 15;   // MFMA N index (component within block) / M index
-    const int lk = lane >> 4;   // MFMA K group
+    const int lj = lane & 15;
 
     double f_acc[J];
     int nnz_acc[J];
 #pragma unroll
     for (int jb = 0; jb < J; ++jb) { f_acc[jb] = 0.0; nnz_acc[jb] = 0; }
 
-    // X DMA source pointers: slot L = 64 i + lane -> quad k = 4 i + lane/16, comp lane%16
+    // component columns of X (component-major) for the ragged tail rows
     const float* xcol[J];
 #pragma unroll
     for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
-    const int xzero = ldx - 4;  // a quad of zero rows (ldx >= p + 4)
 
     for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kT) {
-        // A DMA sources: slot L = 64 i + lane holds column L / 8 and the quad whose
-        // swizzled position is L % 8
-        const float* acol[kQS];
-        int aq[kQS];
-#pragma unroll
-        for (int i = 0; i < kQS; ++i) {
-            const int L = 64 * i + lane;
-            const int cl = L / kQS;
-            const int q = (L % kQS) ^ ((cl >> 1) & 7);
-            int64_t col = c0 + cl;
-            col = (col < cend) ? col : cend - 1;
-            acol[i] = pp.A + col * pp.lda;
-            aq[i] = q;
-        }
-        auto issue = [&](int st) {
-            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
-            const int q0 = kQS * st;
-#pragma unroll
-            for (int i = 0; i < kQS; ++i) {
-                int q = q0 + aq[i];
-                q = (q < nqf) ? q : nqf - 1;
-                dma16(acol[i] + 4 * q, sb + 1024 * i);
-            }
-#pragma unroll
-            for (int jb = 0; jb < J; ++jb)
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const int q = q0 + 4 * i + lk;
-                    const int off = (q < nqf) ? 4 * q : xzero;
-                    dma16(xcol[jb] + off, sb + kAStageBytes + 1024 * (2 * jb + i));
-                }
-        };
-
-        f4m acc[kT][J];
-#pragma unroll
-        for (int t = 0; t < kT; ++t)
-#pragma unroll
-            for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4m{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll
-        for (int s = 0; s < STAGES - 1; ++s)
-            if (s < nst) issue(s);
-
-        for (int st = 0; st < nst; ++st) {
-            if (st + STAGES - 1 < nst) issue(st + STAGES - 1);
-            const int ahead = (nst - 1 - st < STAGES - 1) ? nst - 1 - st : STAGES - 1;
-            if constexpr (STAGES >= 4) {
-                if (ahead >= 3) wait_vmcnt<3 * PER>();
-                else if (ahead == 2) wait_vmcnt<2 * PER>();
-                else if (ahead == 1) wait_vmcnt<PER>();
-                else wait_vmcnt<0>();
-            } else if constexpr (STAGES == 3) {
-                if (ahead >= 2) wait_vmcnt<2 * PER>();
-                else if (ahead == 1) wait_vmcnt<PER>();
-                else wait_vmcnt<0>();
-            } else {
-                if (ahead >= 1) wait_vmcnt<PER>();
-                else wait_vmcnt<0>();
-            }
-            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                f4m av[kT], xv[J];
-#pragma unroll
-                for (int t = 0; t < kT; ++t)
-                    av[t] = lds_read16(sb + a_slot(16 * t + lj, 4 * h + lk));
-#pragma unroll
-                for (int jb = 0; jb < J; ++jb)
-                    xv[jb] = lds_read16(sb + kAStageBytes + 2048u * jb +
-                                        16u * (uint32_t)((4 * h + lk) * 16 + lj));
-                wait_lgkm0();
-#pragma unroll
-                for (int t = 0; t < kT; ++t) after_wait(av[t]);
-#pragma unroll
-                for (int jb = 0; jb < J; ++jb) after_wait(xv[jb]);
-#pragma unroll
-                for (int tm = 0; tm < 4; ++tm)
-#pragma unroll
-                    for (int t = 0; t < kT; ++t)
-#pragma unroll
-                        for (int jb = 0; jb < J; ++jb)
-                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                av[t][tm], xv[jb][tm], acc[t][jb], 0, 0, 0);
-            }
-        }
-
-        // ragged tail rows 4*nqf .. p-1 (p % 4 of them)
-        if (rem) {
-#pragma unroll
-            for (int t = 0; t < kT; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int64_t col = c0 + 16 * t + 4 * lk + v;
-                    col = (col < cend) ? col : cend - 1;
-                    const float* ac = pp.A + col * pp.lda;
-                    for (int r = 4 * nqf; r < p; ++r) {
-                        const float a = ac[r];
-#pragma unroll
-                        for (int jb = 0; jb < J; ++jb)
-                            acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
-                    }
-                }
-        }
-
-        // threshold, S, activity flags
-#pragma unroll
-        for (int t = 0; t < kT; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t col = c0 + 16 * t + 4 * lk + v;
-                const bool cvalid = col < cend;
-                bool any = false;
-#pragma unroll
-                for (int jb = 0; jb < J; ++jb) {
-                    const int comp = 16 * jb + lj;
-                    if (cvalid && comp < m) {
-                        float s;
-                        double fv;
-                        const bool a = threshold_m(l0, pp.mu[comp], pp.gam[comp], acc[t][jb][v], s, fv);
-                        S[col * m + comp] = s;
-                        if (a) {
-                            f_acc[jb] += fv;
-                            nnz_acc[jb] += 1;
-                            any = true;
-                        }
-                    }
-                }
-                const uint64_t bal = __ballot(any);
-                if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
-            }
+        const int64_t left = cend - c0;
+        if (left > 48)
+            mfma_chunk<4, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 32)
+            mfma_chunk<3, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 16)
+            mfma_chunk<2, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
+        else
+            mfma_chunk<1, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
     }
 
     // per-component totals over the lanes sharing lane % 16 (fixed xor order)
@@ -275,6 +328,206 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
             nnzpart[(int64_t)comp * W + w] = c;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// k_corr_rd: the same matrix-core correlation with every operand loaded
+// straight into registers (no LDS): lane (lj, lk) loads rows 4(4h + lk) ..
+// +3 of column 16t + lj (one 16-byte load feeds four MFMAs) and the matching
+// X quad of component lj from the interleaved copy.  Stages of 32 rows are
+// software-pipelined D deep with compile-time buffer indices; loads past the
+// last full quad are clamped and meet zero rows of X, so no load is
+// conditional and the compiler's waits stay exact.
+// ---------------------------------------------------------------------------
+template <int NT, int J, int D>
+__device__ __forceinline__ void rd_chunk(const PassParams& pp, int64_t c0, int64_t cend,
+                                         const float* const* xcol,
+                                         const float* __restrict__ Xil, double* f_acc,
+                                         int* nnz_acc, float* __restrict__ S,
+                                         uint8_t* __restrict__ act) {
+    const int lane = threadIdx.x;
+    const int lj = lane & 15, lk = lane >> 4;
+    const int p = pp.p, m = pp.m;
+    const int nqf = p >> 2;
+    const int nqx = pp.ldx >> 2;
+    const int nst = (nqf + kQS - 1) / kQS;
+    const bool l0 = pp.l0 != 0;
+
+    const float* colp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        int64_t col = c0 + 16 * t + lj;
+        col = (col < cend) ? col : cend - 1;
+        colp[t] = pp.A + col * pp.lda;
+    }
+    f4m abuf[D][NT][2], xbuf[D][J][2];
+    auto load = [&](int st, f4m(&ab)[NT][2], f4m(&xb)[J][2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = kQS * st + 4 * h + lk;
+            const int qa = (q < nqf) ? q : nqf - 1;
+            const int qx = (q < nqf) ? q : nqx - 1;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                ab[t][h] = __builtin_nontemporal_load(reinterpret_cast<const f4m*>(colp[t] + 4 * qa));
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+                xb[jb][h] = *reinterpret_cast<const f4m*>(
+                    Xil + ((size_t)(jb * nqx + qx) * 16 + lj) * 4);
+        }
+    };
+    f4m acc[NT][J];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4m{0.f, 0.f, 0.f, 0.f};
+
+    // the scheduling barriers keep every prefetch where it is written (D stages
+    // ahead of its use); left alone, the scheduler sinks loads next to their
+    // consumers and the pipeline collapses into load-wait-compute
+    if (nst > 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) load(d, abuf[d], xbuf[d]);
+        __builtin_amdgcn_sched_barrier(0);
+        for (int s0 = 0; s0 < nst; s0 += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+#pragma unroll
+                            for (int jb = 0; jb < J; ++jb)
+                                acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    abuf[d][t][h][tm], xbuf[d][jb][h][tm], acc[t][jb], 0, 0, 0);
+                // stages past the last one re-read it (clamped) and meet zero X
+                int nxt = s0 + d + D;
+                nxt = (nxt < nst) ? nxt : nst;
+                __builtin_amdgcn_sched_barrier(0);
+                load(nxt, abuf[d], xbuf[d]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    if (p & 3) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int64_t col = c0 + 16 * t + 4 * lk + v;
+                col = (col < cend) ? col : cend - 1;
+                const float* ac = pp.A + col * pp.lda;
+                for (int r = 4 * nqf; r < p; ++r) {
+                    const float a = ac[r];
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb)
+                        acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
+                }
+            }
+    }
+
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t col = c0 + 16 * t + 4 * lk + v;
+            const bool cvalid = col < cend;
+            bool any = false;
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb) {
+                const int comp = 16 * jb + lj;
+                if (cvalid && comp < m) {
+                    float s;
+                    double fv;
+                    const bool a = threshold_m(l0, pp.mu[comp], pp.gam[comp], acc[t][jb][v], s, fv);
+                    S[col * m + comp] = s;
+                    if (a) {
+                        f_acc[jb] += fv;
+                        nnz_acc[jb] += 1;
+                        any = true;
+                    }
+                }
+            }
+            const uint64_t bal = __ballot(any);
+            if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+        }
+}
+
+template <int J, int D>
+__global__ __launch_bounds__(64) void k_corr_rd(PassParams pp, const float* __restrict__ X,
+                                                const float* __restrict__ Xil,
+                                                float* __restrict__ S, uint8_t* __restrict__ act,
+                                                double* __restrict__ fpart,
+                                                int* __restrict__ nnzpart,
+                                                const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int lane = threadIdx.x;
+    const int m = pp.m, ldx = pp.ldx;
+    const int64_t n = pp.n;
+    const int64_t W = gridDim.x, w = blockIdx.x;
+    const int64_t ntile = (n + 15) / 16;
+    const int64_t cbeg = 16 * (ntile * w / W);
+    const int64_t cend = std::min<int64_t>(n, 16 * (ntile * (w + 1) / W));
+    const int lj = lane & 15;
+    double f_acc[J];
+    int nnz_acc[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) { f_acc[jb] = 0.0; nnz_acc[jb] = 0; }
+    const float* xcol[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kT) {
+        const int64_t left = cend - c0;
+        if (left > 48) rd_chunk<4, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 32) rd_chunk<3, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 16) rd_chunk<2, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else rd_chunk<1, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+    }
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) {
+        double f = f_acc[jb];
+        int c = nnz_acc[jb];
+        f += __shfl_xor(f, 16, 64);
+        c += __shfl_xor(c, 16, 64);
+        f += __shfl_xor(f, 32, 64);
+        c += __shfl_xor(c, 32, 64);
+        const int comp = 16 * jb + lj;
+        if (lane < 16 && comp < m) {
+            fpart[(int64_t)comp * W + w] = f;
+            nnzpart[(int64_t)comp * W + w] = c;
+        }
+    }
+}
+
+int corr_rd_depth() {
+    const char* e = std::getenv("GPSPCA_RD_DEPTH");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 2 || v == 3 || v == 4 || v == 6) ? v : 4;
+}
+
+hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                          float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st) {
+    const dim3 grid(pl.corr_grid), block(64);
+    const int D = pl.rd_depth;
+#define GPSPCA_RD(JJ, DD) \
+    hipLaunchKernelGGL((k_corr_rd<JJ, DD>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl)
+    if (pl.m <= 16) {
+        if (D == 2) GPSPCA_RD(1, 2);
+        else if (D == 3) GPSPCA_RD(1, 3);
+        else if (D == 6) GPSPCA_RD(1, 6);
+        else GPSPCA_RD(1, 4);
+    } else if (pl.m <= 32) {
+        if (D <= 2) GPSPCA_RD(2, 2);
+        else GPSPCA_RD(2, 3);
+    } else {
+        GPSPCA_RD(4, 2);
+    }
+#undef GPSPCA_RD
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -433,14 +686,13 @@ hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, 
     return hipGetLastError();
 }
 
-// Stages in flight of the matrix-core kernel for m <= 16: 3 (30 KB of LDS per
-// wave) or 4 (40 KB, four waves fill the 160 KB of a CU).
+// Stages in flight of the matrix-core kernel for m <= 16: 2 (20 KB of LDS per
+// wave), 3 (30 KB) or 4 (40 KB, four waves fill the 160 KB of a CU).
 int corr_mfma_stages(int m) {
     if (m > 16) return m <= 32 ? 3 : 2;
     const char* e = std::getenv("GPSPCA_MFMA_STAGES");
-    if (e && std::atoi(e) == 3) return 3;
-    if (e && std::atoi(e) == 4) return 4;
-    return 4;
+    const int v = e ? std::atoi(e) : 0;
+    return (v >= 2 && v <= 4) ? v : 4;
 }
 
 // Waves per CU of the matrix-core kernels: what LDS allows, at most 4 (one per
@@ -450,6 +702,8 @@ int corr_mfma_blocks_per_cu(int m, int stages) {
     hipError_t e;
     if (m <= 16 && stages == 4)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 4>, 64, 0);
+    else if (m <= 16 && stages == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 2>, 64, 0);
     else if (m <= 16)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 3>, 64, 0);
     else if (m <= 32)
@@ -463,18 +717,20 @@ int corr_mfma_blocks_per_cu(int m, int stages) {
     return std::min(nb, cap);
 }
 
-hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, float* S,
-                            uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                            float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                             hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(64);
     if (pl.m <= 16 && pl.mfma_stages == 4)
-        hipLaunchKernelGGL((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
+        hipLaunchKernelGGL((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+    else if (pl.m <= 16 && pl.mfma_stages == 2)
+        hipLaunchKernelGGL((k_corr_mfma<1, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 16)
-        hipLaunchKernelGGL((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
+        hipLaunchKernelGGL((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 32)
-        hipLaunchKernelGGL((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
+        hipLaunchKernelGGL((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else
-        hipLaunchKernelGGL((k_corr_mfma<4, 2>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl);
+        hipLaunchKernelGGL((k_corr_mfma<4, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     return hipGetLastError();
 }
 

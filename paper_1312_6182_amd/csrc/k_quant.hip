@@ -7,8 +7,9 @@
 // scale_i * sum_r value(q_ri) x_rj, accumulated in FP32.
 //
 // k_corr_q streams the codes through LDS exactly like the FP32 matrix-core
-// kernel (one wave per workgroup, 64 columns per chunk, 8 swizzled 16-byte
-// slots per column per stage, direct global->LDS DMA), but each slot now holds
+// kernel (one wave per workgroup owning whole tiles of 16 columns, chunks of up
+// to 64 columns, 8 swizzled 16-byte slots per column per stage, direct
+// global->LDS DMA), but each slot now holds
 // 8 (bfloat16) or 16 (e4m3) rows, and the products run on the bfloat16 matrix
 // cores (v_mfma_f32_16x16x32_bf16):
 //   - A codes are bfloat16 operands as loaded (e4m3 codes are widened to
@@ -161,37 +162,214 @@ __device__ __forceinline__ bool thresh_q(bool l0, double mu, double gamma, float
 
 }  // namespace
 
-// ST: kStBF16 | kStF8;  J: component blocks of 16;  STAGES: stages in flight.
-template <int ST, int J, int STAGES>
-__global__ __launch_bounds__(64) void k_corr_q(PassParams pp, const float* __restrict__ X,
-                                               float* __restrict__ S, uint8_t* __restrict__ act,
-                                               double* __restrict__ fpart,
-                                               int* __restrict__ nnzpart,
-                                               const Ctrl* __restrict__ ctrl) {
-    if (ctrl->done) return;
+// One chunk of NT tiles of 16 columns (NT <= 4) starting at column c0 (see
+// k_corr_q).  Columns at or past cend are clamped to cend - 1 and dropped.
+template <int NT, int ST, int J, int STAGES>
+__device__ __forceinline__ void q_chunk(const PassParams& pp, int64_t c0, int64_t cend,
+                                        uint32_t lbase, const float* const* xcol,
+                                        const float* __restrict__ Xil, double* f_acc,
+                                        int* nnz_acc, float* __restrict__ S,
+                                        uint8_t* __restrict__ act) {
     constexpr int ES = (ST == kStBF16) ? 2 : 1;     // bytes per element
     constexpr int EPS = 16 / ES;                     // rows per 16-byte slot
     constexpr int XQ = 2 * EPS;                      // X row quads per stage (8 slots)
     constexpr int XDMA = XQ / 4;                     // X DMA instructions per block
     constexpr int XBlk = XQ * 16 * 16;               // X bytes per component block
     constexpr int StageBytes = kAStageQ + J * XBlk;
-    constexpr int PER = 8 + J * XDMA;
+    constexpr int ADMA = 2 * NT;                     // A DMA instructions (8 columns each)
+    constexpr int PER = ADMA + J * XDMA;
     constexpr int G8 = EPS / 8;                      // 8-row operand groups per slot
+    const int lane = threadIdx.x;
+    const int lj = lane & 15, lk = lane >> 4;
+    const int p = pp.p, m = pp.m;
+    const int nsf = p / EPS;                 // full slots per column
+    const int nst = (nsf + 7) / 8;           // stages
+    const int rows_main = nsf * EPS;
+    const int nxq = nsf * (EPS / 4);         // X row quads covered by full slots
+    const int nqx = pp.ldx >> 2;             // quads of the X buffers; the last is zero
+    const bool l0 = pp.l0 != 0;
+    const uint8_t* Ab = (ST == kStBF16) ? reinterpret_cast<const uint8_t*>(pp.Abf) : pp.Af8;
+    const int64_t colbytes = pp.lda * ES;
+
+    const uint8_t* acol[ADMA];
+    int aslot[ADMA];
+#pragma unroll
+    for (int i = 0; i < ADMA; ++i) {
+        const int L = 64 * i + lane;
+        const int cl = L >> 3;
+        aslot[i] = (L & 7) ^ ((cl >> 1) & 7);
+        int64_t col = c0 + cl;
+        col = (col < cend) ? col : cend - 1;
+        acol[i] = Ab + col * colbytes;
+    }
+    auto issue = [&](int st) {
+        const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+#pragma unroll
+        for (int i = 0; i < ADMA; ++i) {
+            int sl = 8 * st + aslot[i];
+            sl = (sl < nsf) ? sl : nsf - 1;
+            dma(acol[i] + 16 * sl, sb + 1024 * i);
+        }
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+            for (int i = 0; i < XDMA; ++i) {
+                int q = XQ * st + 4 * i + lk;
+                q = (q < nxq) ? q : nqx - 1;
+                dma(Xil + ((size_t)(jb * nqx + q) * 16 + lj) * 4,
+                    sb + kAStageQ + XBlk * jb + 1024 * i);
+            }
+    };
+
+    f4q acc[NT][J];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4q{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int s = 0; s < STAGES - 1; ++s)
+        if (s < nst) issue(s);
+
+    for (int st = 0; st < nst; ++st) {
+        if (st + STAGES - 1 < nst) issue(st + STAGES - 1);
+        const int ahead = (nst - 1 - st < STAGES - 1) ? nst - 1 - st : STAGES - 1;
+        if constexpr (STAGES >= 3) {
+            if (ahead >= 2) wait_vm<2 * PER>();
+            else if (ahead == 1) wait_vm<PER>();
+            else wait_vm<0>();
+        } else {
+            if (ahead >= 1) wait_vm<PER>();
+            else wait_vm<0>();
+        }
+        const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int slot = 4 * h + lk;
+            f4q araw[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) araw[t] = lds16(sb + q_slot(16 * t + lj, slot));
+            f4q xr[J][EPS / 4];
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+                for (int u = 0; u < EPS / 4; ++u)
+                    xr[jb][u] = lds16(sb + kAStageQ + XBlk * jb +
+                                      16u * (uint32_t)(((EPS / 4) * slot + u) * 16 + lj));
+            wait_lgkm();
+#pragma unroll
+            for (int t = 0; t < NT; ++t) tie(araw[t]);
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+                for (int u = 0; u < EPS / 4; ++u) tie(xr[jb][u]);
+#pragma unroll
+            for (int g = 0; g < G8; ++g) {
+                bf8q xh[J], xm[J], xl[J];
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb) {
+                    float xv[8];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        xv[e] = xr[jb][2 * g][e];
+                        xv[4 + e] = xr[jb][2 * g + 1][e];
+                    }
+                    split3(xv, xh[jb], xm[jb], xl[jb]);
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    bf8q aop;
+                    if constexpr (ST == kStBF16) {
+                        aop = __builtin_bit_cast(bf8q, araw[t]);
+                    } else {
+                        const u4q wv = __builtin_bit_cast(u4q, araw[t]);
+                        aop = widen8(wv[2 * g], wv[2 * g + 1]);
+                    }
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb) {
+                        acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xh[jb], acc[t][jb], 0, 0, 0);
+                        acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xm[jb], acc[t][jb], 0, 0, 0);
+                        acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xl[jb], acc[t][jb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+
+    // ragged tail rows rows_main .. p-1 (fewer than one slot), FP32 FMA
+    if (rows_main < p) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int64_t col = c0 + 16 * t + 4 * lk + v;
+                col = (col < cend) ? col : cend - 1;
+                const uint8_t* ac = Ab + col * colbytes;
+                for (int r = rows_main; r < p; ++r) {
+                    const float a = (ST == kStBF16)
+                                        ? bf16_value(reinterpret_cast<const uint16_t*>(ac)[r])
+                                        : e4m3_value(ac[r]);
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb)
+                        acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
+                }
+            }
+    }
+
+    // scale, threshold, S, activity flags
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t col = c0 + 16 * t + 4 * lk + v;
+            const bool cvalid = col < cend;
+            const float sc = cvalid ? column_scale(pp, col) : 1.0f;
+            bool any = false;
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb) {
+                const int comp = 16 * jb + lj;
+                if (cvalid && comp < m) {
+                    float s;
+                    double fv;
+                    const bool a = thresh_q(l0, pp.mu[comp], pp.gam[comp], sc * acc[t][jb][v],
+                                            s, fv);
+                    S[col * m + comp] = s;
+                    if (a) {
+                        f_acc[jb] += fv;
+                        nnz_acc[jb] += 1;
+                        any = true;
+                    }
+                }
+            }
+            const uint64_t bal = __ballot(any);
+            if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+        }
+}
+
+// ST: kStBF16 | kStF8;  J: component blocks of 16;  STAGES: stages in flight.
+// Work partition as in k_corr_mfma: whole tiles of 16 columns per wave.
+template <int ST, int J, int STAGES>
+__global__ __launch_bounds__(64) void k_corr_q(PassParams pp, const float* __restrict__ X,
+                                               const float* __restrict__ Xil,
+                                               float* __restrict__ S, uint8_t* __restrict__ act,
+                                               double* __restrict__ fpart,
+                                               int* __restrict__ nnzpart,
+                                               const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int EPS = (ST == kStBF16) ? 8 : 16;
+    constexpr int XBlk = 2 * EPS * 16 * 16;
+    constexpr int StageBytes = kAStageQ + J * XBlk;
     __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
 
     const int lane = threadIdx.x;
-    const int p = pp.p, m = pp.m, ldx = pp.ldx;
-    const int nsf = p / EPS;                 // full slots per column
-    const int nst = (nsf + 7) / 8;           // stages
-    const int rows_main = nsf * EPS;
-    const bool l0 = pp.l0 != 0;
+    const int m = pp.m, ldx = pp.ldx;
     const int64_t n = pp.n;
     const int64_t W = gridDim.x, w = blockIdx.x;
-    const int64_t cbeg = n * w / W, cend = n * (w + 1) / W;
-    const int lj = lane & 15, lk = lane >> 4;
-    const uint8_t* Ab = (ST == kStBF16) ? reinterpret_cast<const uint8_t*>(pp.Abf) : pp.Af8;
-    const int64_t colbytes = pp.lda * ES;
+    const int64_t ntile = (n + 15) / 16;
+    const int64_t cbeg = 16 * (ntile * w / W);
+    const int64_t cend = std::min<int64_t>(n, 16 * (ntile * (w + 1) / W));
+    const int lj = lane & 15;
 
     double f_acc[J];
     int nnz_acc[J];
@@ -201,162 +379,17 @@ __global__ __launch_bounds__(64) void k_corr_q(PassParams pp, const float* __res
     const float* xcol[J];
 #pragma unroll
     for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
-    const int xzero = ldx - 4;
-    const int nxq = nsf * (EPS / 4);         // X row quads covered by full slots
 
     for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kTq) {
-        const uint8_t* acol[8];
-        int aslot[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int L = 64 * i + lane;
-            const int cl = L >> 3;
-            aslot[i] = (L & 7) ^ ((cl >> 1) & 7);
-            int64_t col = c0 + cl;
-            col = (col < cend) ? col : cend - 1;
-            acol[i] = Ab + col * colbytes;
-        }
-        auto issue = [&](int st) {
-            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                int s = 8 * st + aslot[i];
-                s = (s < nsf) ? s : nsf - 1;
-                dma(acol[i] + 16 * s, sb + 1024 * i);
-            }
-#pragma unroll
-            for (int jb = 0; jb < J; ++jb)
-#pragma unroll
-                for (int i = 0; i < XDMA; ++i) {
-                    const int q = XQ * st + 4 * i + lk;
-                    const int off = (q < nxq) ? 4 * q : xzero;
-                    dma(xcol[jb] + off, sb + kAStageQ + XBlk * jb + 1024 * i);
-                }
-        };
-
-        f4q acc[kTq][J];
-#pragma unroll
-        for (int t = 0; t < kTq; ++t)
-#pragma unroll
-            for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4q{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll
-        for (int s = 0; s < STAGES - 1; ++s)
-            if (s < nst) issue(s);
-
-        for (int st = 0; st < nst; ++st) {
-            if (st + STAGES - 1 < nst) issue(st + STAGES - 1);
-            const int ahead = (nst - 1 - st < STAGES - 1) ? nst - 1 - st : STAGES - 1;
-            if constexpr (STAGES >= 3) {
-                if (ahead >= 2) wait_vm<2 * PER>();
-                else if (ahead == 1) wait_vm<PER>();
-                else wait_vm<0>();
-            } else {
-                if (ahead >= 1) wait_vm<PER>();
-                else wait_vm<0>();
-            }
-            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int slot = 4 * h + lk;
-                f4q araw[kTq];
-#pragma unroll
-                for (int t = 0; t < kTq; ++t) araw[t] = lds16(sb + q_slot(16 * t + lj, slot));
-                f4q xr[J][EPS / 4];
-#pragma unroll
-                for (int jb = 0; jb < J; ++jb)
-#pragma unroll
-                    for (int u = 0; u < EPS / 4; ++u)
-                        xr[jb][u] = lds16(sb + kAStageQ + XBlk * jb +
-                                          16u * (uint32_t)(((EPS / 4) * slot + u) * 16 + lj));
-                wait_lgkm();
-#pragma unroll
-                for (int t = 0; t < kTq; ++t) tie(araw[t]);
-#pragma unroll
-                for (int jb = 0; jb < J; ++jb)
-#pragma unroll
-                    for (int u = 0; u < EPS / 4; ++u) tie(xr[jb][u]);
-#pragma unroll
-                for (int g = 0; g < G8; ++g) {
-                    bf8q xh[J], xm[J], xl[J];
-#pragma unroll
-                    for (int jb = 0; jb < J; ++jb) {
-                        float xv[8];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            xv[e] = xr[jb][2 * g][e];
-                            xv[4 + e] = xr[jb][2 * g + 1][e];
-                        }
-                        split3(xv, xh[jb], xm[jb], xl[jb]);
-                    }
-#pragma unroll
-                    for (int t = 0; t < kTq; ++t) {
-                        bf8q aop;
-                        if constexpr (ST == kStBF16) {
-                            aop = __builtin_bit_cast(bf8q, araw[t]);
-                        } else {
-                            const u4q wv = __builtin_bit_cast(u4q, araw[t]);
-                            aop = widen8(wv[2 * g], wv[2 * g + 1]);
-                        }
-#pragma unroll
-                        for (int jb = 0; jb < J; ++jb) {
-                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xh[jb], acc[t][jb], 0, 0, 0);
-                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xm[jb], acc[t][jb], 0, 0, 0);
-                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xl[jb], acc[t][jb], 0, 0, 0);
-                        }
-                    }
-                }
-            }
-        }
-
-        // ragged tail rows rows_main .. p-1 (fewer than one slot), FP32 FMA
-        if (rows_main < p) {
-#pragma unroll
-            for (int t = 0; t < kTq; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int64_t col = c0 + 16 * t + 4 * lk + v;
-                    col = (col < cend) ? col : cend - 1;
-                    const uint8_t* ac = Ab + col * colbytes;
-                    for (int r = rows_main; r < p; ++r) {
-                        const float a = (ST == kStBF16)
-                                            ? bf16_value(reinterpret_cast<const uint16_t*>(ac)[r])
-                                            : e4m3_value(ac[r]);
-#pragma unroll
-                        for (int jb = 0; jb < J; ++jb)
-                            acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
-                    }
-                }
-        }
-
-        // scale, threshold, S, activity flags
-#pragma unroll
-        for (int t = 0; t < kTq; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t col = c0 + 16 * t + 4 * lk + v;
-                const bool cvalid = col < cend;
-                const float sc = cvalid ? column_scale(pp, col) : 1.0f;
-                bool any = false;
-#pragma unroll
-                for (int jb = 0; jb < J; ++jb) {
-                    const int comp = 16 * jb + lj;
-                    if (cvalid && comp < m) {
-                        float s;
-                        double fv;
-                        const bool a = thresh_q(l0, pp.mu[comp], pp.gam[comp],
-                                                sc * acc[t][jb][v], s, fv);
-                        S[col * m + comp] = s;
-                        if (a) {
-                            f_acc[jb] += fv;
-                            nnz_acc[jb] += 1;
-                            any = true;
-                        }
-                    }
-                }
-                const uint64_t bal = __ballot(any);
-                if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
-            }
+        const int64_t left = cend - c0;
+        if (left > 48)
+            q_chunk<4, ST, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 32)
+            q_chunk<3, ST, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 16)
+            q_chunk<2, ST, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
+        else
+            q_chunk<1, ST, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
     }
 
 #pragma unroll
@@ -420,14 +453,15 @@ int corr_q_blocks_per_cu(int st, int m) {
     return std::max(1, std::min(nb, cap));
 }
 
-hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, float* S,
-                         uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                         float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                          hipStream_t st) {
     int J, Sg;
     corr_q_shape(pl.dtype, pl.m, &J, &Sg);
     const dim3 grid(pl.corr_grid), block(64);
 #define GPSPCA_CQ(STT, JJ, SS) \
-    hipLaunchKernelGGL((k_corr_q<STT, JJ, SS>), grid, block, 0, st, pp, X, S, act, fpart, nnzpart, ctrl)
+    hipLaunchKernelGGL((k_corr_q<STT, JJ, SS>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
+                       nnzpart, ctrl)
     if (pl.dtype == GPSPCA_BF16) {
         if (J == 1) GPSPCA_CQ(kStBF16, 1, 3);
         else if (J == 2) GPSPCA_CQ(kStBF16, 2, 3);

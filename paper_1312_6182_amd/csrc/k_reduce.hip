@@ -886,6 +886,7 @@ __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
                                                const float* __restrict__ Xk,
                                                const double* __restrict__ coef,
                                                float* __restrict__ Xn,
+                                               float* __restrict__ Xil,
                                                const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ double om[kMaxM];
@@ -904,13 +905,36 @@ __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
     if (dead)
         for (int l = 0; l < m; ++l) acc += (double)Xk[(size_t)l * ldx + r] * ps[l];
     Xn[(size_t)j * ldx + r] = (float)acc;
+    if (Xil)
+        Xil[((size_t)((j >> 4) * (ldx >> 2) + (r >> 2)) * 16 + (j & 15)) * 4 + (r & 3)] = (float)acc;
 }
 
 hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, const double* coef,
-                        float* Xn, const Ctrl* ctrl, hipStream_t st) {
+                        float* Xn, float* Xil_n, const Ctrl* ctrl, hipStream_t st) {
     const int p = (int)pl.p;
     hipLaunchKernelGGL(k_apply, dim3((p + 255) / 256, pl.m), dim3(256), 0, st, pl.m, p, pl.ldx,
-                       g64, Xk, coef, Xn, ctrl);
+                       g64, Xk, coef, Xn, Xil_n, ctrl);
+    return hipGetLastError();
+}
+
+// One thread per (block, quad, component): a 16-byte vector of 4 rows.
+__global__ __launch_bounds__(256) void k_x_interleave(int mpad, int ldx,
+                                                      const float* __restrict__ X,
+                                                      float* __restrict__ Xil) {
+    const int nq = ldx >> 2;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)nq * mpad) return;
+    const int c = (int)(e % 16);
+    const int64_t bq = e / 16;             // b * nq + q
+    const int q = (int)(bq % nq), b = (int)(bq / nq);
+    const float4 v = *reinterpret_cast<const float4*>(X + (size_t)(16 * b + c) * ldx + 4 * q);
+    *reinterpret_cast<float4*>(Xil + (size_t)e * 4) = v;
+}
+
+hipError_t launch_x_interleave(const Plan& pl, const float* X, float* Xil, hipStream_t st) {
+    const int64_t ne = (int64_t)(pl.ldx / 4) * pl.mpad;
+    hipLaunchKernelGGL(k_x_interleave, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st,
+                       pl.mpad, pl.ldx, X, Xil);
     return hipGetLastError();
 }
 

@@ -138,13 +138,14 @@ def random_orthonormal(p: int, m: int, seed: int) -> np.ndarray:
     return np.asfortranarray(Q * np.sign(np.diag(R))[None, :])
 
 
-def serving_requests(count: int, seed: int = 1000):
+def serving_requests(count: int, seed: int = 1000, p_max: int = 20000, n_max: int = 200000):
     """Request descriptors of the mixed serving workload.
 
-    p log-uniform in [200, 20000], n log-uniform in [2000, 200000], a
-    formulation uniform over the four, m in {1, 4, 16} (m = 1 for the
-    single-unit forms), gamma fraction uniform in [0.01, 0.5], and with
-    probability 1/2 a repeat of an earlier request's matrix."""
+    p log-uniform in [200, p_max], n log-uniform in [2000, n_max] (20000 and
+    200000 in the full setting), a formulation uniform over the four, m in
+    {1, 4, 16} (m = 1 for the single-unit forms), gamma fraction uniform in
+    [0.01, 0.5], storage FP32 or bfloat16 (even odds), and with probability 1/2
+    a repeat of an earlier request's matrix."""
     rng = np.random.default_rng(seed)
     out = []
     for r in range(count):
@@ -152,8 +153,8 @@ def serving_requests(count: int, seed: int = 1000):
             prev = out[int(rng.integers(len(out)))]
             p, n, mseed, dt = prev["p"], prev["n"], prev["matrix_seed"], prev["dtype"]
         else:
-            p = int(round(math.exp(rng.uniform(math.log(200), math.log(20000)))))
-            n = int(round(math.exp(rng.uniform(math.log(2000), math.log(200000)))))
+            p = int(round(math.exp(rng.uniform(math.log(200), math.log(p_max)))))
+            n = int(round(math.exp(rng.uniform(math.log(2000), math.log(n_max)))))
             mseed = seed + r
             dt = "f32" if rng.random() < 0.5 else "bf16"
         form = int(rng.integers(4))
