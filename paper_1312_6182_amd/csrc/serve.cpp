@@ -33,7 +33,8 @@ namespace gpspca {
 
 namespace {
 
-constexpr size_t kStageBytes = (size_t)64 << 20;  // per-slot upload staging for bfloat16 storage
+constexpr size_t kStageBytes = (size_t)64 << 20;  // per-slot device staging for bfloat16 storage
+constexpr size_t kPinnedBytes = (size_t)32 << 20; // per-slot pinned host buffer (two halves)
 
 size_t al(size_t x) { return serve::align_up(x); }
 
@@ -82,6 +83,7 @@ struct Server {
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
     std::vector<size_t> stage_off;
+    std::vector<uint8_t*> pinned;       // per slot, kPinnedBytes of page-locked host memory
     uint64_t next_matrix = 1, next_req = 1;
     bool stop = false;
     int running = 0;
@@ -95,9 +97,11 @@ struct Server {
     int upload(SMatrix& M, size_t off, int slot, hipStream_t st, std::string* err);
 };
 
-// Copy a registered host matrix into the arena at `off` (FP32 copy, or FP32
-// column chunks through the slot's staging area quantized to bfloat16), then
-// its column norms.
+// Copy a registered host matrix into the arena at `off`, then its column
+// norms.  Column chunks go through the slot's pinned host buffer (two halves:
+// the host copies chunk k+1 while the DMA engine moves chunk k); FP32 storage
+// lands in place, bfloat16 storage lands in the slot's device staging area and
+// is quantized from there.
 int Server::upload(SMatrix& M, size_t off, int slot, hipStream_t st, std::string* err) {
     uint8_t* dst = arena + off;
     auto hip_ok = [&](hipError_t e, const char* what) {
@@ -105,30 +109,52 @@ int Server::upload(SMatrix& M, size_t off, int slot, hipStream_t st, std::string
         *err = std::string(what) + ": " + hipGetErrorString(e);
         return false;
     };
-    if (M.dtype == GPSPCA_F32) {
-        if (!hip_ok(hipMemcpy2DAsync(dst, sizeof(float) * M.lda_dev, M.host, sizeof(float) * M.ld,
-                                     sizeof(float) * M.p, M.n, hipMemcpyHostToDevice, st),
-                    "upload"))
+    const bool f32 = M.dtype == GPSPCA_F32;
+    const size_t half = kPinnedBytes / 2;
+    // FP32 chunks are laid out with the device leading dimension, bfloat16
+    // chunks densely (leading dimension p) for the quantizer
+    const int64_t ldc = f32 ? M.lda_dev : M.p;
+    int64_t cols = (int64_t)(half / (sizeof(float) * ldc));
+    if (!f32) cols = std::min<int64_t>(cols, (int64_t)(kStageBytes / (sizeof(float) * M.p)));
+    if (cols < 1) {
+        *err = "a column exceeds the upload staging buffer";
+        return GPSPCA_ENOMEM;
+    }
+    hipEvent_t done[2] = {nullptr, nullptr};
+    for (int h = 0; h < 2; ++h)
+        if (!hip_ok(hipEventCreateWithFlags(&done[h], hipEventDisableTiming), "upload")) {
+            if (done[0]) (void)hipEventDestroy(done[0]);
             return GPSPCA_EDEVICE;
-    } else {
-        uint8_t* stage = arena + stage_off[slot];
-        const int64_t cols = std::max<int64_t>(1, (int64_t)(kStageBytes / (sizeof(float) * M.p)));
-        for (int64_t c0 = 0; c0 < M.n; c0 += cols) {
-            const int64_t nc = std::min<int64_t>(cols, M.n - c0);
-            if (!hip_ok(hipMemcpy2DAsync(stage, sizeof(float) * M.p, M.host + c0 * M.ld,
-                                         sizeof(float) * M.ld, sizeof(float) * M.p, nc,
-                                         hipMemcpyHostToDevice, st),
-                        "upload"))
-                return GPSPCA_EDEVICE;
-            if (!hip_ok(launch_quantize(reinterpret_cast<const float*>(stage), M.p, (int)M.p, nc,
+        }
+    int rc = GPSPCA_OK;
+    int k = 0;
+    for (int64_t c0 = 0; c0 < M.n && rc == GPSPCA_OK; c0 += cols, ++k) {
+        const int64_t nc = std::min<int64_t>(cols, M.n - c0);
+        uint8_t* buf = pinned[slot] + (k & 1) * half;
+        // the half is free once the copy issued two chunks ago has finished
+        if (k >= 2 && !hip_ok(hipEventSynchronize(done[k & 1]), "upload")) { rc = GPSPCA_EDEVICE; break; }
+        float* hb = reinterpret_cast<float*>(buf);
+        for (int64_t c = 0; c < nc; ++c)
+            std::memcpy(hb + c * ldc, M.host + (c0 + c) * M.ld, sizeof(float) * M.p);
+        if (f32) {
+            if (!hip_ok(hipMemcpyAsync(dst + sizeof(float) * c0 * M.lda_dev, buf,
+                                       sizeof(float) * (size_t)(nc * ldc), hipMemcpyHostToDevice, st),
+                        "upload")) { rc = GPSPCA_EDEVICE; break; }
+        } else {
+            uint8_t* stage = arena + stage_off[slot];
+            if (!hip_ok(hipMemcpyAsync(stage, buf, sizeof(float) * (size_t)(nc * ldc),
+                                       hipMemcpyHostToDevice, st),
+                        "upload") ||
+                !hip_ok(launch_quantize(reinterpret_cast<const float*>(stage), M.p, (int)M.p, nc,
                                         GPSPCA_BF16, dst + sizeof(uint16_t) * c0 * M.lda_dev,
                                         M.lda_dev, nullptr, st),
-                        "quantize"))
-                return GPSPCA_EDEVICE;
-            // the staging area is reused by the next chunk
-            if (!hip_ok(hipStreamSynchronize(st), "upload")) return GPSPCA_EDEVICE;
+                        "quantize")) { rc = GPSPCA_EDEVICE; break; }
         }
+        if (!hip_ok(hipEventRecord(done[k & 1], st), "upload")) { rc = GPSPCA_EDEVICE; break; }
     }
+    if (rc == GPSPCA_OK && !hip_ok(hipStreamSynchronize(st), "upload")) rc = GPSPCA_EDEVICE;
+    for (int h = 0; h < 2; ++h) (void)hipEventDestroy(done[h]);
+    if (rc != GPSPCA_OK) return rc;
     gpspca_matrix A;
     std::memset(&A, 0, sizeof(A));
     A.data = dst;
@@ -136,7 +162,7 @@ int Server::upload(SMatrix& M, size_t off, int slot, hipStream_t st, std::string
     A.n = M.n;
     A.lda = M.lda_dev;
     A.dtype = M.dtype;
-    const int rc = gpspca_column_norms(&A, reinterpret_cast<double*>(arena + off + M.norms_off), st);
+    rc = gpspca_column_norms(&A, reinterpret_cast<double*>(arena + off + M.norms_off), st);
     if (rc != GPSPCA_OK) {
         *err = gpspca_last_error();
         return rc;
@@ -280,14 +306,25 @@ int gpspca_server_create(void* arena, size_t arena_bytes, int slots, gpspca_serv
     const size_t managed = (arena_bytes - staging) / serve::kAlign * serve::kAlign;
     s.sched = serve::Scheduler(managed);
     for (int i = 0; i < slots; ++i) s.stage_off.push_back(managed + (size_t)i * kStageBytes);
+    auto release_all = [&s]() {
+        for (auto x : s.streams) (void)hipStreamDestroy(x);
+        for (auto h : s.pinned) (void)hipHostFree(h);
+    };
     for (int i = 0; i < slots; ++i) {
         hipStream_t st;
         e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
         if (e != hipSuccess) {
-            for (auto x : s.streams) (void)hipStreamDestroy(x);
+            release_all();
             return fail(GPSPCA_EDEVICE, hipGetErrorString(e));
         }
         s.streams.push_back(st);
+        void* h = nullptr;
+        e = hipHostMalloc(&h, kPinnedBytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            release_all();
+            return fail(GPSPCA_EDEVICE, hipGetErrorString(e));
+        }
+        s.pinned.push_back(static_cast<uint8_t*>(h));
     }
     for (int i = 0; i < slots; ++i) s.workers.emplace_back([&s, i] { s.worker(i); });
     *out = S.release();
@@ -475,6 +512,7 @@ int gpspca_server_destroy(gpspca_server* S) {
     s.cv_work.notify_all();
     for (auto& t : s.workers) t.join();
     for (auto st : s.streams) (void)hipStreamDestroy(st);
+    for (auto h : s.pinned) (void)hipHostFree(h);
     delete S;
     return GPSPCA_OK;
 }
