@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--serve-full", action="store_true",
                     help="serving mix at its full sizes (p up to 20000, n up to 200000) instead "
                          "of the default p up to 5000, n up to 50000")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default kernel configuration instead of the autotuned one")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run 3 plain device copies (x * 1) of this many MiB; their "
                          "HBM counter readings calibrate FETCH_SIZE / WRITE_SIZE")
@@ -295,6 +297,10 @@ def main():
     print(f"[bench] data ready in {prep_s:.1f}s: p={args.p} n={args.n} m={m} {args.form} "
           f"gamma={gamma:.4g}", file=sys.stderr, flush=True)
 
+    tuned = None
+    if not args.no_autotune:
+        tuned = G.autotune(Ad, form_id, m, gamma, passes=3)
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
     r, ms, kms, launches, kname = time_gpu(G, torch, Ad, form_id, m, gamma, args.steps, args.warmup)
     ms_per_step = ms / args.steps
     iters_per_s = 1000.0 / ms_per_step
@@ -326,6 +332,7 @@ def main():
                         f"{min(args.m, 8)} planted 200-sparse components, seed {args.seed}), "
                         f"gamma={frac} max||a_i||{'^2' if l0 else ''}, mu=1, tol=0 (fixed passes)",
             "p": args.p, "n": args.n, "m": m, "form": args.form, "gamma": gamma,
+            "kernel_config": tuned["choice"] if tuned else "default",
         },
         "a_stream_gbps_whole_step": a_bytes * args.steps / (ms * 1e-3) / 1e9,
         "roofline": {

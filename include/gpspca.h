@@ -202,6 +202,29 @@ int gpspca_quantize(const gpspca_matrix* A, int to, void* out, int64_t ldq, floa
                     void* stream);
 
 /*
+ * Autotuner of the correlation kernel.  Times every candidate configuration
+ * for this problem (kernel variant: LDS-staged or register-direct matrix-core
+ * kernel, or X-in-registers VALU kernel; LDS stages; workgroups per CU) over
+ * `passes` passes of the iteration from the feasible start X0 (device p x m,
+ * leading dim p), and records the fastest in a process-wide table (thread-safe)
+ * that every later plan with the same storage type, m, p, n, alignment and kind
+ * (single problem, or a gamma path when form is SL1/SL0 and m > 1) uses.
+ * Environment overrides (GPSPCA_CORR_KERNEL, GPSPCA_MFMA_STAGES,
+ * GPSPCA_MFMA_WAVES_PER_CU) still take precedence.  Configurations whose
+ * workspace exceeds ws_bytes are skipped; gpspca_workspace_bytes (or
+ * gpspca_path_workspace_bytes) covers all of them.  A tuned configuration
+ * changes results only within FP32 rounding (every configuration reduces in a
+ * fixed order, so each is deterministic).  Outputs (host, may be NULL): the
+ * number of configurations timed, the best time per pass (ms) and a short
+ * description of the chosen configuration.  Synchronizes `stream`.
+ */
+int gpspca_autotune(const gpspca_matrix* A, int form, int m, double gamma, const float* X0,
+                    int passes, void* workspace, size_t ws_bytes, void* stream,
+                    int* n_timed, double* best_ms, char* best_desc, size_t desc_len);
+/* Forget every tuned configuration (later plans use the defaults again). */
+int gpspca_autotune_clear(void);
+
+/*
  * Column norms ||a_i||_2 of A (FP64 accumulation) into device `norms` (n doubles).
  * Stream-ordered; does not synchronize.
  */

@@ -54,6 +54,8 @@ SIGNATURES = {
     "gpspca_refine_path": (_I, [_MP, _I, _I, _P, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P,
                                 _P]),
     "gpspca_quantize": (_I, [_MP, _I, _P, _I64, _P, _P]),
+    "gpspca_autotune": (_I, [_MP, _I, _I, _D, _P, _I, _P, _SZ, _P, _P, _P, ctypes.c_char_p, _SZ]),
+    "gpspca_autotune_clear": (_I, []),
     "gpspca_last_error": (ctypes.c_char_p, []),
     "gpspca_version": (ctypes.c_char_p, []),
     "gpspca_profile_enable": (_I, [_I]),

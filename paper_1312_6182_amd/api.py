@@ -317,3 +317,35 @@ def refine_path(A: torch.Tensor, form: int, gammas: Sequence[float], support: to
     traces = [list(tr[k * max_iter:k * max_iter + nit[k]]) for k in range(K)]
     return PathResult(X=Xt.t(), Z=Zt.t(), support=sup, traces=traces, n_iter=list(nit),
                       status=list(sts), rc=rc)
+
+
+def autotune(A: torch.Tensor, form: int, m: int, gamma: float, X0: Optional[torch.Tensor] = None,
+             passes: int = 3, col_scale: Optional[torch.Tensor] = None,
+             stream: Optional[torch.cuda.Stream] = None) -> dict:
+    """Time the correlation-kernel configurations for this problem and record the
+    fastest for later solves (gpspca_autotune).  X0 (p, m) defaults to the first m
+    columns of the identity; form SL1/SL0 with m > 1 tunes a gamma path."""
+    lib = L.load()
+    M = matrix(A, col_scale)
+    p, n = A.shape
+    if X0 is None:
+        X0 = torch.zeros((p, m), dtype=torch.float32, device=A.device)
+        X0[torch.arange(m), torch.arange(m)] = 1.0
+    X0c = X0.reshape(p, -1).t().contiguous().to(torch.float32)
+    path = form in (L.SL1, L.SL0) and m > 1
+    nb = (lib.gpspca_path_workspace_bytes(ctypes.byref(M), m, passes + 1) if path
+          else lib.gpspca_workspace_bytes(ctypes.byref(M), form, m, passes + 1))
+    if nb == 0:
+        raise L.GpspcaError(L.EINVAL, L.last_error())
+    ws = _workspace(int(nb), A.device)
+    nt = ctypes.c_int(0)
+    best = ctypes.c_double(0.0)
+    desc = ctypes.create_string_buffer(128)
+    L.check(lib.gpspca_autotune(ctypes.byref(M), form, m, float(gamma), X0c.data_ptr(), passes,
+                                ws.data_ptr(), ws.numel(), _stream_ptr(stream), ctypes.byref(nt),
+                                ctypes.byref(best), desc, 128), "gpspca_autotune")
+    return {"timed": nt.value, "best_ms_per_pass": best.value, "choice": desc.value.decode()}
+
+
+def autotune_clear() -> None:
+    L.load().gpspca_autotune_clear()

@@ -16,7 +16,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -105,9 +107,48 @@ int check_problem(const gpspca_matrix* A, int form, int m, double gamma, const d
     return GPSPCA_OK;
 }
 
+// ------------------------------------------------------------------ tuning
+// Configurations chosen by gpspca_autotune, per (storage, m, p, n, vector
+// alignment, gamma path); consulted by every plan after the environment
+// overrides (GPSPCA_CORR_KERNEL, GPSPCA_MFMA_STAGES, GPSPCA_MFMA_WAVES_PER_CU).
+struct TuneKey {
+    int dtype, m, vec, path;
+    int64_t p, n;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(dtype, m, vec, path, p, n) < std::tie(o.dtype, o.m, o.vec, o.path, o.p, o.n);
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, Tune> g_tune;
+
+static TuneKey tune_key(const gpspca_matrix* A, int m, int path) {
+    const int vec = ((A->lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A->data) & 15) == 0);
+    return TuneKey{A->dtype, m, vec, path, A->p, A->n};
+}
+
+static bool tune_lookup(const TuneKey& k, Tune* t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(k);
+    if (it == g_tune.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+static Tune env_tune() {
+    Tune t{kTuneDefault, 0, 0};
+    if (const char* f = std::getenv("GPSPCA_CORR_KERNEL")) {
+        const std::string fk = f;
+        t.kernel = fk == "mfma" ? kTuneMfma : fk == "vx" ? kTuneVx : fk == "valu" ? kTuneValu
+                 : fk == "rd" ? kTuneRd : fk == "mv" ? -1 : kTuneDefault;
+    }
+    if (const char* e = std::getenv("GPSPCA_MFMA_STAGES")) t.stages = std::atoi(e);
+    if (const char* e = std::getenv("GPSPCA_MFMA_WAVES_PER_CU")) t.waves = std::atoi(e);
+    return t;
+}
+
 // ----------------------------------------------------------------------- plan
 static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int ncu, Plan* pl,
-                      int path = 0, int restricted = 0) {
+                      int path = 0, int restricted = 0, const Tune* force = nullptr) {
     std::memset(pl, 0, sizeof(Plan));
     pl->path = path;
     pl->restricted = restricted;
@@ -141,25 +182,38 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         pl->npart = pl->m1_grid;
         pl->nwave_part = pl->m1_grid;
     } else {
-        // correlation kernel: register-resident X for m <= 4, matrix cores otherwise
-        // (GPSPCA_CORR_KERNEL=vx|mv|mfma|valu forces one, for tests and benchmarks)
-        const char* force = (f32 && !restricted) ? std::getenv("GPSPCA_CORR_KERNEL") : nullptr;
-        const std::string fk = force ? force : (restricted ? "valu" : "");
-        const bool vx_ok = pl->vec4 && m >= 2 && m <= 8 && A->p <= 10240 && A->p >= 4 && !path;
-        const bool mv_ok = pl->vec4 && m <= 16 && A->p >= 4;
-        if (fk == "vx" && vx_ok) pl->use_vx = 1;
-        else if (fk == "mv" && mv_ok) pl->use_mv = 1;
-        else if (fk == "mfma" && pl->vec4) pl->use_mfma = 1;
-        else if (fk == "rd" && pl->vec4) pl->use_mfma = pl->use_rd = 1;
-        else if (fk == "valu") {}
+        // correlation kernel.  Choice: an explicit configuration (the autotuner
+        // trying candidates), else the environment (tests, benchmarks), else the
+        // autotuner's table, else the measured default -- register-resident X
+        // for m <= 4, matrix cores otherwise.
+        Tune tn{kTuneDefault, 0, 0};
+        if (force) {
+            tn = *force;
+        } else if (!restricted) {
+            tn = env_tune();
+            Tune tt;
+            if (tn.kernel == kTuneDefault && tn.stages == 0 && tn.waves == 0 &&
+                tune_lookup(tune_key(A, m, path), &tt))
+                tn = tt;
+        }
+        const bool vx_ok = f32 && pl->vec4 && m >= 2 && m <= 8 && A->p <= 10240 && A->p >= 4 && !path;
+        const bool mv_ok = f32 && pl->vec4 && m <= 16 && A->p >= 4;
+        if (restricted) {}
         else if (!f32) pl->use_q = 1;
+        else if (tn.kernel == -1 && mv_ok) pl->use_mv = 1;
+        else if (tn.kernel == kTuneVx && vx_ok) pl->use_vx = 1;
+        else if (tn.kernel == kTuneMfma && pl->vec4) pl->use_mfma = 1;
+        else if (tn.kernel == kTuneRd && pl->vec4) pl->use_mfma = pl->use_rd = 1;
+        else if (tn.kernel == kTuneValu) {}
         else if (vx_ok && m <= 4) pl->use_vx = 1;
         else pl->use_mfma = pl->vec4;
         if (pl->use_q) {
             // 16/8-bit storage: bfloat16 matrix cores, one wavefront per workgroup
             pl->corr_M = 16;
-            const int per_cu = corr_q_blocks_per_cu(A->dtype, m);
-            int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, cdiv(A->n, 16));
+            pl->mfma_stages = corr_q_stages(A->dtype, m, tn.stages);
+            const int fit = corr_q_blocks_per_cu(A->dtype, m, pl->mfma_stages);
+            pl->waves_per_cu = std::min(fit, tn.waves > 0 ? tn.waves : 4);
+            int64_t grid = std::min<int64_t>((int64_t)ncu * pl->waves_per_cu, cdiv(A->n, 16));
             pl->corr_grid = (int)std::max<int64_t>(1, grid);
             pl->nwave_part = pl->corr_grid;
         } else if (pl->use_vx) {
@@ -172,16 +226,17 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
             pl->corr_grid = (int)std::max<int64_t>(1, grid);
             pl->nwave_part = pl->corr_grid;
         } else if (pl->use_mfma || pl->use_mv) {
-            // one wavefront per workgroup; as many per CU as the LDS stages allow
+            // one wavefront per workgroup; 4 per CU by default (a fifth wave per
+            // CU, or a sixth, was measured slower), never more than LDS allows
             pl->corr_M = 16;
-            pl->mfma_stages = corr_mfma_stages(m);
-            pl->rd_depth = corr_rd_depth();
-            int per_cu = pl->use_mv ? 4 : corr_mfma_blocks_per_cu(m, pl->mfma_stages);
-            if (pl->use_rd) {
-                per_cu = 4;
-                if (const char* w = std::getenv("GPSPCA_MFMA_WAVES_PER_CU"))
-                    per_cu = std::max(1, std::atoi(w));
-            }
+            pl->mfma_stages = (m <= 16) ? ((tn.stages >= 2 && tn.stages <= 4) ? tn.stages : 4)
+                                        : (m <= 32 ? 3 : 2);
+            pl->rd_depth = (tn.stages == 2 || tn.stages == 3 || tn.stages == 6) ? tn.stages : 4;
+            int per_cu = tn.waves > 0 ? tn.waves : 4;
+            if (!pl->use_rd && !pl->use_mv)
+                per_cu = std::min(per_cu, corr_mfma_blocks_per_cu(m, pl->mfma_stages));
+            if (pl->use_mv) per_cu = 4;
+            pl->waves_per_cu = per_cu;
             int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, cdiv(A->n, 16));
             pl->corr_grid = (int)std::max<int64_t>(1, grid);
             pl->nwave_part = pl->corr_grid;
@@ -247,6 +302,47 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->o_xil0 = take(xil ? sizeof(float) * L * (size_t)pl->mpad : 1);
     pl->o_xil1 = take(xil ? sizeof(float) * L * (size_t)pl->mpad : 1);
     pl->total = o;
+}
+
+// Configurations the autotuner tries for this problem (the default first).
+static std::vector<Tune> tune_candidates(const gpspca_matrix* A, int m, int path) {
+    std::vector<Tune> c;
+    c.push_back(Tune{kTuneDefault, 0, 0});
+    const bool vec = ((A->lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A->data) & 15) == 0);
+    if (A->dtype != GPSPCA_F32) {
+        c.push_back(Tune{kTuneMfma, 2, 4});
+        c.push_back(Tune{kTuneMfma, 3, 4});
+        return c;
+    }
+    if (m == 1 && !path && A->p <= 20480) return c;  // the fused single-unit pass
+    if (!vec) return c;
+    if (m <= 16) {
+        for (int st = 2; st <= 4; ++st) c.push_back(Tune{kTuneMfma, st, 4});
+        c.push_back(Tune{kTuneMfma, 2, 8});
+    } else {
+        c.push_back(Tune{kTuneMfma, 0, 4});
+    }
+    c.push_back(Tune{kTuneRd, 4, 4});
+    if (m >= 2 && m <= 8 && A->p <= 10240 && !path) c.push_back(Tune{kTuneVx, 0, 0});
+    return c;
+}
+
+// Workspace that every configuration of the problem fits in (tuned plans
+// change the partial counts).
+static size_t workspace_all(const gpspca_matrix* A, int form, int m, int max_iter, int ncu,
+                            int path) {
+    size_t mx = 0;
+    for (const Tune& t : tune_candidates(A, m, path)) {
+        Plan pl;
+        make_plan(A, form, m, max_iter, ncu, &pl, path, 0, &t);
+        mx = std::max(mx, pl.total);
+    }
+    if (A->dtype == GPSPCA_F32) {
+        Plan pr;  // frozen-support passes (refinement) on the same matrix
+        make_plan(A, form, m, max_iter, ncu, &pr, path, 1);
+        mx = std::max(mx, pr.total);
+    }
+    return mx;
 }
 
 struct Ptrs {
@@ -656,12 +752,7 @@ size_t gpspca_workspace_bytes(const gpspca_matrix* A, int form, int m, int max_i
     }
     int ncu = 0;
     if (device_cus(&ncu) != GPSPCA_OK) return 0;
-    Plan pl;
-    make_plan(A, form, m, max_iter, ncu, &pl);
-    if (A->dtype != GPSPCA_F32) return pl.total;
-    Plan pr;  // frozen-support passes (gpspca_refine) on the same matrix
-    make_plan(A, form, m, max_iter, ncu, &pr, 0, 1);
-    return std::max(pl.total, pr.total);
+    return workspace_all(A, form, m, max_iter, ncu, 0);
 }
 
 int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
@@ -750,11 +841,7 @@ size_t gpspca_path_workspace_bytes(const gpspca_matrix* A, int K, int max_iter) 
     }
     int ncu = 0;
     if (device_cus(&ncu) != GPSPCA_OK) return 0;
-    Plan pl;
-    make_plan(A, GPSPCA_BL1, K, max_iter, ncu, &pl, 1);
-    Plan pr;
-    make_plan(A, GPSPCA_BL1, K, max_iter, ncu, &pr, 1, 1);
-    return std::max(pl.total, pr.total);
+    return workspace_all(A, GPSPCA_BL1, K, max_iter, ncu, 1);
 }
 
 int gpspca_solve_path(const gpspca_matrix* A, int form, int K, const double* gammas,
@@ -799,6 +886,124 @@ int gpspca_quantize(const gpspca_matrix* A, int to, void* out, int64_t ldq, floa
         return fail(GPSPCA_EINVAL, "F8E4M3 needs col_scale");
     GPSPCA_HIP(launch_quantize(static_cast<const float*>(A->data), A->lda, (int)A->p, A->n, to,
                                out, ldq, col_scale, static_cast<hipStream_t>(stream)));
+    return GPSPCA_OK;
+}
+
+}  // extern "C"
+
+namespace gpspca {
+
+// Time `passes` passes of configuration `tn` (after one untimed pass) from the
+// feasible start X0.  Returns GPSPCA_ENOMEM when the workspace is too small.
+static int time_config(const gpspca_matrix* A, int pform, int m, double gamma, int path,
+                       const Tune& tn, const float* X0, int passes, void* ws, size_t ws_bytes,
+                       hipStream_t st, int ncu, float* ms) {
+    Plan pl;
+    make_plan(A, pform, m, passes + 1, ncu, &pl, path, 0, &tn);
+    if (ws_bytes < pl.total) return GPSPCA_ENOMEM;
+    const Ptrs P = carve(pl, ws);
+    std::vector<double> gam(m, gamma);
+    const PassParams pp = make_params(A, pl, gamma, nullptr, path ? gam.data() : nullptr);
+    GPSPCA_HIP(launch_ctrl_reset(P.ctrl, passes + 1, 0.0, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
+    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad, st));
+    if (path) GPSPCA_HIP(launch_fill_zero(P.pstate, sizeof(PathState) * m, st));
+    GPSPCA_HIP(launch_load_g64(pl, X0, (int)A->p, P.g64, st));
+    if (path) {
+        GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 2, P.g64, P.gram, P.ctrl, st));
+        GPSPCA_HIP(launch_project_diag(pl, P.gram, P.coef, P.ctrl, st));
+    } else {
+        GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
+        GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
+    }
+    GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
+    if (pl.use_mfma || pl.use_q) {
+        GPSPCA_HIP(launch_fill_zero(P.xil[1], sizeof(float) * pl.ldx * pl.mpad, st));
+        GPSPCA_HIP(launch_x_interleave(pl, P.x[0], P.xil[0], st));
+    }
+    TimedLaunches tl;
+    int rc = enqueue_pass(pl, pp, P, 0, st, tl);
+    if (rc) return rc;
+    hipEvent_t a = nullptr, b = nullptr;
+    GPSPCA_HIP(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(GPSPCA_EDEVICE, hipGetErrorString(e));
+    }
+    e = hipEventRecord(a, st);
+    for (int k = 1; k <= passes && e == hipSuccess && rc == GPSPCA_OK; ++k)
+        rc = enqueue_pass(pl, pp, P, k, st, tl);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(GPSPCA_EDEVICE, hipGetErrorString(e));
+    *ms /= (float)passes;
+    return GPSPCA_OK;
+}
+
+static std::string tune_text(const Plan& pl) {
+    char b[96];
+    const char* k = pl.fused_m1 ? "k_pass_m1" : pl.use_vx ? "k_corr_vx" : pl.use_rd ? "k_corr_rd"
+                  : pl.use_q ? "k_corr_q" : pl.use_mfma ? "k_corr_mfma" : pl.use_mv ? "k_corr_mv"
+                  : "k_corr";
+    std::snprintf(b, sizeof(b), "%s stages=%d waves_per_cu=%d grid=%d", k, pl.mfma_stages,
+                  pl.waves_per_cu, pl.corr_grid);
+    return b;
+}
+
+}  // namespace gpspca
+
+extern "C" {
+
+int gpspca_autotune(const gpspca_matrix* A, int form, int m, double gamma, const float* X0,
+                    int passes, void* workspace, size_t ws_bytes, void* stream,
+                    int* n_timed, double* best_ms, char* best_desc, size_t desc_len) {
+    const int path = (form == GPSPCA_SL1 || form == GPSPCA_SL0) && m > 1;
+    int rc = path ? check_matrix(A) : check_problem(A, form, m, gamma, nullptr);
+    if (rc) return rc;
+    if (path && (m > kMaxM || m > A->p)) return fail(GPSPCA_EINVAL, "need K <= GPSPCA_MAX_M and K <= p");
+    if (!std::isfinite(gamma) || gamma < 0.0) return fail(GPSPCA_EINVAL, "gamma must be finite and >= 0");
+    if (!X0) return fail(GPSPCA_EINVAL, "X0 is NULL");
+    if (passes < 1 || passes > 1000) return fail(GPSPCA_EINVAL, "need 1 <= passes <= 1000");
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(GPSPCA_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    int ncu = 0;
+    rc = device_cus(&ncu);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int pform = path ? (form == GPSPCA_SL0 ? GPSPCA_BL0 : GPSPCA_BL1) : form;
+    const std::vector<Tune> cand = tune_candidates(A, m, path);
+    int timed = 0, best = -1;
+    float best_t = 0.f;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        float t = 0.f;
+        rc = time_config(A, pform, m, gamma, path, cand[i], X0, passes, workspace, ws_bytes, st,
+                         ncu, &t);
+        if (rc == GPSPCA_ENOMEM) continue;
+        if (rc) return rc;
+        ++timed;
+        if (best < 0 || t < best_t) { best = (int)i; best_t = t; }
+    }
+    if (best < 0) return fail(GPSPCA_ENOMEM, "workspace too small for every configuration");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(A, m, path)] = cand[best];
+    }
+    Plan pl;
+    make_plan(A, pform, m, passes + 1, ncu, &pl, path, 0, &cand[best]);
+    if (n_timed) *n_timed = timed;
+    if (best_ms) *best_ms = best_t;
+    if (best_desc && desc_len) std::snprintf(best_desc, desc_len, "%s", tune_text(pl).c_str());
+    return GPSPCA_OK;
+}
+
+int gpspca_autotune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
     return GPSPCA_OK;
 }
 

@@ -53,6 +53,14 @@ struct PassParams {
     int64_t mask_words;
 };
 
+// A configuration of the correlation kernel: the autotuner's unit of choice.
+enum TuneKernel { kTuneDefault = 0, kTuneMfma = 1, kTuneVx = 2, kTuneValu = 3, kTuneRd = 4 };
+struct Tune {
+    int kernel;            // TuneKernel
+    int stages;            // LDS stages (matrix-core kernels), 0 = default
+    int waves;             // workgroups per CU (matrix-core kernels), 0 = default
+};
+
 // Layout of the caller's workspace for one solve (byte offsets).
 struct Plan {
     // problem
@@ -78,7 +86,8 @@ struct Plan {
     int use_q;             // 16/8-bit storage: bfloat16 matrix-core correlation
     int restricted;        // frozen-support passes over a column list (VALU correlation)
     int use_mfma;          // block correlation on the matrix cores (LDS DMA staging)
-    int mfma_stages;       // stages in flight of the matrix-core kernel
+    int mfma_stages;       // stages in flight of the matrix-core kernels (FP32 and 16/8-bit)
+    int waves_per_cu;      // resident matrix-core workgroups per CU
     int use_rd;            // matrix-core correlation with register-direct operand loads
     int rd_depth;          // its software-pipeline depth (stages of 32 rows)
     int use_vx;            // block correlation with X held in registers (m <= 8, p <= 10240)
@@ -103,8 +112,6 @@ hipError_t launch_corr(const Plan& pl, const PassParams& pp, const float* X, flo
 hipError_t launch_corr_vx(const Plan& pl, const PassParams& pp, const float* X, float* S,
                           uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st);
-int corr_mfma_stages(int m);
-int corr_rd_depth();
 hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
                           float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st);
@@ -127,7 +134,8 @@ hipError_t launch_mask_list(const uint32_t* mask, int64_t words, int m, int64_t 
 // reduced-precision storage (k_quant.hip)
 hipError_t launch_quantize(const float* A, int64_t lda, int p, int64_t n, int to, void* out,
                            int64_t ldq, float* scale, hipStream_t st);
-int corr_q_blocks_per_cu(int dtype, int m);
+int corr_q_stages(int dtype, int m, int want);
+int corr_q_blocks_per_cu(int dtype, int m, int stages);
 hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
                          float* S,
                          uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,

@@ -502,12 +502,6 @@ __global__ __launch_bounds__(64) void k_corr_rd(PassParams pp, const float* __re
     }
 }
 
-int corr_rd_depth() {
-    const char* e = std::getenv("GPSPCA_RD_DEPTH");
-    const int v = e ? std::atoi(e) : 0;
-    return (v == 2 || v == 3 || v == 4 || v == 6) ? v : 4;
-}
-
 hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
                           float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st) {
@@ -686,17 +680,8 @@ hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, 
     return hipGetLastError();
 }
 
-// Stages in flight of the matrix-core kernel for m <= 16: 2 (20 KB of LDS per
-// wave), 3 (30 KB) or 4 (40 KB, four waves fill the 160 KB of a CU).
-int corr_mfma_stages(int m) {
-    if (m > 16) return m <= 32 ? 3 : 2;
-    const char* e = std::getenv("GPSPCA_MFMA_STAGES");
-    const int v = e ? std::atoi(e) : 0;
-    return (v >= 2 && v <= 4) ? v : 4;
-}
-
-// Waves per CU of the matrix-core kernels: what LDS allows, at most 4 (one per
-// SIMD; a fifth wave per CU lowers the DMA streaming rate).
+// Resident workgroups per CU of the matrix-core kernel for (m, stages): what
+// LDS allows (the caller caps it).
 int corr_mfma_blocks_per_cu(int m, int stages) {
     int nb = 0;
     hipError_t e;
@@ -711,10 +696,7 @@ int corr_mfma_blocks_per_cu(int m, int stages) {
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<4, 2>, 64, 0);
     (void)hipGetLastError();
-    int cap = 4;
-    if (const char* s = std::getenv("GPSPCA_MFMA_WAVES_PER_CU")) cap = std::max(1, std::atoi(s));
-    if (e != hipSuccess || nb <= 0) nb = 1;
-    return std::min(nb, cap);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,

@@ -419,11 +419,14 @@ hipError_t launch_quantize(const float* A, int64_t lda, int p, int64_t n, int to
     return hipGetLastError();
 }
 
-// Stages and component blocks of the quantized kernel for (storage, m).
-static void corr_q_shape(int st, int m, int* J, int* stages) {
-    *J = m <= 16 ? 1 : m <= 32 ? 2 : 4;
-    if (st == GPSPCA_BF16) *stages = (*J <= 2) ? 3 : 2;
-    else *stages = 2;
+// Component blocks of the quantized kernel, and the stage counts it is built
+// for: (storage, J) -> stages {2, 3} for bfloat16 with J <= 2, else {2}.
+static int q_blocks(int m) { return m <= 16 ? 1 : m <= 32 ? 2 : 4; }
+
+int corr_q_stages(int dtype, int m, int want) {
+    const int J = q_blocks(m);
+    if (dtype == GPSPCA_BF16 && J <= 2) return want == 2 ? 2 : 3;
+    return 2;
 }
 
 template <int ST, int J, int S>
@@ -435,35 +438,33 @@ static int occ_q() {
     return nb;
 }
 
-int corr_q_blocks_per_cu(int st, int m) {
-    int J, S;
-    corr_q_shape(st, m, &J, &S);
+int corr_q_blocks_per_cu(int dtype, int m, int stages) {
+    const int J = q_blocks(m);
     int nb;
-    if (st == GPSPCA_BF16) {
-        if (J == 1) nb = occ_q<kStBF16, 1, 3>();
-        else if (J == 2) nb = occ_q<kStBF16, 2, 3>();
+    if (dtype == GPSPCA_BF16) {
+        if (J == 1) nb = stages == 2 ? occ_q<kStBF16, 1, 2>() : occ_q<kStBF16, 1, 3>();
+        else if (J == 2) nb = stages == 2 ? occ_q<kStBF16, 2, 2>() : occ_q<kStBF16, 2, 3>();
         else nb = occ_q<kStBF16, 4, 2>();
     } else {
         if (J == 1) nb = occ_q<kStF8, 1, 2>();
         else if (J == 2) nb = occ_q<kStF8, 2, 2>();
         else nb = occ_q<kStF8, 4, 2>();
     }
-    int cap = 4;
-    if (const char* s = std::getenv("GPSPCA_MFMA_WAVES_PER_CU")) cap = std::max(1, std::atoi(s));
-    return std::max(1, std::min(nb, cap));
+    return std::max(1, nb);
 }
 
 hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
                          float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                          hipStream_t st) {
-    int J, Sg;
-    corr_q_shape(pl.dtype, pl.m, &J, &Sg);
+    const int J = q_blocks(pl.m), Sg = pl.mfma_stages;
     const dim3 grid(pl.corr_grid), block(64);
 #define GPSPCA_CQ(STT, JJ, SS) \
     hipLaunchKernelGGL((k_corr_q<STT, JJ, SS>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
                        nnzpart, ctrl)
     if (pl.dtype == GPSPCA_BF16) {
-        if (J == 1) GPSPCA_CQ(kStBF16, 1, 3);
+        if (J == 1 && Sg == 2) GPSPCA_CQ(kStBF16, 1, 2);
+        else if (J == 1) GPSPCA_CQ(kStBF16, 1, 3);
+        else if (J == 2 && Sg == 2) GPSPCA_CQ(kStBF16, 2, 2);
         else if (J == 2) GPSPCA_CQ(kStBF16, 2, 3);
         else GPSPCA_CQ(kStBF16, 4, 2);
     } else {

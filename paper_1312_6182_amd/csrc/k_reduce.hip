@@ -75,13 +75,23 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
                                                          double* __restrict__ l1,
                                                          const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= ne) return;
     const int y = blockIdx.y;
     const int c0 = (int)((int64_t)npart * y / nsplit), c1 = (int)((int64_t)npart * (y + 1) / nsplit);
+    // this split's flags, staged in LDS once instead of loaded per step
+    __shared__ int tf[1024];
+    const bool staged = touched && (c1 - c0) <= 1024;
+    if (staged) {
+        for (int i = threadIdx.x; i < c1 - c0; i += 256) tf[i] = touched[c0 + i];
+        __syncthreads();
+    }
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
     double s = 0.0;
     int c = c0;
-    if (!touched) {
+    if (staged) {
+        for (; c < c1; ++c)
+            if (tf[c - c0]) s += (double)gpart[(size_t)c * ne + e];
+    } else if (!touched) {
         for (; c + 4 <= c1; c += 4) {
             const float v0 = gpart[(size_t)c * ne + e];
             const float v1 = gpart[(size_t)(c + 1) * ne + e];
@@ -141,6 +151,39 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ l1, int
     __syncthreads();
     const int mm = m * m;
     double* out = gram + (size_t)blockIdx.x * 3 * mm;
+    // Few entries (small m, or the diagonal only on a gamma path): every entry
+    // is summed by S row slices in parallel, then a fixed-order tree adds the
+    // slices, instead of one thread walking all rows.
+    const int nent = (with_x == 2) ? m : 3 * mm;
+    if (nent <= 128) {
+        __shared__ double red[256];
+        int S = 1;
+        while (2 * S * nent <= (int)blockDim.x && S < 64) S *= 2;
+        if (t < nent * S) {
+            const int e = t % nent, sl = t / nent;
+            double acc = 0.0;
+            if (with_x == 2) {
+                for (int rr = sl; rr < nr; rr += S) acc += gt[rr * mp + e] * gt[rr * mp + e];
+            } else {
+                const int which = e / mm, ab = e % mm, a = ab / m, b = ab % m;
+                const double* u = which == 2 ? xt : gt;
+                const double* w = which == 0 ? gt : xt;
+                if (which == 0 || with_x == 1)
+                    for (int rr = sl; rr < nr; rr += S) acc += u[rr * mp + a] * w[rr * mp + b];
+            }
+            red[sl * nent + e] = acc;
+        }
+        __syncthreads();
+        for (int h = S / 2; h >= 1; h /= 2) {
+            if (t < nent * h) red[t] += red[t + h * nent];
+            __syncthreads();
+        }
+        if (t < nent) {
+            if (with_x == 2) out[t * m + t] = red[t];
+            else out[t] = red[t];
+        }
+        return;
+    }
     if (with_x == 2) {  // independent columns (gamma path): only ||g_j||^2 is needed
         for (int a = t; a < m; a += blockDim.x) {
             double sgg = 0.0;
@@ -178,25 +221,42 @@ hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float
 
 // Final fixed-order reduction of the per-row-block Gram partials into the
 // coefficient scratch: coef[2mm + e] = sum_g gram[g][e] for e < nent.
-__global__ __launch_bounds__(256) void k_gram_sum(int nent, int mm, int ngram,
+// Each workgroup owns EPB = 256 / S entries; S slices per entry sum the
+// partials g = sl, sl + S, ... and a fixed-order tree adds the slices.
+__global__ __launch_bounds__(256) void k_gram_sum(int nent, int mm, int ngram, int S,
                                                   const double* __restrict__ gram,
                                                   double* __restrict__ coef,
                                                   const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= nent) return;
+    __shared__ double red[256];
+    const int t = threadIdx.x, epb = 256 / S;
+    const int el = t % epb, sl = t / epb;
+    const int e = blockIdx.x * epb + el;
     double s = 0.0;
-    const double* gp = gram + e;
-#pragma unroll 8
-    for (int g = 0; g < ngram; ++g) s += gp[(size_t)g * 3 * mm];
-    coef[2 * mm + e] = s;
+    if (e < nent) {
+        const double* gp = gram + e;
+#pragma unroll 4
+        for (int g = sl; g < ngram; g += S) s += gp[(size_t)g * 3 * mm];
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int h = S / 2; h >= 1; h /= 2) {
+        if (sl < h) red[t] += red[t + h * epb];
+        __syncthreads();
+    }
+    if (sl == 0 && e < nent) coef[2 * mm + e] = red[t];
 }
 
 hipError_t launch_gram_sum(const Plan& pl, int nent, int ngram, const double* gram, double* coef,
                            const Ctrl* ctrl, hipStream_t st) {
     const int mm = pl.m * pl.m;
-    hipLaunchKernelGGL(k_gram_sum, dim3((nent + 255) / 256), dim3(256), 0, st, nent, mm, ngram,
-                       gram, coef, ctrl);
+    // slices per entry: enough to shorten the serial chains, while keeping at
+    // least a few workgroups busy
+    int S = 1;
+    while (S < 64 && S * 8 <= ngram && (nent * 2 * S + 255) / 256 <= 64) S *= 2;
+    const int epb = 256 / S;
+    hipLaunchKernelGGL(k_gram_sum, dim3((nent + epb - 1) / epb), dim3(256), 0, st, nent, mm,
+                       ngram, S, gram, coef, ctrl);
     return hipGetLastError();
 }
 
@@ -219,31 +279,54 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const float* __restrict__ g
     __shared__ double part[4][64][MP];
     __shared__ double gt[64][MP];
     __shared__ double xt[64][MP];
+    __shared__ int plist[1024];
+    __shared__ int wcnt[4];
     const int t = threadIdx.x, rr = t & 63, sl = t >> 6;
     const int r0 = blockIdx.x * 64;
     const int r = r0 + rr;
     const int nr = (p - r0 < 64) ? p - r0 : 64;
     const size_t stride = (size_t)m * ldx;
+    // ascending list of the partials that hold data (all of them without flags),
+    // built in parallel so that the sums below never wait on a flag
+    int nlist = 0;
+    for (int c0 = 0; c0 < npart; c0 += 256) {
+        const int c = c0 + t;
+        const bool on = c < npart && (!touched || touched[c] != 0);
+        const uint64_t bal = __ballot(on);
+        if ((t & 63) == 0) wcnt[sl] = __popcll(bal);
+        __syncthreads();
+        int before = nlist;
+        for (int w = 0; w < sl; ++w) before += wcnt[w];
+        if (on && before + __popcll(bal & ((1ull << (t & 63)) - 1ull)) < 1024)
+            plist[before + __popcll(bal & ((1ull << (t & 63)) - 1ull))] = c;
+        nlist += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        __syncthreads();
+    }
     double g[MB];
 #pragma unroll
     for (int j = 0; j < MB; ++j) g[j] = 0.0;
-    if (r < p) {
-        int c = sl;
-        if (!touched) {
-            for (; c + 12 < npart; c += 16) {
-                float v[4][MB];
+    if (r < p && nlist <= 1024) {
+        int e = sl;
+        for (; e + 12 < nlist; e += 16) {
+            float v[4][MB];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int j = 0; j < MB; ++j)
-                        v[u][j] = (j < m) ? gpart[(size_t)(c + 4 * u) * stride + (size_t)j * ldx + r] : 0.f;
+                for (int j = 0; j < MB; ++j)
+                    v[u][j] = (j < m) ? gpart[(size_t)plist[e + 4 * u] * stride + (size_t)j * ldx + r] : 0.f;
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int j = 0; j < MB; ++j) g[j] += (double)v[u][j];
-            }
+                for (int j = 0; j < MB; ++j) g[j] += (double)v[u][j];
         }
-        for (; c < npart; c += 4) {
+        for (; e < nlist; e += 4) {
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+                if (j < m) g[j] += (double)gpart[(size_t)plist[e] * stride + (size_t)j * ldx + r];
+        }
+    } else if (r < p) {
+        // more than 1024 partials: walk the flags directly
+        for (int c = sl; c < npart; c += 4) {
             if (touched && !touched[c]) continue;
 #pragma unroll
             for (int j = 0; j < MB; ++j)
