@@ -7,10 +7,11 @@
 // Work decomposition (one wavefront per workgroup, no barriers):
 //   - each wave owns a contiguous range of whole tiles of 16 columns (the
 //     same number of tiles, +-1, for every wave) and walks it in chunks of up
-//     to 4 tiles (64 columns); a shorter last chunk issues DMA and matrix-core
-//     work for its own tiles only;
-//   - the rows of a chunk are streamed in stages of 32 rows: 8 DMA
-//     instructions bring the 64 x 32 A tile into LDS (column-major, quads
+//     to 4 or 8 tiles (64 or 128 columns); a shorter last chunk issues DMA and
+//     matrix-core work for its own tiles only.  With 8-tile chunks a wave's
+//     columns usually fit one chunk, so X is staged once per wave;
+//   - the rows of a chunk are streamed in stages of 32 rows: 2 DMA
+//     instructions per tile bring the A stage into LDS (column-major, quads
 //     XOR-swizzled per column so that the MFMA operand reads are free of bank
 //     conflicts), 2 per component block bring the matching X rows;
 //     STAGES stages are in flight while the oldest is consumed (X comes from
@@ -91,14 +92,15 @@ __device__ __forceinline__ bool threshold_m(bool l0, double mu, double gamma, fl
 // One chunk of NT tiles of 16 columns (NT <= 4) starting at column c0: stream
 // its rows through the LDS stages, multiply on the matrix cores, threshold.
 // Columns at or past cend are clamped to cend - 1 and their results dropped.
-template <int NT, int J, int STAGES>
+template <int NT, int J, int STAGES, int TMAX>
 __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int64_t cend,
                                            uint32_t lbase, const float* const* xcol,
                                            const float* __restrict__ Xil, double* f_acc,
                                            int* nnz_acc, float* __restrict__ S,
                                            uint8_t* __restrict__ act) {
+    constexpr int AStage = TMAX * 16 * kQS * 16;   // A bytes per stage: TMAX tiles x 32 rows
     constexpr int XStageBytes = J * 2 * 1024;
-    constexpr int StageBytes = kAStageBytes + XStageBytes;
+    constexpr int StageBytes = AStage + XStageBytes;
     constexpr int ADMA = 2 * NT;           // A DMA instructions per stage (8 columns each)
     constexpr int PER = ADMA + 2 * J;      // DMA instructions per stage
     const int lane = threadIdx.x;
@@ -140,7 +142,7 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                 int q = q0 + 4 * i + lk;
                 q = (q < nqf) ? q : nqx - 1;
                 dma16(Xil + ((size_t)(jb * nqx + q) * 16 + lj) * 4,
-                      sb + kAStageBytes + 1024 * (2 * jb + i));
+                      sb + AStage + 1024 * (2 * jb + i));
             }
     };
 
@@ -181,7 +183,7 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                 av[h][t] = lds_read16(sb + a_slot(16 * t + lj, 4 * h + lk));
 #pragma unroll
             for (int jb = 0; jb < J; ++jb)
-                xv[h][jb] = lds_read16(sb + kAStageBytes + 2048u * jb +
+                xv[h][jb] = lds_read16(sb + AStage + 2048u * jb +
                                        16u * (uint32_t)((4 * h + lk) * 16 + lj));
             if (h == 0) {
                 // wait for the first half's reads before the second half's are issued
@@ -264,7 +266,9 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
 }
 
 // J: component blocks of 16 (m <= 16 J);  STAGES: stages in flight.
-template <int J, int STAGES>
+// TMAX: tiles of 16 columns per chunk (4, or 8 to stage X once per wave when
+// a wave owns up to 128 columns).
+template <int J, int STAGES, int TMAX = 4>
 __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __restrict__ X,
                                                   const float* __restrict__ Xil,
                                                   float* __restrict__ S,
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
                                                   const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     constexpr int XStageBytes = J * 2 * 1024;
-    constexpr int StageBytes = kAStageBytes + XStageBytes;
+    constexpr int StageBytes = TMAX * 16 * kQS * 16 + XStageBytes;
     __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
 
@@ -301,16 +305,30 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
 #pragma unroll
     for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
 
-    for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kT) {
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * TMAX) {
         const int64_t left = cend - c0;
-        if (left > 48)
-            mfma_chunk<4, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
-        else if (left > 32)
-            mfma_chunk<3, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
-        else if (left > 16)
-            mfma_chunk<2, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
-        else
-            mfma_chunk<1, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
+        const int nt = left >= 16 * TMAX ? TMAX : (int)((left + 15) / 16);
+#define GPSPCA_CH(NT) mfma_chunk<NT, J, STAGES, TMAX>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act)
+        if constexpr (TMAX == 8) {
+            switch (nt) {
+                case 8: GPSPCA_CH(8); break;
+                case 7: GPSPCA_CH(7); break;
+                case 6: GPSPCA_CH(6); break;
+                case 5: GPSPCA_CH(5); break;
+                case 4: GPSPCA_CH(4); break;
+                case 3: GPSPCA_CH(3); break;
+                case 2: GPSPCA_CH(2); break;
+                default: GPSPCA_CH(1); break;
+            }
+        } else {
+            switch (nt) {
+                case 4: GPSPCA_CH(4); break;
+                case 3: GPSPCA_CH(3); break;
+                case 2: GPSPCA_CH(2); break;
+                default: GPSPCA_CH(1); break;
+            }
+        }
+#undef GPSPCA_CH
     }
 
     // per-component totals over the lanes sharing lane % 16 (fixed xor order)
@@ -685,7 +703,9 @@ hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, 
 int corr_mfma_blocks_per_cu(int m, int stages) {
     int nb = 0;
     hipError_t e;
-    if (m <= 16 && stages == 4)
+    if (m <= 16 && stages == 8)  // wide chunks: 2 stages of 8 tiles
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 2, 8>, 64, 0);
+    else if (m <= 16 && stages == 4)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 4>, 64, 0);
     else if (m <= 16 && stages == 2)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 2>, 64, 0);
@@ -703,7 +723,9 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
                             float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                             hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(64);
-    if (pl.m <= 16 && pl.mfma_stages == 4)
+    if (pl.m <= 16 && pl.mfma_stages == 8)
+        hipLaunchKernelGGL((k_corr_mfma<1, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+    else if (pl.m <= 16 && pl.mfma_stages == 4)
         hipLaunchKernelGGL((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 16 && pl.mfma_stages == 2)
         hipLaunchKernelGGL((k_corr_mfma<1, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
