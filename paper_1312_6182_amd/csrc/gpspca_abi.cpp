@@ -139,7 +139,7 @@ static Tune env_tune() {
     if (const char* f = std::getenv("GPSPCA_CORR_KERNEL")) {
         const std::string fk = f;
         t.kernel = fk == "mfma" ? kTuneMfma : fk == "vx" ? kTuneVx : fk == "valu" ? kTuneValu
-                 : fk == "rd" ? kTuneRd : fk == "mv" ? -1 : kTuneDefault;
+                 : fk == "rd" ? kTuneRd : fk == "wg" ? kTuneWg : fk == "mv" ? -1 : kTuneDefault;
     }
     if (const char* e = std::getenv("GPSPCA_MFMA_STAGES")) t.stages = std::atoi(e);
     if (const char* e = std::getenv("GPSPCA_MFMA_WAVES_PER_CU")) t.waves = std::atoi(e);
@@ -204,6 +204,7 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         else if (tn.kernel == kTuneVx && vx_ok) pl->use_vx = 1;
         else if (tn.kernel == kTuneMfma && pl->vec4) pl->use_mfma = 1;
         else if (tn.kernel == kTuneRd && pl->vec4) pl->use_mfma = pl->use_rd = 1;
+        else if (tn.kernel == kTuneWg && pl->vec4) pl->use_mfma = pl->use_wg = 1;
         else if (tn.kernel == kTuneValu) {}
         else if (vx_ok && m <= 4) pl->use_vx = 1;
         else pl->use_mfma = pl->vec4;
@@ -244,6 +245,14 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
             int64_t grid = std::min<int64_t>((int64_t)ncu * per_cu, cdiv(A->n, 16));
             pl->corr_grid = (int)std::max<int64_t>(1, grid);
             pl->nwave_part = pl->corr_grid;
+            if (pl->use_wg) {
+                // one four-wave workgroup per CU (the LDS of a CU holds its stages)
+                if (m > 16) pl->mfma_stages = 8;
+                pl->waves_per_cu = 4;
+                grid = std::min<int64_t>((int64_t)ncu, cdiv(cdiv(A->n, 16), 4));
+                pl->corr_grid = (int)std::max<int64_t>(1, grid);
+                pl->nwave_part = pl->corr_grid * 4;
+            }
         } else {
             pl->corr_M = m >= 5 ? 8 : m >= 3 ? 4 : m == 2 ? 2 : 1;
             int64_t grid = std::min<int64_t>((int64_t)ncu * 2, std::max<int64_t>(1, cdiv(A->n, 32)));
@@ -324,8 +333,11 @@ static std::vector<Tune> tune_candidates(const gpspca_matrix* A, int m, int path
         for (int st = 2; st <= 4; ++st) c.push_back(Tune{kTuneMfma, st, 4});
         c.push_back(Tune{kTuneMfma, 8, 4});   // 2 stages of 8-tile chunks
         c.push_back(Tune{kTuneMfma, 2, 8});
+        c.push_back(Tune{kTuneWg, 8, 4});
+        c.push_back(Tune{kTuneWg, 4, 4});
     } else {
         c.push_back(Tune{kTuneMfma, 0, 4});
+        c.push_back(Tune{kTuneWg, 8, 4});
     }
     c.push_back(Tune{kTuneRd, 4, 4});
     if (m >= 2 && m <= 8 && A->p <= 10240 && !path) c.push_back(Tune{kTuneVx, 0, 0});
@@ -502,6 +514,9 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
         else if (pl.use_rd)
             GPSPCA_HIP(launch_corr_rd(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
                                       P.ctrl, st));
+        else if (pl.use_wg)
+            GPSPCA_HIP(launch_corr_wg(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
+                                      P.ctrl, st));
         else if (pl.use_mfma)
             GPSPCA_HIP(launch_corr_mfma(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
                                         P.ctrl, st));
@@ -583,6 +598,7 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
                            : pl.use_mv ? "k_corr_mv"
                            : pl.use_q ? "k_corr_q"
                            : pl.use_rd ? "k_corr_rd"
+                           : pl.use_wg ? "k_corr_wg"
                            : pl.use_mfma ? "k_corr_mfma" : "k_corr");
     *fin = *snap;
     return GPSPCA_OK;
@@ -953,6 +969,7 @@ static int time_config(const gpspca_matrix* A, int pform, int m, double gamma, i
 static std::string tune_text(const Plan& pl) {
     char b[96];
     const char* k = pl.fused_m1 ? "k_pass_m1" : pl.use_vx ? "k_corr_vx" : pl.use_rd ? "k_corr_rd"
+                  : pl.use_wg ? "k_corr_wg"
                   : pl.use_q ? "k_corr_q" : pl.use_mfma ? "k_corr_mfma" : pl.use_mv ? "k_corr_mv"
                   : "k_corr";
     std::snprintf(b, sizeof(b), "%s stages=%d waves_per_cu=%d grid=%d", k, pl.mfma_stages,

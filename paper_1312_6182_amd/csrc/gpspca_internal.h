@@ -54,7 +54,8 @@ struct PassParams {
 };
 
 // A configuration of the correlation kernel: the autotuner's unit of choice.
-enum TuneKernel { kTuneDefault = 0, kTuneMfma = 1, kTuneVx = 2, kTuneValu = 3, kTuneRd = 4 };
+enum TuneKernel { kTuneDefault = 0, kTuneMfma = 1, kTuneVx = 2, kTuneValu = 3, kTuneRd = 4,
+                  kTuneWg = 5 };
 struct Tune {
     int kernel;            // TuneKernel
     int stages;            // LDS stages (matrix-core kernels), 0 = default
@@ -89,6 +90,7 @@ struct Plan {
     int mfma_stages;       // stages in flight of the matrix-core kernels (FP32 and 16/8-bit)
     int waves_per_cu;      // resident matrix-core workgroups per CU
     int use_rd;            // matrix-core correlation with register-direct operand loads
+    int use_wg;            // matrix-core correlation, four waves sharing X per workgroup
     int rd_depth;          // its software-pipeline depth (stages of 32 rows)
     int use_vx;            // block correlation with X held in registers (m <= 8, p <= 10240)
     int vx_threads, vx_kq;
@@ -111,6 +113,9 @@ hipError_t launch_corr(const Plan& pl, const PassParams& pp, const float* X, flo
                        hipStream_t st);
 hipError_t launch_corr_vx(const Plan& pl, const PassParams& pp, const float* X, float* S,
                           uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st);
+hipError_t launch_corr_wg(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                          float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st);
 hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
                           float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,

@@ -349,6 +349,291 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
 }
 
 // ---------------------------------------------------------------------------
+// k_corr_wg: the matrix-core correlation with four waves per workgroup that
+// stream the same row stages in lockstep (one barrier per stage) over their
+// own columns and share each stage of X in LDS, so X costs a quarter of the
+// DMA instructions it costs one wave alone.  The workgroup owns whole tiles of
+// 16 columns; in each round every wave takes its share (up to TMAX tiles) of
+// the round's tiles.  Every wave executes the same barriers, including a wave
+// with no tiles in a round.
+//   stage: per wave TMAX tiles x 32 rows of A (2 KB per tile), then X (2 KB per
+//   component block); per stage, wave w waits for its own DMAs, then the
+//   barrier makes everyone's DMAs visible and frees the slot read in the last
+//   stage, then w issues its DMAs for the stage STAGES - 1 ahead.
+// ---------------------------------------------------------------------------
+namespace {
+template <int J>
+__device__ __forceinline__ void wg_issue_x(const float* __restrict__ Xil, int nqx, int nqf, int q0,
+                                           int wv, int lane, uint32_t xbase) {
+    const int lj = lane & 15, lk = lane >> 4;
+    if constexpr (J == 1) {
+        // two 1 KB instructions: wave w moves half of instruction w / 2
+        const int i = wv >> 1;
+        if ((lane >> 5) == (wv & 1)) {
+            int q = q0 + 4 * i + lk;
+            q = (q < nqf) ? q : nqx - 1;
+            dma16(Xil + ((size_t)q * 16 + lj) * 4, xbase + 1024 * i);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < J / 2; ++u) {
+            const int idx = wv + 4 * u;          // instruction idx = 2 jb + i
+            const int jb = idx >> 1, i = idx & 1;
+            int q = q0 + 4 * i + lk;
+            q = (q < nqf) ? q : nqx - 1;
+            dma16(Xil + ((size_t)(jb * nqx + q) * 16 + lj) * 4, xbase + 2048u * jb + 1024 * i);
+        }
+    }
+}
+}  // namespace
+
+// One round of a wave that owns NT tiles (NT = 0: it only helps with X).
+template <int NT, int J, int STAGES, int TMAX>
+__device__ __forceinline__ void wg_round(const PassParams& pp, int64_t c0, int64_t cend,
+                                         uint32_t lbase, int wv, const float* const* xcol,
+                                         const float* __restrict__ Xil, double* f_acc,
+                                         int* nnz_acc, float* __restrict__ S,
+                                         uint8_t* __restrict__ act) {
+    constexpr int AW = TMAX * 2048;                 // A bytes per wave per stage
+    constexpr int StageBytes = 4 * AW + J * 2048;
+    constexpr int ADMA = 2 * NT;
+    constexpr int XW = (J == 1) ? 1 : J / 2;        // X DMA instructions per wave
+    constexpr int PER = ADMA + XW;
+    const int lane = threadIdx.x & 63;
+    const int lj = lane & 15, lk = lane >> 4;
+    const int p = pp.p, m = pp.m;
+    const int nqf = p >> 2;
+    const int nqx = pp.ldx >> 2;
+    const int nst = (nqf + kQS - 1) / kQS;
+    const bool l0 = pp.l0 != 0;
+
+    const float* acol[ADMA > 0 ? ADMA : 1];
+    int aq[ADMA > 0 ? ADMA : 1];
+#pragma unroll
+    for (int i = 0; i < ADMA; ++i) {
+        const int L = 64 * i + lane;
+        const int cl = L / kQS;
+        aq[i] = (L % kQS) ^ ((cl >> 1) & 7);
+        int64_t col = c0 + cl;
+        col = (col < cend) ? col : cend - 1;
+        acol[i] = pp.A + col * pp.lda;
+    }
+    auto issue = [&](int st) {
+        const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+        const int q0 = kQS * st;
+#pragma unroll
+        for (int i = 0; i < ADMA; ++i) {
+            int q = q0 + aq[i];
+            q = (q < nqf) ? q : nqf - 1;
+            dma16(acol[i] + 4 * q, sb + wv * AW + 1024 * i);
+        }
+        wg_issue_x<J>(Xil, nqx, nqf, q0, wv, lane, sb + 4 * AW);
+    };
+
+    f4m acc[NT > 0 ? NT : 1][J];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4m{0.f, 0.f, 0.f, 0.f};
+
+    // the previous round's last stage may still be read by other waves
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < STAGES - 1; ++s2)
+        if (s2 < nst) issue(s2);
+
+    for (int st = 0; st < nst; ++st) {
+        // own DMAs of stage st done: later stages issued so far are st+1 .. st+STAGES-2
+        const int later = (nst - 1 - st < STAGES - 2) ? nst - 1 - st : STAGES - 2;
+        if constexpr (STAGES >= 4) {
+            if (later >= 2) wait_vmcnt<2 * PER>();
+            else if (later == 1) wait_vmcnt<PER>();
+            else wait_vmcnt<0>();
+        } else if constexpr (STAGES == 3) {
+            if (later >= 1) wait_vmcnt<PER>();
+            else wait_vmcnt<0>();
+        } else {
+            wait_vmcnt<0>();
+        }
+        __syncthreads();
+        if (st + STAGES - 1 < nst) issue(st + STAGES - 1);
+        if constexpr (NT > 0) {
+            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+            const uint32_t sa = sb + wv * AW, sx = sb + 4 * AW;
+            f4m av[2][NT], xv[2][J];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    av[h][t] = lds_read16(sa + a_slot(16 * t + lj, 4 * h + lk));
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    xv[h][jb] = lds_read16(sx + 2048u * jb + 16u * (uint32_t)((4 * h + lk) * 16 + lj));
+                if (h == 0) {
+                    wait_lgkm0();
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) after_wait(av[0][t]);
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb) after_wait(xv[0][jb]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb)
+                        acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            av[0][t][tm], xv[0][jb][tm], acc[t][jb], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            wait_lgkm0();
+#pragma unroll
+            for (int t = 0; t < NT; ++t) after_wait(av[1][t]);
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb) after_wait(xv[1][jb]);
+#pragma unroll
+            for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb)
+                        acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            av[1][t][tm], xv[1][jb][tm], acc[t][jb], 0, 0, 0);
+        }
+    }
+
+    if constexpr (NT > 0) {
+        if (p & 3) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int64_t col = c0 + 16 * t + 4 * lk + v;
+                    col = (col < cend) ? col : cend - 1;
+                    const float* ac = pp.A + col * pp.lda;
+                    for (int r = 4 * nqf; r < p; ++r) {
+                        const float a = ac[r];
+#pragma unroll
+                        for (int jb = 0; jb < J; ++jb)
+                            acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
+                    }
+                }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t col = c0 + 16 * t + 4 * lk + v;
+                const bool cvalid = col < cend;
+                bool any = false;
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb) {
+                    const int comp = 16 * jb + lj;
+                    if (cvalid && comp < m) {
+                        float s;
+                        double fv;
+                        const bool a = threshold_m(l0, pp.mu[comp], pp.gam[comp], acc[t][jb][v], s, fv);
+                        S[col * m + comp] = s;
+                        if (a) {
+                            f_acc[jb] += fv;
+                            nnz_acc[jb] += 1;
+                            any = true;
+                        }
+                    }
+                }
+                const uint64_t bal = __ballot(any);
+                if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+            }
+    }
+}
+
+template <int J, int STAGES, int TMAX>
+__global__ __launch_bounds__(256) void k_corr_wg(PassParams pp, const float* __restrict__ X,
+                                                 const float* __restrict__ Xil,
+                                                 float* __restrict__ S, uint8_t* __restrict__ act,
+                                                 double* __restrict__ fpart,
+                                                 int* __restrict__ nnzpart,
+                                                 const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int StageBytes = 4 * TMAX * 2048 + J * 2048;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
+    const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = pp.m, ldx = pp.ldx;
+    const int64_t n = pp.n;
+    const int64_t G = gridDim.x, g = blockIdx.x;
+    const int64_t ntile = (n + 15) / 16;
+    const int64_t tb = ntile * g / G, te = ntile * (g + 1) / G;   // this workgroup's tiles
+    const int lj = lane & 15;
+
+    double f_acc[J];
+    int nnz_acc[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) { f_acc[jb] = 0.0; nnz_acc[jb] = 0; }
+    const float* xcol[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
+
+    for (int64_t r0 = tb; r0 < te; r0 += 4 * TMAX) {
+        // this round: tiles r0 .. r1-1, split evenly over the four waves
+        const int64_t r1 = (r0 + 4 * TMAX < te) ? r0 + 4 * TMAX : te;
+        const int64_t nt = r1 - r0;
+        const int64_t w0 = r0 + nt * wv / 4, w1 = r0 + nt * (wv + 1) / 4;
+        const int64_t c0 = 16 * w0;
+        const int64_t cend = std::min<int64_t>(n, 16 * w1);
+        const int k = (int)(w1 - w0);
+#define GPSPCA_WG(NT) wg_round<NT, J, STAGES, TMAX>(pp, c0, cend, lbase, wv, xcol, Xil, f_acc, nnz_acc, S, act)
+        switch (k) {
+            case 0: GPSPCA_WG(0); break;
+            case 1: GPSPCA_WG(1); break;
+            case 2: GPSPCA_WG(2); break;
+            case 3: GPSPCA_WG(3); break;
+            case 4: GPSPCA_WG(4); break;
+            case 5: if constexpr (TMAX >= 5) GPSPCA_WG(5); break;
+            case 6: if constexpr (TMAX >= 6) GPSPCA_WG(6); break;
+            case 7: if constexpr (TMAX >= 7) GPSPCA_WG(7); break;
+            default: if constexpr (TMAX >= 8) GPSPCA_WG(8); break;
+        }
+#undef GPSPCA_WG
+    }
+
+    const int64_t W = G * 4, w = g * 4 + wv;
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) {
+        double f = f_acc[jb];
+        int c = nnz_acc[jb];
+        f += __shfl_xor(f, 16, 64);
+        c += __shfl_xor(c, 16, 64);
+        f += __shfl_xor(f, 32, 64);
+        c += __shfl_xor(c, 32, 64);
+        const int comp = 16 * jb + lj;
+        if (lane < 16 && comp < m) {
+            fpart[(int64_t)comp * W + w] = f;
+            nnzpart[(int64_t)comp * W + w] = c;
+        }
+    }
+}
+
+hipError_t launch_corr_wg(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                          float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st) {
+    const dim3 grid(pl.corr_grid), block(256);
+#define GPSPCA_KW(JJ, SS, TT) \
+    hipLaunchKernelGGL((k_corr_wg<JJ, SS, TT>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl)
+    if (pl.m <= 16) {
+        if (pl.mfma_stages == 4) GPSPCA_KW(1, 4, 4);
+        else GPSPCA_KW(1, 2, 8);
+    } else if (pl.m <= 32) {
+        GPSPCA_KW(2, 2, 8);
+    } else {
+        GPSPCA_KW(4, 2, 8);
+    }
+#undef GPSPCA_KW
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // k_corr_rd: the same matrix-core correlation with every operand loaded
 // straight into registers (no LDS): lane (lj, lk) loads rows 4(4h + lk) ..
 // +3 of column 16t + lj (one 16-byte load feeds four MFMAs) and the matching

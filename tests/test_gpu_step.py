@@ -98,7 +98,7 @@ def test_step_zero_gamma_dense_support(gpu, form):
     np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
 
 
-@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "rd", "valu"])
+@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "rd", "wg", "valu"])
 @pytest.mark.parametrize("form,m", [(O.BL1, 4), (O.BL0, 8)])
 def test_every_correlation_kernel(gpu, kernel, form, m, monkeypatch):
     """Force each block correlation kernel (registers-X, matrix cores through

@@ -61,6 +61,7 @@ def test_checker_flags_a_consumer_before_the_wait():
                     reason="hipcc not installed")
 @pytest.mark.parametrize("src,kernel,mfma,count", [
     ("k_corr_mfma.hip", "k_corr_mfma", "v_mfma_f32_16x16x4_f32", 4),
+    ("k_corr_mfma.hip", "k_corr_wg", "v_mfma_f32_16x16x4_f32", 3),
     ("k_quant.hip", "k_corr_q", "v_mfma_f32_16x16x32_bf16", 6),
 ])
 def test_mfma_kernel_waits_before_consuming_lds_reads(tmp_path, src, kernel, mfma, count):
