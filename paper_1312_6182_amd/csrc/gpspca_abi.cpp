@@ -563,9 +563,50 @@ static int pinned_ctrl(Ctrl** out) {
 }
 
 
+// Two consecutive passes (even then odd k: the X buffers alternate) captured
+// as one HIP graph, replayed for every pair of passes of a solve.  Capture runs
+// on a private stream (the legacy default stream cannot capture); the graph is
+// launched on the caller's stream.  Every pass kernel reads its pass index and
+// stop flag from the device control block, so a replay is the same work as
+// enqueuing the pair again.
+struct PassGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    ~PassGraph() {
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+static bool graphs_enabled() {
+    const char* e = std::getenv("GPSPCA_GRAPH");
+    return !(e && e[0] == '0');
+}
+
+static int capture_pair(const Plan& pl, const PassParams& pp, const Ptrs& P, PassGraph* pg) {
+    static thread_local hipStream_t cap = nullptr;
+    if (!cap) GPSPCA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    GPSPCA_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    TimedLaunches none;
+    int rc = enqueue_pass(pl, pp, P, 0, cap, none);
+    if (!rc) rc = enqueue_pass(pl, pp, P, 1, cap, none);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(GPSPCA_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    pg->g = g;
+    GPSPCA_HIP(hipGraphInstantiate(&pg->ex, g, nullptr, nullptr, 0));
+    return GPSPCA_OK;
+}
+
 // Enqueue passes in growing chunks; the stopping rule runs on the device and
 // the host reads the control block once per chunk (with tol = 0 every pass is
-// enqueued at once).  Returns the final control block in *fin.
+// enqueued at once).  Pairs of passes go through a captured graph when the
+// solve is long enough to repay the capture (and kernel timing is off).
+// Returns the final control block in *fin.
 static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int max_iter,
                       double tol, hipStream_t st, Ctrl* fin) {
     TimedLaunches tl;
@@ -576,11 +617,20 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
     Ctrl* snap = nullptr;
     int rc = pinned_ctrl(&snap);
     if (rc) return rc;
+    PassGraph pg;
+    const bool use_graph = !tl.on && max_iter >= 8 && graphs_enabled();
+    if (use_graph) {
+        rc = capture_pair(pl, pp, P, &pg);
+        if (rc) return rc;
+    }
     int kk = 0;
-    int chunk = (tol == 0.0) ? max_iter : 1;
+    int chunk = (tol == 0.0) ? max_iter : (use_graph ? 2 : 1);
     while (kk < max_iter) {
         const int c = std::min(chunk, max_iter - kk);
-        for (int i = 0; i < c; ++i) {
+        int i = 0;
+        if (use_graph)
+            for (; i + 1 < c; i += 2) GPSPCA_HIP(hipGraphLaunch(pg.ex, st));
+        for (; i < c; ++i) {
             rc = enqueue_pass(pl, pp, P, kk + i, st, tl);
             if (rc) return rc;
         }
