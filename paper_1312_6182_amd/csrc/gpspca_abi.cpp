@@ -146,6 +146,32 @@ static Tune env_tune() {
     return t;
 }
 
+// Active fraction (in 1/1024) of the n columns from which a pass is
+// back-projected densely on the matrix cores.  The support-restricted kernel
+// reads each active column once per group of 16 components; the dense one
+// reads every column once for all components.  The thresholds are the measured
+// crossovers on a 10000 x 100000 matrix (gamma paths and block solves with
+// 16 to 64 components at 2% to 55% activity), per storage type and number of
+// component groups (1, 2, 3, 4); for FP32 they are near 0.40, 0.22, 0.19 and
+// 0.18.  Frozen-support passes visit only listed columns and leave S of the
+// others unwritten, so they stay sparse.
+static int backproj_threshold(const gpspca_matrix* A, int m, int vec4, int restricted) {
+    const int never = 2 * 1024;
+    if (restricted || A->p < 64 || (A->dtype == GPSPCA_F32 && !vec4)) return never;
+    if (const char* e = std::getenv("GPSPCA_BACKPROJ")) {
+        const std::string v = e;
+        if (v == "dense") return 0;
+        if (v == "sparse") return never;
+        if (!v.empty() && v != "auto") return std::max(0, std::min(never, std::atoi(e)));
+    }
+    static const int thr[3][4] = {{410, 225, 195, 185},    // FP32
+                                  {185, 125, 110, 100},    // bfloat16
+                                  {195, 135, 125, 120}};   // e4m3
+    const int st = A->dtype == GPSPCA_BF16 ? 1 : A->dtype == GPSPCA_F8E4M3 ? 2 : 0;
+    const int groups = std::min(4, (m + 15) / 16);
+    return thr[st][groups - 1];
+}
+
 // ----------------------------------------------------------------------- plan
 static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int ncu, Plan* pl,
                       int path = 0, int restricted = 0, const Tune* force = nullptr) {
@@ -264,6 +290,12 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         int64_t cr = std::min<int64_t>(cdiv(A->n, 1024), std::max<int64_t>(1, (4LL * ncu) / pl->bp_rb));
         pl->bp_cr = (int)std::max<int64_t>(1, cr);
         pl->npart = pl->bp_cr;
+        pl->bp_thr = backproj_threshold(A, m, pl->vec4, restricted);
+        // the decision needs the pass's active-column count, which only the
+        // correlation kernels below keep
+        if (!(pl->use_mfma || pl->use_vx || pl->use_mv || pl->use_q)) pl->bp_thr = 2 * 1024;
+        pl->bp_depth = 3;
+        if (const char* e = std::getenv("GPSPCA_BACKPROJ_DEPTH")) pl->bp_depth = std::atoi(e);
     }
     pl->mpad = pl->fused_m1 ? 1 : (int)align_up((size_t)m, (size_t)pl->corr_M);
     const int64_t ne = (int64_t)m * pl->ldx;
@@ -684,6 +716,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
     if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
     const Ptrs P = carve(pl, workspace);
     PassParams pp = make_params(A, pl, gamma, mu, gammas);
+    pp.nact = &P.ctrl->nact;
     const int64_t words = cdiv(A->n, 32);
 
     GPSPCA_HIP(launch_ctrl_reset(P.ctrl, max_iter, tol, st));
@@ -873,7 +906,8 @@ int gpspca_step(const gpspca_matrix* A, int form, int m, double gamma, const dou
     make_plan(A, form, m, 1, ncu, &pl);
     if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
     const Ptrs P = carve(pl, workspace);
-    const PassParams pp = make_params(A, pl, gamma, mu);
+    PassParams pp = make_params(A, pl, gamma, mu);
+    pp.nact = &P.ctrl->nact;
     GPSPCA_HIP(launch_ctrl_reset(P.ctrl, 1, 0.0, st));
     GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
     GPSPCA_HIP(hipMemcpy2DAsync(P.x[0], sizeof(float) * pl.ldx, Xin, sizeof(float) * A->p,
@@ -974,7 +1008,8 @@ static int time_config(const gpspca_matrix* A, int pform, int m, double gamma, i
     if (ws_bytes < pl.total) return GPSPCA_ENOMEM;
     const Ptrs P = carve(pl, ws);
     std::vector<double> gam(m, gamma);
-    const PassParams pp = make_params(A, pl, gamma, nullptr, path ? gam.data() : nullptr);
+    PassParams pp = make_params(A, pl, gamma, nullptr, path ? gam.data() : nullptr);
+    pp.nact = &P.ctrl->nact;
     GPSPCA_HIP(launch_ctrl_reset(P.ctrl, passes + 1, 0.0, st));
     GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
     GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad, st));

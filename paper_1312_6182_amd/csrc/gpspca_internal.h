@@ -25,6 +25,8 @@ struct Ctrl {
     int degenerate_seen;   // some retraction completed dead components / F = 0
     int max_iter;
     int warm;              // the previous retraction's eigenvectors may seed the next
+    int nact;              // columns with any active component in the current pass (the
+                           // correlation kernels add to it; the stop kernel clears it)
     double tol;
     double last_F;
 };
@@ -51,6 +53,7 @@ struct PassParams {
     const int* nlist;      // device count of list entries
     const uint32_t* mask;  // mask[j * mask_words + i / 32] bit i % 32, or nullptr
     int64_t mask_words;
+    int* nact;             // &Ctrl::nact: active-column count of the pass
 };
 
 // A configuration of the correlation kernel: the autotuner's unit of choice.
@@ -74,6 +77,9 @@ struct Plan {
     int m1_threads, m1_kq, m1_grid;
     int corr_M, corr_grid; // corr kernel: padded component count and grid
     int bp_kq, bp_rb, bp_cr; // back-projection: quads per thread, row blocks, column ranges
+    int bp_thr;            // column ranges with >= bp_thr/1024 active columns are back-projected
+                           // densely on the matrix cores (> 1024: never)
+    int bp_depth;          // software-pipeline depth of the dense back-projection (steps of 4 columns)
     int npart;             // number of G partials
     int nwave_part;        // objective partial slots per component (fpart[j * nwave_part + w])
     int red_split;         // split of the partial reduction
@@ -129,6 +135,7 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
                             float* S,
                             uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                             hipStream_t st);
+int backproj_mfma_rows(int m);
 hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
                            const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                            hipStream_t st);

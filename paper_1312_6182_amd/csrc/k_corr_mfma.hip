@@ -25,6 +25,7 @@
 // LDS reads are issued with inline asm and every wait is explicit, because
 // the compiler cannot count LDS DMA completions across the loop back-edge.
 #include "gpspca_internal.h"
+#include "storage.h"
 
 #include <algorithm>
 #include <cstdlib>
@@ -98,6 +99,7 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                                            const float* __restrict__ Xil, double* f_acc,
                                            int* nnz_acc, float* __restrict__ S,
                                            uint8_t* __restrict__ act) {
+    int nact_l = 0;   // active columns written by this lane
     constexpr int AStage = TMAX * 16 * kQS * 16;   // A bytes per stage: TMAX tiles x 32 rows
     constexpr int XStageBytes = J * 2 * 1024;
     constexpr int StageBytes = AStage + XStageBytes;
@@ -261,8 +263,13 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                 }
             }
             const uint64_t bal = __ballot(any);
-            if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+            if (cvalid && lj == 0) {
+                const int fl = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                act[col] = fl;
+                nact_l += fl;
+            }
         }
+    add_active_count(nact_l, pp.nact);
 }
 
 // J: component blocks of 16 (m <= 16 J);  STAGES: stages in flight.
@@ -394,6 +401,7 @@ __device__ __forceinline__ void wg_round(const PassParams& pp, int64_t c0, int64
                                          const float* __restrict__ Xil, double* f_acc,
                                          int* nnz_acc, float* __restrict__ S,
                                          uint8_t* __restrict__ act) {
+    int nact_l = 0;   // active columns written by this lane
     constexpr int AW = TMAX * 2048;                 // A bytes per wave per stage
     constexpr int StageBytes = 4 * AW + J * 2048;
     constexpr int ADMA = 2 * NT;
@@ -543,9 +551,14 @@ __device__ __forceinline__ void wg_round(const PassParams& pp, int64_t c0, int64
                     }
                 }
                 const uint64_t bal = __ballot(any);
-                if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                if (cvalid && lj == 0) {
+                const int fl = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                act[col] = fl;
+                nact_l += fl;
+            }
             }
     }
+    add_active_count(nact_l, pp.nact);
 }
 
 template <int J, int STAGES, int TMAX>
@@ -648,6 +661,7 @@ __device__ __forceinline__ void rd_chunk(const PassParams& pp, int64_t c0, int64
                                          const float* __restrict__ Xil, double* f_acc,
                                          int* nnz_acc, float* __restrict__ S,
                                          uint8_t* __restrict__ act) {
+    int nact_l = 0;   // active columns written by this lane
     const int lane = threadIdx.x;
     const int lj = lane & 15, lk = lane >> 4;
     const int p = pp.p, m = pp.m;
@@ -755,8 +769,13 @@ __device__ __forceinline__ void rd_chunk(const PassParams& pp, int64_t c0, int64
                 }
             }
             const uint64_t bal = __ballot(any);
-            if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+            if (cvalid && lj == 0) {
+                const int fl = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                act[col] = fl;
+                nact_l += fl;
+            }
         }
+    add_active_count(nact_l, pp.nact);
 }
 
 template <int J, int D>
@@ -852,6 +871,7 @@ __global__ __launch_bounds__(64) void k_corr_mv(PassParams pp, const float* __re
                                                 double* __restrict__ fpart,
                                                 int* __restrict__ nnzpart,
                                                 const Ctrl* __restrict__ ctrl) {
+    int nact_l = 0;   // active columns written by this lane
     if (ctrl->done) return;
     __shared__ __attribute__((aligned(16))) f4m tr[kMvC * kMvQ];  // 16 KB transpose buffer
     const int lane = threadIdx.x;
@@ -962,7 +982,11 @@ __global__ __launch_bounds__(64) void k_corr_mv(PassParams pp, const float* __re
                     }
                 }
                 const uint64_t bal = __ballot(a);
-                if (col < cend && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                if (col < cend && lj == 0) {
+                    const int fl = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                    act[col] = fl;
+                    nact_l += fl;
+                }
             }
     }
     f_acc += __shfl_xor(f_acc, 16, 64);
@@ -973,6 +997,7 @@ __global__ __launch_bounds__(64) void k_corr_mv(PassParams pp, const float* __re
         fpart[(int64_t)lj * W + w] = f_acc;
         nnzpart[(int64_t)lj * W + w] = nnz_acc;
     }
+    add_active_count(nact_l, pp.nact);
 }
 
 hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, float* S,

@@ -20,6 +20,10 @@
 //  k_backproj  block forms: G partials = sum over ACTIVE columns only of
 //              a_i (mu * s_i)^T, so a sparse support costs a small fraction of a
 //              second pass; workgroups own a (row block, column range) tile.
+//  k_backproj_mfma  the same partial over all columns of a range, dense, on
+//              the matrix cores, every component group in one read of A: taken
+//              when enough of the pass's columns are active.  Both kernels take
+//              the same decision, so exactly one of them writes each partial.
 //  k_colnorm   ||a_i|| in FP64 (default start).
 #include "gpspca_internal.h"
 #include "storage.h"
@@ -407,6 +411,7 @@ __global__ __launch_bounds__(T) void k_corr_vx(PassParams pp, const float* __res
     const int p = pp.p, nqf = p >> 2, m = pp.m, ldx = pp.ldx;
     const int64_t cb = pp.n * (int64_t)blockIdx.x / gridDim.x;
     const int64_t ce = pp.n * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    int nact_t = 0;   // active columns (thread 0 writes the flags)
     const bool l0 = pp.l0 != 0;
     const int tail_t = nqf % T, tail_k = nqf / T;
     const bool has_tail = (p & 3) != 0;
@@ -485,7 +490,11 @@ __global__ __launch_bounds__(T) void k_corr_vx(PassParams pp, const float* __res
             }
         }
         const uint64_t bal = __ballot(active);
-        if (t == 0) act[c] = (bal & ((1ull << M) - 1ull)) ? 1 : 0;
+        if (t == 0) {
+            const int fl = (bal & ((1ull << M) - 1ull)) ? 1 : 0;
+            act[c] = fl;
+            nact_t += fl;
+        }
         if (more) {
 #pragma unroll
             for (int k = 0; k < KQ; ++k) a[k] = an[k];
@@ -495,6 +504,43 @@ __global__ __launch_bounds__(T) void k_corr_vx(PassParams pp, const float* __res
         fpart[(int64_t)t * gridDim.x + blockIdx.x] = f_acc;
         nnzpart[(int64_t)t * gridDim.x + blockIdx.x] = nnz_acc;
     }
+    if (t == 0 && nact_t > 0 && pp.nact) atomicAdd(pp.nact, nact_t);
+}
+
+// ---------------------------------------------------------------------------
+// Dense or sparse back-projection.  The pass is back-projected densely
+// (k_backproj_mfma) iff at least thr/1024 of all n columns are active (the
+// correlation kernels count them into *pp.nact); then every column range with
+// an active column goes to k_backproj_mfma and the others (nothing to add) to
+// k_backproj.  One decision for the whole pass: a dense range costs a full
+// read of its columns by a few waves, so a pass with only some dense ranges
+// would wait on them.  thr > kBpThrMax: never (k_backproj_mfma not launched).
+// ---------------------------------------------------------------------------
+constexpr int kBpThrMax = 1024;
+
+__device__ __forceinline__ bool pass_is_dense(const PassParams& pp, int thr) {
+    if (thr > kBpThrMax) return false;
+    const int64_t na = *pp.nact;
+    return na > 0 && na * kBpThrMax >= (int64_t)thr * pp.n;
+}
+
+// This thread's share of the active columns of [cb, ce) (flags are 0 or 1),
+// read as aligned 32-bit words of the flag array, whose allocation is padded
+// to 256 bytes; bytes outside the range are masked off.
+__device__ __forceinline__ int count_active(const uint8_t* __restrict__ act, int64_t cb,
+                                            int64_t ce, int tid, int nthreads) {
+    const uint32_t* aw = reinterpret_cast<const uint32_t*>(act);
+    const int64_t w0 = cb >> 2, w1 = (ce + 3) >> 2;
+    int c = 0;
+#pragma unroll 4
+    for (int64_t w = w0 + tid; w < w1; w += nthreads) {
+        uint32_t v = aw[w];
+        const int64_t lo = cb - 4 * w, hi = 4 * w + 4 - ce;
+        if (lo > 0) v &= 0xFFFFFFFFu << (8 * lo);
+        if (hi > 0) v &= 0xFFFFFFFFu >> (8 * hi);
+        c += __popc(v);
+    }
+    return c;
 }
 
 // ---------------------------------------------------------------------------
@@ -507,7 +553,7 @@ __global__ __launch_bounds__(256) void k_backproj(PassParams pp, int j0,
                                                   const float* __restrict__ S,
                                                   const uint8_t* __restrict__ act,
                                                   float* __restrict__ gpart,
-                                                  int* __restrict__ touched, int ncr,
+                                                  int* __restrict__ touched, int ncr, int thr,
                                                   const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     constexpr int U = 4;
@@ -519,6 +565,17 @@ __global__ __launch_bounds__(256) void k_backproj(PassParams pp, int j0,
     const int qbase = blockIdx.x * 256 * KQ2;
     const int cr = blockIdx.y;
     const int64_t cb = pp.n * cr / ncr, ce = pp.n * (cr + 1) / ncr;
+    if (pass_is_dense(pp, thr)) {
+        // ranges with an active column are k_backproj_mfma's
+        int c = count_active(act, cb, ce, t, 256);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0) wcount[wv] = c;
+        __syncthreads();
+        const int64_t total = (int64_t)wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (total > 0) return;
+        __syncthreads();
+    }
 
     f4 g[KQ2][M];
 #pragma unroll
@@ -592,6 +649,211 @@ __global__ __launch_bounds__(256) void k_backproj(PassParams pp, int j0,
         }
     }
     if (t == 0 && blockIdx.x == 0 && j0 == 0) touched[cr] = any ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_backproj_mfma: G partial of column range cr = A[:, cb:ce] W[cb:ce, :],
+// W_ij = mu_j s_ij scale_i, over every column of the range, on the matrix
+// cores (v_mfma_f32_16x16x4_f32: 16 rows x 16 components, contraction over 4
+// columns).
+//   grid (row blocks of 64 RL rows, column ranges); one wave per workgroup;
+//   every component group (G of 16) in the same read of A.
+//   Lane (li, lk) = (l % 16, l / 16) loads quad q0 + li + 16 r (r < RL) of
+//   column c + lk; that one load feeds the four tiles (r, e), whose operand row
+//   li is data row 4 (q0 + li + 16 r) + e, against the weight of column
+//   c + lk, component 16 g + li.  Accumulator register v of tile (r, e) then
+//   holds data row 4 (q0 + 16 r + 4 lk + v) + e, so each lane stores whole
+//   quads.
+//   Steps of 4 columns are software-pipelined D deep with compile-time buffer
+//   indices.  Columns past the range are clamped and weighted 0; quads past
+//   the last full one are clamped and replaced by the ragged rows or zeros
+//   (TAIL, the last row block only), so no load is conditional.
+// ---------------------------------------------------------------------------
+// Raw (undecoded) storage of one full quad, and its decoding; the tail quad
+// is kept as four raw elements.
+template <int ST> struct QuadRaw { using T = f4; };
+template <> struct QuadRaw<kStBF16> { using T = uint2; };
+template <> struct QuadRaw<kStF8> { using T = uint32_t; };
+
+template <int ST>
+__device__ __forceinline__ typename QuadRaw<ST>::T load_quad_raw(const void* colv, int q) {
+    using T = typename QuadRaw<ST>::T;
+    if constexpr (ST == kStF32)
+        return __builtin_nontemporal_load(reinterpret_cast<const f4*>(static_cast<const float*>(colv) + 4 * q));
+    else if constexpr (ST == kStBF16)
+        return *reinterpret_cast<const T*>(static_cast<const uint16_t*>(colv) + 4 * q);
+    else
+        return *reinterpret_cast<const T*>(static_cast<const uint8_t*>(colv) + 4 * q);
+}
+
+template <int ST>
+__device__ __forceinline__ f4 decode_quad(typename QuadRaw<ST>::T w) {
+    if constexpr (ST == kStF32) {
+        return w;
+    } else if constexpr (ST == kStBF16) {
+        return f4{__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                  __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u)};
+    } else {
+        const qf2 lo = e4m3_pair(w, false), hi = e4m3_pair(w, true);
+        return f4{lo.x, lo.y, hi.x, hi.y};
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ uint32_t load_elem_raw(const void* colv, int r) {
+    if constexpr (ST == kStF32) return __float_as_uint(static_cast<const float*>(colv)[r]);
+    else if constexpr (ST == kStBF16) return static_cast<const uint16_t*>(colv)[r];
+    else return static_cast<const uint8_t*>(colv)[r];
+}
+
+template <int ST>
+__device__ __forceinline__ float decode_elem(uint32_t w) {
+    if constexpr (ST == kStF32) return __uint_as_float(w);
+    else if constexpr (ST == kStBF16) return bf16_value(w);
+    else return e4m3_value(w);
+}
+
+template <int RL, int G, int D, bool TAIL, int ST>
+__device__ __forceinline__ void bpm_block(const PassParams& pp, int64_t cb, int64_t ce, int q0,
+                                          const float* __restrict__ S,
+                                          float* __restrict__ gp) {
+    using RawT = typename QuadRaw<ST>::T;
+    const int lane = threadIdx.x;
+    const int li = lane & 15, lk = lane >> 4;
+    const int p = pp.p, m = pp.m, nqf = p >> 2, nq = (p + 3) >> 2;
+    float mul[G];
+    int comp[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int j = 16 * g + li;
+        mul[g] = (j < m) ? pp.muf[j] : 0.f;
+        comp[g] = (j < m) ? j : m - 1;
+    }
+    int qa[RL];
+    bool full[RL], tailq[RL];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+        const int q = q0 + li + 16 * r;
+        qa[r] = (q < nqf) ? q : nqf - 1;
+        full[r] = q < nqf;
+        tailq[r] = q == nqf;
+    }
+    int trow[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) trow[e] = (4 * nqf + e < p) ? 4 * nqf + e : p - 1;
+
+    // loads only fill registers; decoding and weighting happen where the
+    // operands are consumed, so no wait sits between a load and its prefetch slot
+    struct Buf {
+        RawT a[RL];
+        uint32_t t[TAIL ? 4 : 1];
+        float s[G];
+        float sc;
+    };
+    auto load = [&](int64_t step, Buf& b) {
+        const int64_t c = cb + 4 * step + lk;
+        const int64_t cc = (c < ce) ? c : ce - 1;
+        const void* colv = column_ptr<ST>(pp, cc);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) b.a[r] = load_quad_raw<ST>(colv, qa[r]);
+        if constexpr (TAIL) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) b.t[e] = load_elem_raw<ST>(colv, trow[e]);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) b.s[g] = S[cc * m + comp[g]];
+        if constexpr (ST != kStF32) b.sc = column_scale(pp, cc);
+    };
+    f4 acc[RL][4][G];
+#pragma unroll
+    for (int r = 0; r < RL; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[r][e][g] = zero4();
+
+    const int64_t nstep = (ce - cb + 3) / 4;
+    Buf buf[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(d, buf[d]);
+    __builtin_amdgcn_sched_barrier(0);
+    // steps past the last one are clamped loads with zero weights
+    for (int64_t s0 = 0; s0 < nstep; s0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const Buf& b = buf[d];
+            const float valid = (cb + 4 * (s0 + d) + lk < ce) ? 1.f : 0.f;
+            float w[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                float wv = mul[g] * b.s[g];
+                if constexpr (ST != kStF32) wv *= b.sc;
+                w[g] = wv * valid;
+            }
+            f4 a[RL];
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                a[r] = decode_quad<ST>(b.a[r]);
+                if constexpr (TAIL) {
+                    f4 rag;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        rag[e] = (4 * nqf + e < p) ? decode_elem<ST>(b.t[e]) : 0.f;
+                    a[r] = full[r] ? a[r] : (tailq[r] ? rag : zero4());
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RL; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        acc[r][e][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            a[r][e], w[g], acc[r][e][g], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(s0 + d + D, buf[d]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < RL; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int qw = q0 + 16 * r + 4 * lk + v;
+            if (qw < nq) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int j = 16 * g + li;
+                    if (j < m)
+                        *reinterpret_cast<f4*>(gp + (size_t)j * pp.ldx + 4 * qw) =
+                            f4{acc[r][0][g][v], acc[r][1][g][v], acc[r][2][g][v], acc[r][3][g][v]};
+                }
+            }
+        }
+}
+
+template <int RL, int G, int D, int ST>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_backproj_mfma(PassParams pp, const float* __restrict__ S,
+                                                      const uint8_t* __restrict__ act,
+                                                      float* __restrict__ gpart,
+                                                      int* __restrict__ touched, int ncr, int thr,
+                                                      const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done || !pass_is_dense(pp, thr)) return;
+    const int lane = threadIdx.x;
+    const int cr = blockIdx.y;
+    const int64_t cb = pp.n * cr / ncr, ce = pp.n * (cr + 1) / ncr;
+    int c = count_active(act, cb, ce, lane, 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (c == 0) return;
+    const int q0 = blockIdx.x * 16 * RL;
+    float* gp = gpart + (size_t)cr * pp.m * pp.ldx;
+    if (q0 + 16 * RL > (pp.p >> 2))
+        bpm_block<RL, G, D, true, ST>(pp, cb, ce, q0, S, gp);
+    else
+        bpm_block<RL, G, D, false, ST>(pp, cb, ce, q0, S, gp);
+    if (blockIdx.x == 0 && lane == 0) touched[cr] = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -765,7 +1027,7 @@ static hipError_t launch_bp_t(const Plan& pl, const PassParams& pp, int j0, cons
                               const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                               hipStream_t st) {
     hipLaunchKernelGGL((k_backproj<M, 2, VEC, ST>), dim3(pl.bp_rb, pl.bp_cr), dim3(256), 0, st,
-                       pp, j0, S, act, gpart, touched, pl.bp_cr, ctrl);
+                       pp, j0, S, act, gpart, touched, pl.bp_cr, pl.bp_thr, ctrl);
     return hipGetLastError();
 }
 
@@ -784,10 +1046,50 @@ static hipError_t launch_bp_v(const Plan& pl, const PassParams& pp, int j0, cons
     }
 }
 
-// Component groups of at most 16 (the group's partial of g lives in registers).
+int backproj_mfma_rows(int m) { return m <= 32 ? 256 : 128; }
+
+template <int ST>
+static hipError_t launch_bpm_st(const Plan& pl, const PassParams& pp, const float* S,
+                                const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
+                                hipStream_t st) {
+    const int nq = (int)((pl.p + 3) / 4);
+    const int qb = backproj_mfma_rows(pl.m) / 4;
+    const dim3 grid((unsigned)((nq + qb - 1) / qb), pl.bp_cr), block(64);
+#define GPSPCA_BPM(RL, G, D) \
+    hipLaunchKernelGGL((k_backproj_mfma<RL, G, D, ST>), grid, block, 0, st, pp, S, act, gpart, \
+                       touched, pl.bp_cr, pl.bp_thr, ctrl)
+    const int d = pl.bp_depth;
+    if (pl.m <= 16) {
+        if (d == 2) GPSPCA_BPM(4, 1, 2);
+        else if (d == 4) GPSPCA_BPM(4, 1, 4);
+        else GPSPCA_BPM(4, 1, 3);
+    } else if (pl.m <= 32) {
+        if (d == 2) GPSPCA_BPM(4, 2, 2);
+        else if (d == 4) GPSPCA_BPM(4, 2, 4);
+        else GPSPCA_BPM(4, 2, 3);
+    } else {
+        if (d == 2) GPSPCA_BPM(2, 4, 2);
+        else GPSPCA_BPM(2, 4, 3);
+    }
+#undef GPSPCA_BPM
+    return hipGetLastError();
+}
+
+// Component groups of at most 16 (the group's partial of g lives in registers);
+// ranges with enough active columns go to the matrix-core kernel instead.
 hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
                            const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                            hipStream_t st) {
+    if (pl.bp_thr <= kBpThrMax) {
+        hipError_t e;
+        if (pl.dtype == GPSPCA_BF16)
+            e = launch_bpm_st<kStBF16>(pl, pp, S, act, gpart, touched, ctrl, st);
+        else if (pl.dtype == GPSPCA_F8E4M3)
+            e = launch_bpm_st<kStF8>(pl, pp, S, act, gpart, touched, ctrl, st);
+        else
+            e = launch_bpm_st<kStF32>(pl, pp, S, act, gpart, touched, ctrl, st);
+        if (e != hipSuccess) return e;
+    }
     for (int j0 = 0; j0 < pl.m; j0 += 16) {
         hipError_t e;
         if (pl.dtype == GPSPCA_BF16)

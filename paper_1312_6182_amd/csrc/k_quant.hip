@@ -170,6 +170,7 @@ __device__ __forceinline__ void q_chunk(const PassParams& pp, int64_t c0, int64_
                                         const float* __restrict__ Xil, double* f_acc,
                                         int* nnz_acc, float* __restrict__ S,
                                         uint8_t* __restrict__ act) {
+    int nact_l = 0;   // active columns written by this lane
     constexpr int ES = (ST == kStBF16) ? 2 : 1;     // bytes per element
     constexpr int EPS = 16 / ES;                     // rows per 16-byte slot
     constexpr int XQ = 2 * EPS;                      // X row quads per stage (8 slots)
@@ -342,8 +343,13 @@ __device__ __forceinline__ void q_chunk(const PassParams& pp, int64_t c0, int64_
                 }
             }
             const uint64_t bal = __ballot(any);
-            if (cvalid && lj == 0) act[col] = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+            if (cvalid && lj == 0) {
+                const int fl = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                act[col] = fl;
+                nact_l += fl;
+            }
         }
+    add_active_count(nact_l, pp.nact);
 }
 
 // ST: kStBF16 | kStF8;  J: component blocks of 16;  STAGES: stages in flight.

@@ -56,6 +56,7 @@ __global__ void k_ctrl_reset(Ctrl* ctrl, int max_iter, double tol) {
         ctrl->degenerate_seen = 0;
         ctrl->max_iter = max_iter;
         ctrl->warm = 0;
+        ctrl->nact = 0;
         ctrl->tol = tol;
         ctrl->last_F = 0.0;
     }
@@ -391,6 +392,10 @@ hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* tou
 // a (msz x msz, leading dim LDM, LDS) is diagonalized in place; v receives the
 // eigenvectors (columns).  With `warm`, v already holds an orthogonal V0 and a
 // holds V0^T M V0: the rotations continue from there (V <- V0 J ...).
+// A step computes its rotations (one thread per pair), then applies
+// A <- R A R^T as independent 2 x 2 blocks (rows of pair k1, columns of pair
+// k2: rows first, then columns, each block by one thread) and V <- V R^T, so
+// every entry is read and written once per step.
 // Executed by the whole workgroup.
 __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                            bool warm = false) {
@@ -435,29 +440,39 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                 prs[2 * t + 1] = qq;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int e = t; e < half * msz; e += nt) {
-                const int k = e / msz, col = e % msz;
-                const int pp = prs[2 * k], qq = prs[2 * k + 1];
-                if (qq >= msz) continue;
-                const double c = rot[2 * k], s = rot[2 * k + 1];
-                const double ap = a[pp * LDM + col], aq = a[qq * LDM + col];
-                a[pp * LDM + col] = c * ap - s * aq;
-                a[qq * LDM + col] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int e = t; e < half * msz; e += nt) {
-                const int k = e / msz, row = e % msz;
-                const int pp = prs[2 * k], qq = prs[2 * k + 1];
-                if (qq >= msz) continue;
-                const double c = rot[2 * k], s = rot[2 * k + 1];
-                const double ap = a[row * LDM + pp], aq = a[row * LDM + qq];
-                a[row * LDM + pp] = c * ap - s * aq;
-                a[row * LDM + qq] = s * ap + c * aq;
-                const double vp = v[row * LDM + pp], vq = v[row * LDM + qq];
-                v[row * LDM + pp] = c * vp - s * vq;
-                v[row * LDM + qq] = s * vp + c * vq;
+            // A <- R A R^T by 2 x 2 blocks; a pair whose second index is the
+            // padding position (odd msz) has a single row / column
+            const int nblk = half * half;
+            for (int e = t; e < nblk + msz * half; e += nt) {
+                if (e < nblk) {
+                    const int k1 = e / half, k2 = e % half;
+                    const int p1 = prs[2 * k1], q1 = prs[2 * k1 + 1];
+                    const int p2 = prs[2 * k2], q2 = prs[2 * k2 + 1];
+                    const double c1 = rot[2 * k1], s1 = rot[2 * k1 + 1];
+                    const double c2 = rot[2 * k2], s2 = rot[2 * k2 + 1];
+                    const bool h1 = q1 < msz, h2 = q2 < msz;
+                    const double x00 = a[p1 * LDM + p2];
+                    const double x01 = h2 ? a[p1 * LDM + q2] : 0.0;
+                    const double x10 = h1 ? a[q1 * LDM + p2] : 0.0;
+                    const double x11 = (h1 && h2) ? a[q1 * LDM + q2] : 0.0;
+                    // rows
+                    const double r00 = c1 * x00 - s1 * x10, r01 = c1 * x01 - s1 * x11;
+                    const double r10 = s1 * x00 + c1 * x10, r11 = s1 * x01 + c1 * x11;
+                    // columns
+                    a[p1 * LDM + p2] = c2 * r00 - s2 * r01;
+                    if (h2) a[p1 * LDM + q2] = s2 * r00 + c2 * r01;
+                    if (h1) a[q1 * LDM + p2] = c2 * r10 - s2 * r11;
+                    if (h1 && h2) a[q1 * LDM + q2] = s2 * r10 + c2 * r11;
+                } else {
+                    const int f = e - nblk;
+                    const int k = f / msz, row = f % msz;
+                    const int pp = prs[2 * k], qq = prs[2 * k + 1];
+                    if (qq >= msz) continue;
+                    const double c = rot[2 * k], s = rot[2 * k + 1];
+                    const double vp = v[row * LDM + pp], vq = v[row * LDM + qq];
+                    v[row * LDM + pp] = c * vp - s * vq;
+                    v[row * LDM + qq] = s * vp + c * vq;
+                }
             }
             __syncthreads();
         }
@@ -624,14 +639,14 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
 }
 
 // One workgroup: objective, trace, stopping rule, retraction coefficients.
-__global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
+__global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __restrict__ fpart,
                        const int* __restrict__ nnzpart, double* __restrict__ vprev,
                        double* __restrict__ trace, double* __restrict__ coef,
                        double* __restrict__ fcomp, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ StopShared ss;
-    __shared__ double red[512];
-    __shared__ int redi[512];
+    __shared__ double red[1024];
+    __shared__ int redi[1024];
     extern __shared__ double dyn[];
     double* A0 = dyn;
     double* A1 = dyn + (size_t)m * LDM;
@@ -738,7 +753,10 @@ __global__ void k_stop(int m, int nwp, const double* __restrict__ fpart,
         }
         __syncthreads();
     }
-    if (t == 0 && !ctrl->done) ctrl->k = k + 1;
+    if (t == 0 && !ctrl->done) {
+        ctrl->k = k + 1;
+        ctrl->nact = 0;   // the next pass counts its active columns afresh
+    }
 }
 
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
@@ -746,7 +764,8 @@ hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        double* vprev, Ctrl* ctrl, hipStream_t st) {
     hipError_t e = launch_gram_sum(pl, 3 * pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st);
     if (e != hipSuccess) return e;
-    const int threads = pl.m > 16 ? 512 : 256;
+    // threads: the Jacobi steps of m = 64 have 32 x 32 blocks plus 64 x 32 rotated pairs of V
+    const int threads = pl.m > 32 ? 1024 : pl.m > 16 ? 512 : 256;
     const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
@@ -849,6 +868,7 @@ __global__ void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
             ctrl->k = k + 1;
         }
         ctrl->last_F = 0.0;
+        ctrl->nact = 0;   // the next pass counts its active columns afresh
     }
 }
 

@@ -83,6 +83,15 @@ __device__ __forceinline__ qf4 load_quad_st(const void* colv, int q, int nqf, in
     }
 }
 
+// Adds the active-column counts c held by the lanes of this wave to *nact (one
+// integer atomic per wave, so the total does not depend on the order).  Called
+// by every lane of the wave.
+__device__ __forceinline__ void add_active_count(int c, int* nact) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c > 0 && nact) atomicAdd(nact, c);
+}
+
 // Scale of column `col` (1 when the matrix has none).
 __device__ __forceinline__ float column_scale(const PassParams& pp, int64_t col) {
     return pp.scale ? pp.scale[col] : 1.0f;

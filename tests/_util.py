@@ -114,3 +114,49 @@ def tie_mask(A64, X64, form, gamma, mu, safety=4.0):
     Y = A64.T @ X64
     eb = corr_band(A64, X64)
     return np.abs(margins(Y, form, gamma, mu)) <= safety * margin_band(Y, eb, form, mu)
+
+
+TNAME = {O.BF16: "bf16", O.E4M3: "e4m3"}
+
+
+def _torch_dtype(to):
+    import torch
+    return {O.BF16: torch.bfloat16, O.E4M3: torch.float8_e4m3fn}[to]
+
+
+class _TorchDtypes(dict):
+    """O.BF16 / O.E4M3 -> torch dtype, resolved on first use (torch is imported lazily)."""
+
+    def __missing__(self, to):
+        v = _torch_dtype(to)
+        self[to] = v
+        return v
+
+
+TD = _TorchDtypes()
+
+
+def q_to_device(codes, to, p):
+    """Device (p, n) view of oracle codes (ldq x n, column-major)."""
+    import torch
+    ldq, n = codes.shape
+    host = np.ascontiguousarray(codes.T)
+    t = torch.from_numpy(host.view(np.int16) if to == O.BF16 else host).cuda()
+    t = t.view(TD[to])
+    return t[:, :p].t()
+
+
+def quantized_problem(p, n, m, seed, to, ldq_pad=0, A32=None):
+    """A planted FP32 matrix (or the given one), the oracle's codes of it on the
+    device, their dequantized FP64 values and the device column scales."""
+    import torch
+    from workloads import generators as W
+    if A32 is None:
+        A32, _, _ = W.planted_block(p, n, max(1, min(m, 4)), seed, k=min(40, n // 8))
+    align = 8 if to == O.BF16 else 16
+    ldq = (p + align - 1) // align * align + ldq_pad * align
+    codes, scale = O.quantize(A32, to, ldq=ldq)
+    Adeq = O.dequantize(codes, to, scale, p)
+    Ad = q_to_device(codes, to, p)
+    sc = torch.from_numpy(scale).cuda() if to == O.E4M3 else None
+    return A32, Adeq, Ad, sc

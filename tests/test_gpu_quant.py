@@ -18,34 +18,10 @@ import torch
 import oracle as O
 from workloads import generators as W
 
-from _util import (FORM_NAMES, corr_band, fp32_round, is_l0, pick_gamma, rel, tie_mask,
-                   to_device, x_to_device)
+from _util import (FORM_NAMES, TD, TNAME, corr_band, fp32_round, is_l0, pick_gamma,
+                   quantized_problem, rel, tie_mask, to_device, x_to_device)
 
 pytestmark = pytest.mark.gpu
-
-TD = {O.BF16: torch.bfloat16, O.E4M3: torch.float8_e4m3fn}
-TNAME = {O.BF16: "bf16", O.E4M3: "e4m3"}
-
-
-def q_to_device(codes, to, p):
-    """Device (p, n) view of oracle codes (ldq x n, column-major)."""
-    ldq, n = codes.shape
-    host = np.ascontiguousarray(codes.T)
-    t = torch.from_numpy(host.view(np.int16) if to == O.BF16 else host).cuda()
-    t = t.view(TD[to])
-    return t[:, :p].t()
-
-
-def quantized_problem(p, n, m, seed, to, ldq_pad=0):
-    A32, _, _ = W.planted_block(p, n, max(1, min(m, 4)), seed, k=min(40, n // 8))
-    align = 8 if to == O.BF16 else 16
-    ldq = (p + align - 1) // align * align + ldq_pad * align
-    codes, scale = O.quantize(A32, to, ldq=ldq)
-    Adeq = O.dequantize(codes, to, scale, p)
-    Ad = q_to_device(codes, to, p)
-    sc = torch.from_numpy(scale).cuda() if to == O.E4M3 else None
-    return A32, Adeq, Ad, sc
-
 
 def _words_to_device(mask):
     """(n, m) bool -> (m, ceil(n/32)) int32 words."""
