@@ -139,7 +139,8 @@ static Tune env_tune() {
     if (const char* f = std::getenv("GPSPCA_CORR_KERNEL")) {
         const std::string fk = f;
         t.kernel = fk == "mfma" ? kTuneMfma : fk == "vx" ? kTuneVx : fk == "valu" ? kTuneValu
-                 : fk == "rd" ? kTuneRd : fk == "wg" ? kTuneWg : fk == "mv" ? -1 : kTuneDefault;
+                 : fk == "rd" ? kTuneRd : fk == "rd128" ? kTuneRd128 : fk == "wg" ? kTuneWg
+                 : fk == "mv" ? -1 : kTuneDefault;
     }
     if (const char* e = std::getenv("GPSPCA_MFMA_STAGES")) t.stages = std::atoi(e);
     if (const char* e = std::getenv("GPSPCA_MFMA_WAVES_PER_CU")) t.waves = std::atoi(e);
@@ -157,7 +158,7 @@ static Tune env_tune() {
 // others unwritten, so they stay sparse.
 static int backproj_threshold(const gpspca_matrix* A, int m, int vec4, int restricted) {
     const int never = 2 * 1024;
-    if (restricted || A->p < 64 || (A->dtype == GPSPCA_F32 && !vec4)) return never;
+    if (restricted || m <= 4 || A->p < 64 || (A->dtype == GPSPCA_F32 && !vec4)) return never;
     if (const char* e = std::getenv("GPSPCA_BACKPROJ")) {
         const std::string v = e;
         if (v == "dense") return 0;
@@ -230,6 +231,7 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         else if (tn.kernel == kTuneVx && vx_ok) pl->use_vx = 1;
         else if (tn.kernel == kTuneMfma && pl->vec4) pl->use_mfma = 1;
         else if (tn.kernel == kTuneRd && pl->vec4) pl->use_mfma = pl->use_rd = 1;
+        else if (tn.kernel == kTuneRd128 && pl->vec4) pl->use_mfma = pl->use_rd = pl->rd128 = 1;
         else if (tn.kernel == kTuneWg && pl->vec4) pl->use_mfma = pl->use_wg = 1;
         else if (tn.kernel == kTuneValu) {}
         else if (vx_ok && m <= 4) pl->use_vx = 1;
@@ -294,8 +296,6 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         // the decision needs the pass's active-column count, which only the
         // correlation kernels below keep
         if (!(pl->use_mfma || pl->use_vx || pl->use_mv || pl->use_q)) pl->bp_thr = 2 * 1024;
-        pl->bp_depth = 3;
-        if (const char* e = std::getenv("GPSPCA_BACKPROJ_DEPTH")) pl->bp_depth = std::atoi(e);
     }
     pl->mpad = pl->fused_m1 ? 1 : (int)align_up((size_t)m, (size_t)pl->corr_M);
     const int64_t ne = (int64_t)m * pl->ldx;
@@ -372,6 +372,8 @@ static std::vector<Tune> tune_candidates(const gpspca_matrix* A, int m, int path
         c.push_back(Tune{kTuneWg, 8, 4});
     }
     c.push_back(Tune{kTuneRd, 4, 4});
+    c.push_back(Tune{kTuneRd128, 4, 4});
+    c.push_back(Tune{kTuneRd128, 3, 4});
     if (m >= 2 && m <= 8 && A->p <= 10240 && !path) c.push_back(Tune{kTuneVx, 0, 0});
     return c;
 }
@@ -1053,12 +1055,13 @@ static int time_config(const gpspca_matrix* A, int pform, int m, double gamma, i
 
 static std::string tune_text(const Plan& pl) {
     char b[96];
-    const char* k = pl.fused_m1 ? "k_pass_m1" : pl.use_vx ? "k_corr_vx" : pl.use_rd ? "k_corr_rd"
+    const char* k = pl.fused_m1 ? "k_pass_m1" : pl.use_vx ? "k_corr_vx"
+                  : pl.use_rd ? (pl.rd128 ? "k_corr_rd(128-byte lines)" : "k_corr_rd")
                   : pl.use_wg ? "k_corr_wg"
                   : pl.use_q ? "k_corr_q" : pl.use_mfma ? "k_corr_mfma" : pl.use_mv ? "k_corr_mv"
                   : "k_corr";
-    std::snprintf(b, sizeof(b), "%s stages=%d waves_per_cu=%d grid=%d", k, pl.mfma_stages,
-                  pl.waves_per_cu, pl.corr_grid);
+    std::snprintf(b, sizeof(b), "%s stages=%d waves_per_cu=%d grid=%d", k,
+                  pl.use_rd ? pl.rd_depth : pl.mfma_stages, pl.waves_per_cu, pl.corr_grid);
     return b;
 }
 

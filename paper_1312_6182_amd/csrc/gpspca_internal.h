@@ -58,7 +58,7 @@ struct PassParams {
 
 // A configuration of the correlation kernel: the autotuner's unit of choice.
 enum TuneKernel { kTuneDefault = 0, kTuneMfma = 1, kTuneVx = 2, kTuneValu = 3, kTuneRd = 4,
-                  kTuneWg = 5 };
+                  kTuneWg = 5, kTuneRd128 = 6 };
 struct Tune {
     int kernel;            // TuneKernel
     int stages;            // LDS stages (matrix-core kernels), 0 = default
@@ -79,7 +79,6 @@ struct Plan {
     int bp_kq, bp_rb, bp_cr; // back-projection: quads per thread, row blocks, column ranges
     int bp_thr;            // column ranges with >= bp_thr/1024 active columns are back-projected
                            // densely on the matrix cores (> 1024: never)
-    int bp_depth;          // software-pipeline depth of the dense back-projection (steps of 4 columns)
     int npart;             // number of G partials
     int nwave_part;        // objective partial slots per component (fpart[j * nwave_part + w])
     int red_split;         // split of the partial reduction
@@ -98,6 +97,7 @@ struct Plan {
     int use_rd;            // matrix-core correlation with register-direct operand loads
     int use_wg;            // matrix-core correlation, four waves sharing X per workgroup
     int rd_depth;          // its software-pipeline depth (stages of 32 rows)
+    int rd128;             // register-direct loads of whole 128-byte lines (8 columns each)
     int use_vx;            // block correlation with X held in registers (m <= 8, p <= 10240)
     int vx_threads, vx_kq;
     int use_mv;            // block correlation on the matrix cores, A staged through registers
@@ -135,7 +135,6 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
                             float* S,
                             uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                             hipStream_t st);
-int backproj_mfma_rows(int m);
 hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
                            const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                            hipStream_t st);

@@ -655,7 +655,17 @@ hipError_t launch_corr_wg(const Plan& pl, const PassParams& pp, const float* X, 
 // last full quad are clamped and meet zero rows of X, so no load is
 // conditional and the compiler's waits stay exact.
 // ---------------------------------------------------------------------------
-template <int NT, int J, int D>
+// W128: a load instruction covers 8 columns x 128 bytes (whole cache lines)
+// instead of 16 columns x 64 bytes.  Lane l then holds quad 8 st + (l >> 3) of
+// column 16 t + (l & 7) (first load) and of column 16 t + 8 + (l & 7) (second
+// load); the MFMA operand of lane (lj, lk) for k-slot quad 8 st + 2 lk + hh is
+// rebuilt in registers with one swap of the lane halves of each 16-lane row
+// (DPP row rotation by 8) and two selects.
+__device__ __forceinline__ float swap_row_halves(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));
+}
+
+template <int NT, int J, int D, bool W128>
 __device__ __forceinline__ void rd_chunk(const PassParams& pp, int64_t c0, int64_t cend,
                                          const float* const* xcol,
                                          const float* __restrict__ Xil, double* f_acc,
@@ -670,23 +680,31 @@ __device__ __forceinline__ void rd_chunk(const PassParams& pp, int64_t c0, int64
     const int nst = (nqf + kQS - 1) / kQS;
     const bool l0 = pp.l0 != 0;
 
-    const float* colp[NT];
+    constexpr int NH = W128 ? 2 : 1;
+    const float* colp[NT][NH];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        int64_t col = c0 + 16 * t + lj;
-        col = (col < cend) ? col : cend - 1;
-        colp[t] = pp.A + col * pp.lda;
-    }
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            int64_t col = W128 ? c0 + 16 * t + 8 * h + (lane & 7) : c0 + 16 * t + lj;
+            col = (col < cend) ? col : cend - 1;
+            colp[t][h] = pp.A + col * pp.lda;
+        }
+    const bool lo8 = (lane & 8) == 0;
     f4m abuf[D][NT][2], xbuf[D][J][2];
     auto load = [&](int st, f4m(&ab)[NT][2], f4m(&xb)[J][2]) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int q = kQS * st + 4 * h + lk;
+            // A: W128 lane quad 8 st + (l >> 3) of column half h; else quad 8 st + 4 h + lk
+            const int q = W128 ? kQS * st + (lane >> 3) : kQS * st + 4 * h + lk;
             const int qa = (q < nqf) ? q : nqf - 1;
-            const int qx = (q < nqf) ? q : nqx - 1;
+            // X: the quad of k-slot lk in operand h (8 st + 2 lk + h under W128)
+            const int qk = W128 ? kQS * st + 2 * lk + h : q;
+            const int qx = (qk < nqf) ? qk : nqx - 1;
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-                ab[t][h] = __builtin_nontemporal_load(reinterpret_cast<const f4m*>(colp[t] + 4 * qa));
+                ab[t][h] = __builtin_nontemporal_load(
+                    reinterpret_cast<const f4m*>(colp[t][W128 ? h : 0] + 4 * qa));
 #pragma unroll
             for (int jb = 0; jb < J; ++jb)
                 xb[jb][h] = *reinterpret_cast<const f4m*>(
@@ -709,6 +727,19 @@ __device__ __forceinline__ void rd_chunk(const PassParams& pp, int64_t c0, int64
         for (int s0 = 0; s0 < nst; s0 += D) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
+                if constexpr (W128) {
+                    // operand 0: own first load (lj < 8) or the partner lane's second;
+                    // operand 1: the partner's first load (lj < 8) or own second
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+#pragma unroll
+                        for (int tm = 0; tm < 4; ++tm) {
+                            const float a0 = abuf[d][t][0][tm], a1 = abuf[d][t][1][tm];
+                            const float sw = swap_row_halves(lo8 ? a1 : a0);
+                            abuf[d][t][0][tm] = lo8 ? a0 : sw;
+                            abuf[d][t][1][tm] = lo8 ? sw : a1;
+                        }
+                }
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -778,7 +809,7 @@ __device__ __forceinline__ void rd_chunk(const PassParams& pp, int64_t c0, int64
     add_active_count(nact_l, pp.nact);
 }
 
-template <int J, int D>
+template <int J, int D, bool W128>
 __global__ __launch_bounds__(64) void k_corr_rd(PassParams pp, const float* __restrict__ X,
                                                 const float* __restrict__ Xil,
                                                 float* __restrict__ S, uint8_t* __restrict__ act,
@@ -803,10 +834,10 @@ __global__ __launch_bounds__(64) void k_corr_rd(PassParams pp, const float* __re
     for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
     for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kT) {
         const int64_t left = cend - c0;
-        if (left > 48) rd_chunk<4, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
-        else if (left > 32) rd_chunk<3, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
-        else if (left > 16) rd_chunk<2, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
-        else rd_chunk<1, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        if (left > 48) rd_chunk<4, J, D, W128>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 32) rd_chunk<3, J, D, W128>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 16) rd_chunk<2, J, D, W128>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else rd_chunk<1, J, D, W128>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
     }
 #pragma unroll
     for (int jb = 0; jb < J; ++jb) {
@@ -829,19 +860,23 @@ hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, 
                           hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(64);
     const int D = pl.rd_depth;
-#define GPSPCA_RD(JJ, DD) \
-    hipLaunchKernelGGL((k_corr_rd<JJ, DD>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl)
+#define GPSPCA_RD(JJ, DD, WW) \
+    hipLaunchKernelGGL((k_corr_rd<JJ, DD, WW>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
+                       nnzpart, ctrl)
+#define GPSPCA_RDW(JJ, DD) \
+    do { if (pl.rd128) GPSPCA_RD(JJ, DD, true); else GPSPCA_RD(JJ, DD, false); } while (0)
     if (pl.m <= 16) {
-        if (D == 2) GPSPCA_RD(1, 2);
-        else if (D == 3) GPSPCA_RD(1, 3);
-        else if (D == 6) GPSPCA_RD(1, 6);
-        else GPSPCA_RD(1, 4);
+        if (D == 2) GPSPCA_RDW(1, 2);
+        else if (D == 3) GPSPCA_RDW(1, 3);
+        else if (D == 6) GPSPCA_RDW(1, 6);
+        else GPSPCA_RDW(1, 4);
     } else if (pl.m <= 32) {
-        if (D <= 2) GPSPCA_RD(2, 2);
-        else GPSPCA_RD(2, 3);
+        if (D <= 2) GPSPCA_RDW(2, 2);
+        else GPSPCA_RDW(2, 3);
     } else {
-        GPSPCA_RD(4, 2);
+        GPSPCA_RDW(4, 2);
     }
+#undef GPSPCA_RDW
 #undef GPSPCA_RD
     return hipGetLastError();
 }

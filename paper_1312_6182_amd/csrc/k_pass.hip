@@ -20,10 +20,10 @@
 //  k_backproj  block forms: G partials = sum over ACTIVE columns only of
 //              a_i (mu * s_i)^T, so a sparse support costs a small fraction of a
 //              second pass; workgroups own a (row block, column range) tile.
-//  k_backproj_mfma  the same partial over all columns of a range, dense, on
-//              the matrix cores, every component group in one read of A: taken
-//              when enough of the pass's columns are active.  Both kernels take
-//              the same decision, so exactly one of them writes each partial.
+//              When enough of the pass's columns are active it instead runs
+//              the dense form: every column of each range with an active
+//              column, on the matrix cores (bpm_block), every component group
+//              in one read of A.
 //  k_colnorm   ||a_i|| in FP64 (default start).
 #include "gpspca_internal.h"
 #include "storage.h"
@@ -508,13 +508,13 @@ __global__ __launch_bounds__(T) void k_corr_vx(PassParams pp, const float* __res
 }
 
 // ---------------------------------------------------------------------------
-// Dense or sparse back-projection.  The pass is back-projected densely
-// (k_backproj_mfma) iff at least thr/1024 of all n columns are active (the
-// correlation kernels count them into *pp.nact); then every column range with
-// an active column goes to k_backproj_mfma and the others (nothing to add) to
-// k_backproj.  One decision for the whole pass: a dense range costs a full
+// Dense or sparse back-projection.  The pass is back-projected densely iff at
+// least thr/1024 of all n columns are active (the correlation kernels count
+// them into *pp.nact): then every column range with an active column is taken
+// by the dense form of k_backproj, and the others (nothing to add) by its
+// sparse form.  One decision for the whole pass: a dense range costs a full
 // read of its columns by a few waves, so a pass with only some dense ranges
-// would wait on them.  thr > kBpThrMax: never (k_backproj_mfma not launched).
+// would wait on them.  thr > kBpThrMax: never.
 // ---------------------------------------------------------------------------
 constexpr int kBpThrMax = 1024;
 
@@ -543,121 +543,14 @@ __device__ __forceinline__ int count_active(const uint8_t* __restrict__ act, int
     return c;
 }
 
-// ---------------------------------------------------------------------------
-// k_backproj: G partial of column range cr over its active columns.
-//   grid (row blocks, column ranges); 256 threads, thread t owns quads
-//   qbase + t + 256 k (k < KQ2) of the row block; U active columns per step.
-// ---------------------------------------------------------------------------
-template <int M, int KQ2, bool VEC, int ST>
-__global__ __launch_bounds__(256) void k_backproj(PassParams pp, int j0,
-                                                  const float* __restrict__ S,
-                                                  const uint8_t* __restrict__ act,
-                                                  float* __restrict__ gpart,
-                                                  int* __restrict__ touched, int ncr, int thr,
-                                                  const Ctrl* __restrict__ ctrl) {
-    if (ctrl->done) return;
-    constexpr int U = 4;
-    __shared__ int list[256];
-    __shared__ int wcount[4];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int p = pp.p, nqf = p >> 2, nq = (p + 3) >> 2, m = pp.m;
-    const int mg = (m - j0 < M) ? m - j0 : M;
-    const int qbase = blockIdx.x * 256 * KQ2;
-    const int cr = blockIdx.y;
-    const int64_t cb = pp.n * cr / ncr, ce = pp.n * (cr + 1) / ncr;
-    if (pass_is_dense(pp, thr)) {
-        // ranges with an active column are k_backproj_mfma's
-        int c = count_active(act, cb, ce, t, 256);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        if (lane == 0) wcount[wv] = c;
-        __syncthreads();
-        const int64_t total = (int64_t)wcount[0] + wcount[1] + wcount[2] + wcount[3];
-        if (total > 0) return;
-        __syncthreads();
-    }
-
-    f4 g[KQ2][M];
-#pragma unroll
-    for (int k = 0; k < KQ2; ++k)
-#pragma unroll
-        for (int j = 0; j < M; ++j) g[k][j] = zero4();
-    bool any = false;
-
-    for (int64_t base = cb; base < ce; base += 256) {
-        const int64_t i = base + t;
-        const bool fl = (i < ce) && act[i] != 0;
-        const uint64_t bal = __ballot(fl);
-        if (lane == 0) wcount[wv] = __popcll(bal);
-        __syncthreads();
-        int off = 0;
-        for (int w = 0; w < wv; ++w) off += wcount[w];
-        const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
-        if (fl) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = t;
-        __syncthreads();
-        for (int e = 0; e < total; e += U) {
-            f4 a[U][KQ2];
-            float w[U][M];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int li = (e + u < total) ? list[e + u] : list[e];
-                const int64_t col = base + li;
-                const void* colv = column_ptr<ST>(pp, col);
-                const float sc = (ST == kStF32) ? 1.0f : column_scale(pp, col);
-#pragma unroll
-                for (int j = 0; j < M; ++j)
-                    w[u][j] = (j < mg) ? pp.muf[j0 + j] * S[col * m + j0 + j] * sc : 0.f;
-#pragma unroll
-                for (int k = 0; k < KQ2; ++k) {
-                    const int q = qbase + t + 256 * k;
-                    if constexpr (ST == kStF32)
-                        a[u][k] = (q < nq) ? load_quad<VEC>(static_cast<const float*>(colv), q, nqf, p)
-                                           : zero4();
-                    else
-                        a[u][k] = (q < nq) ? load_quad_st<ST>(colv, q, nqf, p) : zero4();
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (e + u < total) {
-#pragma unroll
-                    for (int k = 0; k < KQ2; ++k)
-#pragma unroll
-                        for (int j = 0; j < M; ++j) {
-                            g[k][j].x = __builtin_fmaf(w[u][j], a[u][k].x, g[k][j].x);
-                            g[k][j].y = __builtin_fmaf(w[u][j], a[u][k].y, g[k][j].y);
-                            g[k][j].z = __builtin_fmaf(w[u][j], a[u][k].z, g[k][j].z);
-                            g[k][j].w = __builtin_fmaf(w[u][j], a[u][k].w, g[k][j].w);
-                        }
-                }
-            }
-        }
-        any = any || total > 0;
-        __syncthreads();
-    }
-    if (any) {
-        float* gp = gpart + (size_t)cr * m * pp.ldx;
-#pragma unroll
-        for (int k = 0; k < KQ2; ++k) {
-            const int q = qbase + t + 256 * k;
-            if (q < nq) {
-#pragma unroll
-                for (int j = 0; j < M; ++j)
-                    if (j < mg)
-                        *reinterpret_cast<f4*>(gp + (size_t)(j0 + j) * pp.ldx + 4 * q) = g[k][j];
-            }
-        }
-    }
-    if (t == 0 && blockIdx.x == 0 && j0 == 0) touched[cr] = any ? 1 : 0;
-}
 
 // ---------------------------------------------------------------------------
-// k_backproj_mfma: G partial of column range cr = A[:, cb:ce] W[cb:ce, :],
+// bpm_block: dense G partial of column range cr = A[:, cb:ce] W[cb:ce, :],
 // W_ij = mu_j s_ij scale_i, over every column of the range, on the matrix
 // cores (v_mfma_f32_16x16x4_f32: 16 rows x 16 components, contraction over 4
 // columns).
-//   grid (row blocks of 64 RL rows, column ranges); one wave per workgroup;
-//   every component group (G of 16) in the same read of A.
+//   grid (row blocks of 64 RL rows, four per workgroup; column ranges); every
+//   component group (G of 16) in the same read of A.
 //   Lane (li, lk) = (l % 16, l / 16) loads quad q0 + li + 16 r (r < RL) of
 //   column c + lk; that one load feeds the four tiles (r, e), whose operand row
 //   li is data row 4 (q0 + li + 16 r) + e, against the weight of column
@@ -718,7 +611,7 @@ __device__ __forceinline__ void bpm_block(const PassParams& pp, int64_t cb, int6
                                           const float* __restrict__ S,
                                           float* __restrict__ gp) {
     using RawT = typename QuadRaw<ST>::T;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int p = pp.p, m = pp.m, nqf = p >> 2, nq = (p + 3) >> 2;
     float mul[G];
@@ -833,27 +726,135 @@ __device__ __forceinline__ void bpm_block(const PassParams& pp, int64_t cb, int6
         }
 }
 
-template <int RL, int G, int D, int ST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_backproj_mfma(PassParams pp, const float* __restrict__ S,
-                                                      const uint8_t* __restrict__ act,
-                                                      float* __restrict__ gpart,
-                                                      int* __restrict__ touched, int ncr, int thr,
-                                                      const Ctrl* __restrict__ ctrl) {
-    if (ctrl->done || !pass_is_dense(pp, thr)) return;
-    const int lane = threadIdx.x;
+// ---------------------------------------------------------------------------
+// k_backproj: G partial of column range cr.
+//   grid (row blocks, column ranges); 256 threads.
+//   Sparse pass: thread t owns quads qbase + t + 256 k (k < KQ2) of the row
+//   block and adds the active columns, U per step, for components j0 .. j0+M-1.
+//   Dense pass, G = 1 (m <= 16): the workgroup's four waves take row blocks of
+//   256 rows in turn and run bpm_block over every column of a range that has
+//   an active column.  One launch serves both, so a sparse pass pays no launch
+//   for the dense code.  (m > 16: k_backproj_dense, below.)
+// ---------------------------------------------------------------------------
+template <int M, int KQ2, bool VEC, int ST, int G>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_backproj(
+                                                  PassParams pp, int j0,
+                                                  const float* __restrict__ S,
+                                                  const uint8_t* __restrict__ act,
+                                                  float* __restrict__ gpart,
+                                                  int* __restrict__ touched, int ncr, int thr,
+                                                  const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int U = 4;
+    __shared__ int list[256];
+    __shared__ int wcount[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int p = pp.p, nqf = p >> 2, nq = (p + 3) >> 2, m = pp.m;
+    const int mg = (m - j0 < M) ? m - j0 : M;
+    const int qbase = blockIdx.x * 256 * KQ2;
     const int cr = blockIdx.y;
     const int64_t cb = pp.n * cr / ncr, ce = pp.n * (cr + 1) / ncr;
-    int c = count_active(act, cb, ce, lane, 64);
+    if (pass_is_dense(pp, thr)) {
+        // dense pass: ranges with an active column are read in full
+        int c = count_active(act, cb, ce, t, 256);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if (c == 0) return;
-    const int q0 = blockIdx.x * 16 * RL;
-    float* gp = gpart + (size_t)cr * pp.m * pp.ldx;
-    if (q0 + 16 * RL > (pp.p >> 2))
-        bpm_block<RL, G, D, true, ST>(pp, cb, ce, q0, S, gp);
-    else
-        bpm_block<RL, G, D, false, ST>(pp, cb, ce, q0, S, gp);
-    if (blockIdx.x == 0 && lane == 0) touched[cr] = 1;
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0) wcount[wv] = c;
+        __syncthreads();
+        const int64_t total = (int64_t)wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (total > 0) {
+            if constexpr (G > 0) {
+                if (j0 == 0) {
+                    constexpr int RL = G <= 2 ? 4 : 2;
+                    const int nrb = (nq + 16 * RL - 1) / (16 * RL);
+                    float* gp = gpart + (size_t)cr * m * pp.ldx;
+                    for (int rb = blockIdx.x * 4 + wv; rb < nrb; rb += 4 * gridDim.x) {
+                        const int q0 = rb * 16 * RL;
+                        if (q0 + 16 * RL > nqf)
+                            bpm_block<RL, G, 3, true, ST>(pp, cb, ce, q0, S, gp);
+                        else
+                            bpm_block<RL, G, 3, false, ST>(pp, cb, ce, q0, S, gp);
+                    }
+                    if (blockIdx.x == 0 && t == 0) touched[cr] = 1;
+                }
+            }
+            return;
+        }
+        __syncthreads();
+    }
+
+    f4 g[KQ2][M];
+#pragma unroll
+    for (int k = 0; k < KQ2; ++k)
+#pragma unroll
+        for (int j = 0; j < M; ++j) g[k][j] = zero4();
+    bool any = false;
+
+    for (int64_t base = cb; base < ce; base += 256) {
+        const int64_t i = base + t;
+        const bool fl = (i < ce) && act[i] != 0;
+        const uint64_t bal = __ballot(fl);
+        if (lane == 0) wcount[wv] = __popcll(bal);
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wv; ++w) off += wcount[w];
+        const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (fl) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+        __syncthreads();
+        for (int e = 0; e < total; e += U) {
+            f4 a[U][KQ2];
+            float w[U][M];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int li = (e + u < total) ? list[e + u] : list[e];
+                const int64_t col = base + li;
+                const void* colv = column_ptr<ST>(pp, col);
+                const float sc = (ST == kStF32) ? 1.0f : column_scale(pp, col);
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    w[u][j] = (j < mg) ? pp.muf[j0 + j] * S[col * m + j0 + j] * sc : 0.f;
+#pragma unroll
+                for (int k = 0; k < KQ2; ++k) {
+                    const int q = qbase + t + 256 * k;
+                    if constexpr (ST == kStF32)
+                        a[u][k] = (q < nq) ? load_quad<VEC>(static_cast<const float*>(colv), q, nqf, p)
+                                           : zero4();
+                    else
+                        a[u][k] = (q < nq) ? load_quad_st<ST>(colv, q, nqf, p) : zero4();
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (e + u < total) {
+#pragma unroll
+                    for (int k = 0; k < KQ2; ++k)
+#pragma unroll
+                        for (int j = 0; j < M; ++j) {
+                            g[k][j].x = __builtin_fmaf(w[u][j], a[u][k].x, g[k][j].x);
+                            g[k][j].y = __builtin_fmaf(w[u][j], a[u][k].y, g[k][j].y);
+                            g[k][j].z = __builtin_fmaf(w[u][j], a[u][k].z, g[k][j].z);
+                            g[k][j].w = __builtin_fmaf(w[u][j], a[u][k].w, g[k][j].w);
+                        }
+                }
+            }
+        }
+        any = any || total > 0;
+        __syncthreads();
+    }
+    if (any) {
+        float* gp = gpart + (size_t)cr * m * pp.ldx;
+#pragma unroll
+        for (int k = 0; k < KQ2; ++k) {
+            const int q = qbase + t + 256 * k;
+            if (q < nq) {
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j < mg)
+                        *reinterpret_cast<f4*>(gp + (size_t)(j0 + j) * pp.ldx + 4 * q) = g[k][j];
+            }
+        }
+    }
+    if (t == 0 && blockIdx.x == 0 && j0 == 0) touched[cr] = any ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1022,72 +1023,94 @@ hipError_t launch_corr_vx(const Plan& pl, const PassParams& pp, const float* X, 
     }
 }
 
-template <int M, bool VEC, int ST>
+// Dense pass with more than one component group (m > 16): a launch of its
+// own (merged into k_backproj, the dense code would spill registers); four
+// waves per workgroup, each with its own row block.
+template <int RL, int G, int ST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_backproj_dense(
+    PassParams pp, const float* __restrict__ S, const uint8_t* __restrict__ act,
+    float* __restrict__ gpart, int* __restrict__ touched, int ncr, int thr,
+    const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done || !pass_is_dense(pp, thr)) return;
+    const int lane = threadIdx.x & 63;
+    const int q0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * RL;
+    if (q0 >= ((pp.p + 3) >> 2)) return;   // past the last row block (whole wave)
+    const int cr = blockIdx.y;
+    const int64_t cb = pp.n * cr / ncr, ce = pp.n * (cr + 1) / ncr;
+    int c = count_active(act, cb, ce, lane, 64);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (c == 0) return;
+    float* gp = gpart + (size_t)cr * pp.m * pp.ldx;
+    if (q0 + 16 * RL > (pp.p >> 2))
+        bpm_block<RL, G, 3, true, ST>(pp, cb, ce, q0, S, gp);
+    else
+        bpm_block<RL, G, 3, false, ST>(pp, cb, ce, q0, S, gp);
+    if (blockIdx.x == 0 && threadIdx.x == 0) touched[cr] = 1;
+}
+
+template <int ST>
+static hipError_t launch_bp_dense(const Plan& pl, const PassParams& pp, const float* S,
+                                  const uint8_t* act, float* gpart, int* touched,
+                                  const Ctrl* ctrl, hipStream_t st) {
+    const int nq = (int)((pl.p + 3) / 4);
+    const int qb = pl.m <= 32 ? 64 : 32;   // quads per row block: 16 RL
+    const int nrb = (nq + qb - 1) / qb;
+    const dim3 grid((unsigned)((nrb + 3) / 4), pl.bp_cr), block(256);
+    if (pl.m <= 32)
+        hipLaunchKernelGGL((k_backproj_dense<4, 2, ST>), grid, block, 0, st, pp, S, act, gpart,
+                           touched, pl.bp_cr, pl.bp_thr, ctrl);
+    else
+        hipLaunchKernelGGL((k_backproj_dense<2, 4, ST>), grid, block, 0, st, pp, S, act, gpart,
+                           touched, pl.bp_cr, pl.bp_thr, ctrl);
+    return hipGetLastError();
+}
+
+template <int M, bool VEC, int ST, int G>
 static hipError_t launch_bp_t(const Plan& pl, const PassParams& pp, int j0, const float* S,
                               const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                               hipStream_t st) {
-    hipLaunchKernelGGL((k_backproj<M, 2, VEC, ST>), dim3(pl.bp_rb, pl.bp_cr), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_backproj<M, 2, VEC, ST, G>), dim3(pl.bp_rb, pl.bp_cr), dim3(256), 0, st,
                        pp, j0, S, act, gpart, touched, pl.bp_cr, pl.bp_thr, ctrl);
     return hipGetLastError();
 }
 
+// With m <= 16 the launch carries the dense code when the plan allows dense
+// passes (m > 4, 16-byte loads).
 template <bool VEC, int ST>
 static hipError_t launch_bp_v(const Plan& pl, const PassParams& pp, int j0, const float* S,
                               const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                               hipStream_t st) {
     const int r = pl.m - j0;
     const int mb = r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 16;
+    // m <= 16: the dense code rides in this launch; m > 16: k_backproj_dense
+    const bool dense_here = j0 == 0 && pl.bp_thr <= kBpThrMax && pl.m <= 16;
+    if constexpr (VEC) {
+        if (dense_here && mb == 8) return launch_bp_t<8, VEC, ST, 1>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        if (dense_here && mb == 16) return launch_bp_t<16, VEC, ST, 1>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+    }
+    if (dense_here) return hipErrorInvalidValue;   // the plan never allows this
     switch (mb) {
-        case 1: return launch_bp_t<1, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
-        case 2: return launch_bp_t<2, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
-        case 4: return launch_bp_t<4, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
-        case 8: return launch_bp_t<8, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
-        default: return launch_bp_t<16, VEC, ST>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 1: return launch_bp_t<1, VEC, ST, 0>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 2: return launch_bp_t<2, VEC, ST, 0>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 4: return launch_bp_t<4, VEC, ST, 0>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        case 8: return launch_bp_t<8, VEC, ST, 0>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
+        default: return launch_bp_t<16, VEC, ST, 0>(pl, pp, j0, S, act, gpart, touched, ctrl, st);
     }
 }
 
-int backproj_mfma_rows(int m) { return m <= 32 ? 256 : 128; }
-
-template <int ST>
-static hipError_t launch_bpm_st(const Plan& pl, const PassParams& pp, const float* S,
-                                const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
-                                hipStream_t st) {
-    const int nq = (int)((pl.p + 3) / 4);
-    const int qb = backproj_mfma_rows(pl.m) / 4;
-    const dim3 grid((unsigned)((nq + qb - 1) / qb), pl.bp_cr), block(64);
-#define GPSPCA_BPM(RL, G, D) \
-    hipLaunchKernelGGL((k_backproj_mfma<RL, G, D, ST>), grid, block, 0, st, pp, S, act, gpart, \
-                       touched, pl.bp_cr, pl.bp_thr, ctrl)
-    const int d = pl.bp_depth;
-    if (pl.m <= 16) {
-        if (d == 2) GPSPCA_BPM(4, 1, 2);
-        else if (d == 4) GPSPCA_BPM(4, 1, 4);
-        else GPSPCA_BPM(4, 1, 3);
-    } else if (pl.m <= 32) {
-        if (d == 2) GPSPCA_BPM(4, 2, 2);
-        else if (d == 4) GPSPCA_BPM(4, 2, 4);
-        else GPSPCA_BPM(4, 2, 3);
-    } else {
-        if (d == 2) GPSPCA_BPM(2, 4, 2);
-        else GPSPCA_BPM(2, 4, 3);
-    }
-#undef GPSPCA_BPM
-    return hipGetLastError();
-}
-
-// Component groups of at most 16 (the group's partial of g lives in registers);
-// ranges with enough active columns go to the matrix-core kernel instead.
+// Component groups of at most 16 (the group's partial of g lives in registers).
 hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
                            const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                            hipStream_t st) {
-    if (pl.bp_thr <= kBpThrMax) {
+    if (pl.bp_thr <= kBpThrMax && pl.m > 16) {
         hipError_t e;
         if (pl.dtype == GPSPCA_BF16)
-            e = launch_bpm_st<kStBF16>(pl, pp, S, act, gpart, touched, ctrl, st);
+            e = launch_bp_dense<kStBF16>(pl, pp, S, act, gpart, touched, ctrl, st);
         else if (pl.dtype == GPSPCA_F8E4M3)
-            e = launch_bpm_st<kStF8>(pl, pp, S, act, gpart, touched, ctrl, st);
+            e = launch_bp_dense<kStF8>(pl, pp, S, act, gpart, touched, ctrl, st);
         else
-            e = launch_bpm_st<kStF32>(pl, pp, S, act, gpart, touched, ctrl, st);
+            e = launch_bp_dense<kStF32>(pl, pp, S, act, gpart, touched, ctrl, st);
         if (e != hipSuccess) return e;
     }
     for (int j0 = 0; j0 < pl.m; j0 += 16) {

@@ -410,12 +410,21 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
     if (msz < 2) return;
     const int mm = msz + (msz & 1);
     const int half = mm / 2;
-    __shared__ int rotated;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        // cyclic Jacobi stopping rule: a sweep that applies no rotation (every
-        // |a_pq| <= eps sqrt(|a_pp a_qq|)) ends the iteration
-        if (t == 0) rotated = 0;
-        __syncthreads();
+        // cyclic Jacobi stopping rule: a sweep that would apply no rotation
+        // (every |a_pq| <= eps sqrt(|a_pp a_qq|)) ends the iteration.  Every pair
+        // is tested at once before the sweep: if none qualifies, no step of the
+        // sweep would rotate (nothing changes), so the sweep is skipped.
+        int need = 0;
+        for (int e = t; e < msz * msz; e += nt) {
+            const int i = e / msz, j = e % msz;
+            if (i < j) {
+                const double apq = a[i * LDM + j];
+                need |= (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(a[i * LDM + i] * a[j * LDM + j])) &&
+                         fabs(apq) > 1e-300) ? 1 : 0;
+            }
+        }
+        if (!__syncthreads_or(need)) break;
         for (int r = 0; r < mm - 1; ++r) {
             if (t < half) {
                 // round-robin schedule: position 0 fixed, the others rotate
@@ -427,7 +436,6 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                     const double apq = a[pp * LDM + qq];
                     const double app = a[pp * LDM + pp], aqq = a[qq * LDM + qq];
                     if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-                        rotated = 1;
                         const double tau = (aqq - app) / (2.0 * apq);
                         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + tt * tt);
@@ -476,9 +484,6 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
             }
             __syncthreads();
         }
-        const int any_rot = rotated;
-        __syncthreads();
-        if (!any_rot) break;
     }
 }
 

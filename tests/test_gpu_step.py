@@ -98,7 +98,7 @@ def test_step_zero_gamma_dense_support(gpu, form):
     np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
 
 
-@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "rd", "wg", "valu"])
+@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "rd", "rd128", "wg", "valu"])
 @pytest.mark.parametrize("form,m", [(O.BL1, 4), (O.BL0, 8)])
 def test_every_correlation_kernel(gpu, kernel, form, m, monkeypatch):
     """Force each block correlation kernel (registers-X, matrix cores through
@@ -124,3 +124,25 @@ def test_every_correlation_kernel(gpu, kernel, form, m, monkeypatch):
     res = gpu.solve(Ad, form, m, gamma, mu=list(mu), X0=x_to_device(X0), tol=0.0, max_iter=6)
     assert rel(res.X.cpu().numpy(), rs["X"]) <= 1e-5
     np.testing.assert_allclose(res.trace, rs["trace"], rtol=1e-5)
+
+
+@pytest.mark.parametrize("kernel", ["rd", "rd128"])
+@pytest.mark.parametrize("m,p,n", [(20, 1001, 2999), (40, 514, 1500), (16, 4097, 64)])
+def test_register_direct_kernels_component_groups(gpu, kernel, m, p, n, monkeypatch):
+    """The register-direct matrix-core kernels with 2 and 4 component groups,
+    ragged rows and a matrix of only 4 tiles: one step against the oracle."""
+    monkeypatch.setenv("GPSPCA_CORR_KERNEL", kernel)
+    print(f"\n[corr {kernel}] m={m} p={p} n={n}", flush=True)
+    A32, _, _ = W.planted_block(p, n, 4, 90 + m, k=min(40, n // 4))
+    A64 = A32.astype(np.float64)
+    mu = np.linspace(1.0, 0.7, m)
+    X0 = fp32_round(O.init(A64, m)[0])
+    gamma = W.gamma_absolute(A64, False, 0.05)
+    Ad = to_device(A32, lda=(p + 3) // 4 * 4)
+    ref = O.step(A64, O.BL1, X0, gamma, mu=mu)
+    out = gpu.step(Ad, O.BL1, x_to_device(X0), gamma, mu=list(mu))
+    ties = tie_mask(A64, X0, O.BL1, gamma, mu)
+    S = out.S.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal((S != 0)[~ties], (ref["S"] != 0)[~ties])
+    assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
+    np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
