@@ -214,7 +214,8 @@ def serving_leg(W, count, full, slots=8, arena_gb=64, seed=1000):
     opened = run(rate)
     print(f"[bench] serving open loop at {rate:.1f}/s: {opened}", file=sys.stderr, flush=True)
     return {"workload": f"{count} requests, p log-uniform [200, {p_max}], n log-uniform "
-                        f"[2000, {n_max}], forms uniform, m in (1, 4, 16), gamma fraction "
+                        f"[2000, {n_max}], forms uniform, m in (1, 4, 16) (single-unit forms: m "
+                        f"starts), gamma fraction "
                         f"U[0.01, 0.5], FP32 or bf16 storage, half repeat an earlier matrix; "
                         f"{len(mats)} distinct matrices ({distinct_gb:.1f} GB stored), "
                         f"{slots} slots, {arena_gb} GB arena",

@@ -160,6 +160,21 @@ int gpspca_solve_path(const gpspca_matrix* A, int form, int K, const double* gam
                       int* n_iter, int* status);
 
 /*
+ * Multi-start single-unit solves: m independent problems of one single-unit
+ * formulation (form GPSPCA_SL1 or GPSPCA_SL0) with the same gamma, problem k
+ * starting at the column of A with the k-th largest norm (ties to the lower
+ * index), normalized.  They share every pass over A exactly as the problems of
+ * gpspca_solve_path do (Section 2, Table 1, rows 1-2, run from m starts: the
+ * reading of "m" for single-unit serving requests).  1 <= m <= min(n,
+ * GPSPCA_MAX_M).  Workspace: gpspca_path_workspace_bytes(A, m, max_iter).
+ * Outputs, return value and synchronization as in gpspca_solve_path with K = m.
+ */
+int gpspca_solve_multistart(const gpspca_matrix* A, int form, int m, double gamma, double tol,
+                            int max_iter, void* workspace, size_t ws_bytes, void* stream,
+                            float* X, float* Z, uint32_t* support, double* obj_trace,
+                            int* n_iter, int* status);
+
+/*
  * Refinement on a frozen support (for results of a reduced-precision solve).
  * Runs passes of the iteration of gpspca_solve on the FP32 matrix A in which
  * s_ij is forced to 0 wherever bit (i % 32) of word (j * ceil(n/32) + i/32) of
@@ -246,7 +261,8 @@ int gpspca_column_norms(const gpspca_matrix* A, double* norms, void* stream);
  * request uses are evicted, least recently used first.  Admission is in arrival
  * order, except that a request that does not fit yet may be passed by later
  * ones a bounded number of times.  Every result equals what gpspca_solve
- * returns for the same problem from the default start.
+ * returns for the same problem from the default start; a single-unit request
+ * with m > 1 is m starts, as gpspca_solve_multistart.
  * ------------------------------------------------------------------------ */
 typedef struct gpspca_server gpspca_server;
 
@@ -259,8 +275,11 @@ typedef struct gpspca_result {
     const float* X;           /* host p x m (leading dim p), owned by the server */
     const float* Z;           /* host n x m */
     const uint32_t* support;  /* host ceil(n/32) x m words, as gpspca_solve */
-    const double* obj_trace;  /* host n_iter entries */
+    const double* obj_trace;  /* host n_iter entries (multi-start: m x n_iter, problem k's
+                                 trace at obj_trace[k * n_iter], col_n_iter[k] entries) */
     double t_submit, t_admit, t_done;  /* seconds since the server was created */
+    const int* col_n_iter;    /* multi-start: per-problem passes (n_iter is their max); else NULL */
+    const int* col_status;    /* multi-start: per-problem status (status is the largest); else NULL */
 } gpspca_result;
 
 typedef struct gpspca_stats {
@@ -277,8 +296,9 @@ int gpspca_server_register(gpspca_server* s, const float* host, int64_t p, int64
                            int store_dtype, uint64_t* matrix_id);
 /* Fails while the matrix has pending requests. */
 int gpspca_server_unregister(gpspca_server* s, uint64_t matrix_id);
-/* Queue a solve (arguments as gpspca_solve, default start); returns at once.
- * GPSPCA_ENOMEM if the request could not fit even in an empty arena. */
+/* Queue a solve (arguments as gpspca_solve, default start; a single-unit form
+ * with m > 1 as gpspca_solve_multistart); returns at once.  GPSPCA_ENOMEM if
+ * the request could not fit even in an empty arena. */
 int gpspca_server_submit(gpspca_server* s, uint64_t matrix_id, int form, int m, double gamma,
                          const double* mu, double tol, int max_iter, uint64_t* request_id);
 /* 0 and *out filled when the request is done, 1 while it is pending, < 0 on

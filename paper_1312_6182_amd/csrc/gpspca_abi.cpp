@@ -704,11 +704,13 @@ static const char* status_text(int s) {
 //  a support bit are read and s_ij = 0 wherever bit (i, j) is clear.
 //  norms_in != nullptr: device column norms of A for the default start (the
 //  server caches them with a resident matrix).
+//  multistart (path, no X0): problem j starts at the normalized column of the
+//  j-th largest norm instead of all at the largest.
 int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
                const double* gammas, int path, const uint32_t* mask, const float* X0,
                double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
                float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
-               int* status_out, const double* norms_in) {
+               int* status_out, const double* norms_in, int multistart) {
     int ncu = 0;
     int rc = device_cus(&ncu);
     if (rc) return rc;
@@ -746,6 +748,16 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
             GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
             GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
         }
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
+    } else if (path && multistart) {
+        // problem j starts at the column of the j-th largest norm (ties to the
+        // lower index), normalized on its own
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
+        if (!norms_in) GPSPCA_HIP(launch_colnorm(pp, A->dtype, P.norms, grid, st));
+        GPSPCA_HIP(launch_topm(pl, norms_in ? norms_in : P.norms, P.cand_v, P.cand_i, P.idx, st));
+        GPSPCA_HIP(launch_gather(pl, pp, P.idx, P.g64, st));
+        GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 2, P.g64, P.gram, P.ctrl, st));
+        GPSPCA_HIP(launch_project_diag(pl, P.gram, P.coef, P.ctrl, st));
         GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
     } else if (path) {
         // all columns start at the normalized column of largest norm
@@ -961,7 +973,24 @@ int gpspca_solve_path(const gpspca_matrix* A, int form, int K, const double* gam
     if (rc) return rc;
     return solve_core(A, form, K, 0.0, nullptr, gammas, 1, nullptr, X0, tol, max_iter, workspace,
                       ws_bytes, static_cast<hipStream_t>(stream), X, Z, support, obj_trace,
-                      n_iter, status, nullptr);
+                      n_iter, status, nullptr, 0);
+}
+
+int gpspca_solve_multistart(const gpspca_matrix* A, int form, int m, double gamma, double tol,
+                            int max_iter, void* workspace, size_t ws_bytes, void* stream,
+                            float* X, float* Z, uint32_t* support, double* obj_trace,
+                            int* n_iter, int* status) {
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    if (m > A->n) return fail(GPSPCA_EINVAL, "multi-start needs m <= n");
+    std::vector<double> gammas((size_t)std::max(0, std::min(m, kMaxM)), gamma);
+    rc = check_path(A, form, m, gammas.data());
+    if (rc) return rc;
+    rc = check_run(tol, max_iter, X, workspace);
+    if (rc) return rc;
+    return solve_core(A, form, m, 0.0, nullptr, gammas.data(), 1, nullptr, nullptr, tol,
+                      max_iter, workspace, ws_bytes, static_cast<hipStream_t>(stream), X, Z,
+                      support, obj_trace, n_iter, status, nullptr, 1);
 }
 
 int gpspca_refine_path(const gpspca_matrix* A, int form, int K, const double* gammas,

@@ -215,6 +215,6 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
                const double* gammas, int path, const uint32_t* mask, const float* X0,
                double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
                float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
-               int* status_out, const double* norms_in);
+               int* status_out, const double* norms_in, int multistart = 0);
 
 }  // namespace gpspca

@@ -62,6 +62,8 @@ struct SRequest {
     bool done = false;
     int status = 0;
     int n_iter = 0;
+    int multistart = 0;                 // single-unit form with m > 1: m starts
+    std::vector<int> col_n_iter, col_status;
     std::string error;
     std::vector<float> X, Z;
     std::vector<uint32_t> support;
@@ -228,12 +230,32 @@ void Server::worker(int slot) {
             float* Zd = reinterpret_cast<float*>(ws + R->solve_ws + al(sizeof(float) * M->p * R->m));
             uint32_t* Sd = reinterpret_cast<uint32_t*>(
                 ws + R->solve_ws + al(sizeof(float) * M->p * R->m) + al(sizeof(float) * M->n * R->m));
-            R->trace.assign(R->max_iter, 0.0);
             int nit = 0;
-            rc = solve_core(&A, R->form, R->m, R->gamma, R->mu.empty() ? nullptr : R->mu.data(),
-                            nullptr, 0, nullptr, nullptr, R->tol, R->max_iter, ws, R->solve_ws, st,
-                            Xd, Zd, Sd, R->trace.data(), &nit, nullptr,
-                            reinterpret_cast<const double*>(arena + adm.matrix_offset + M->norms_off));
+            const double* norms =
+                reinterpret_cast<const double*>(arena + adm.matrix_offset + M->norms_off);
+            if (R->multistart) {
+                // m single-unit problems from the m columns of largest norm
+                const std::vector<double> gam((size_t)R->m, R->gamma);
+                std::vector<double> tr((size_t)R->m * R->max_iter, 0.0);
+                R->col_n_iter.assign(R->m, 0);
+                R->col_status.assign(R->m, 0);
+                rc = solve_core(&A, R->form, R->m, 0.0, nullptr, gam.data(), 1, nullptr, nullptr,
+                                R->tol, R->max_iter, ws, R->solve_ws, st, Xd, Zd, Sd, tr.data(),
+                                R->col_n_iter.data(), R->col_status.data(), norms, 1);
+                for (int k = 0; k < R->m; ++k) nit = std::max(nit, R->col_n_iter[k]);
+                // problem k's trace at [k * n_iter, k * n_iter + col_n_iter[k])
+                R->trace.assign((size_t)R->m * nit, 0.0);
+                for (int k = 0; k < R->m; ++k)
+                    std::copy(tr.begin() + (size_t)k * R->max_iter,
+                              tr.begin() + (size_t)k * R->max_iter + R->col_n_iter[k],
+                              R->trace.begin() + (size_t)k * nit);
+            } else {
+                R->trace.assign(R->max_iter, 0.0);
+                rc = solve_core(&A, R->form, R->m, R->gamma,
+                                R->mu.empty() ? nullptr : R->mu.data(), nullptr, 0, nullptr,
+                                nullptr, R->tol, R->max_iter, ws, R->solve_ws, st, Xd, Zd, Sd,
+                                R->trace.data(), &nit, nullptr, norms);
+            }
             if (rc >= 0) {
                 const size_t words = (size_t)((M->n + 31) / 32);
                 R->X.resize((size_t)M->p * R->m);
@@ -253,7 +275,7 @@ void Server::worker(int slot) {
                     err = hipGetErrorString(e);
                 }
                 R->n_iter = nit;
-                R->trace.resize(std::max(0, nit));
+                if (!R->multistart) R->trace.resize(std::max(0, nit));
             } else {
                 err = gpspca_last_error();
             }
@@ -389,12 +411,16 @@ int gpspca_server_submit(gpspca_server* S, uint64_t matrix_id, int form, int m, 
     A.n = M.n;
     A.lda = M.lda_dev;
     A.dtype = M.dtype;
-    int rc = check_problem(&A, form, m, gamma, mu);
+    // a single-unit form with m > 1 runs m starts (the m columns of largest norm)
+    const int multistart = (form == GPSPCA_SL1 || form == GPSPCA_SL0) && m > 1;
+    int rc = check_problem(&A, form, multistart ? 1 : m, gamma, mu);
     if (rc) return rc;
+    if (m < 1 || m > GPSPCA_MAX_M) return fail(GPSPCA_EINVAL, "need 1 <= m <= GPSPCA_MAX_M");
     if (!std::isfinite(tol) || tol < 0.0) return fail(GPSPCA_EINVAL, "tol must be finite and >= 0");
     if (max_iter < 1) return fail(GPSPCA_EINVAL, "max_iter must be >= 1");
     if (m > M.n) return fail(GPSPCA_EINVAL, "default start needs m <= n");
-    const size_t ws = gpspca_workspace_bytes(&A, form, m, max_iter);
+    const size_t ws = multistart ? gpspca_path_workspace_bytes(&A, m, max_iter)
+                                 : gpspca_workspace_bytes(&A, form, m, max_iter);
     if (ws == 0) return GPSPCA_EINVAL;
     SRequest R;
     R.matrix = matrix_id;
@@ -403,6 +429,7 @@ int gpspca_server_submit(gpspca_server* S, uint64_t matrix_id, int form, int m, 
     R.gamma = gamma;
     R.tol = tol;
     R.max_iter = max_iter;
+    R.multistart = multistart;
     if (mu && form >= GPSPCA_BL1) R.mu.assign(mu, mu + m);
     R.solve_ws = al(ws);
     R.ws_bytes = R.solve_ws + al(sizeof(float) * M.p * m) + al(sizeof(float) * M.n * m) +
@@ -435,6 +462,8 @@ static int fill_result(const gpspca::SRequest& R, const gpspca::SMatrix* M, gpsp
     out->Z = R.Z.empty() ? nullptr : R.Z.data();
     out->support = R.support.empty() ? nullptr : R.support.data();
     out->obj_trace = R.trace.empty() ? nullptr : R.trace.data();
+    out->col_n_iter = R.col_n_iter.empty() ? nullptr : R.col_n_iter.data();
+    out->col_status = R.col_status.empty() ? nullptr : R.col_status.data();
     out->t_submit = R.t_submit;
     out->t_admit = R.t_admit;
     out->t_done = R.t_done;

@@ -24,6 +24,7 @@ class _Result(ctypes.Structure):
         ("support", ctypes.POINTER(ctypes.c_uint32)),
         ("obj_trace", ctypes.POINTER(ctypes.c_double)),
         ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+        ("col_n_iter", ctypes.POINTER(ctypes.c_int)), ("col_status", ctypes.POINTER(ctypes.c_int)),
     ]
 
 
@@ -64,13 +65,15 @@ class ServeResult:
     X: np.ndarray            # (p, m)
     Z: np.ndarray            # (n, m)
     support: np.ndarray      # (m, ceil(n/32)) uint32 words
-    trace: list
+    trace: list              # multi-start: one list per problem
     n_iter: int
     status: int
     t_submit: float          # seconds on the server's clock
     t_admit: float
     t_done: float
     uploaded: bool
+    col_n_iter: Optional[list] = None   # multi-start: passes and status per problem
+    col_status: Optional[list] = None
 
     @property
     def latency(self) -> float:
@@ -135,10 +138,17 @@ class Server:
         X = arr(r.X, p * m, np.float32).reshape(m, p).T
         Z = arr(r.Z, n * m, np.float32).reshape(m, n).T
         sup = arr(r.support, nw * m, np.uint32).reshape(m, nw)
-        tr = list(arr(r.obj_trace, k, np.float64))
+        cn = cs = None
+        if r.col_n_iter:
+            cn = [int(v) for v in arr(r.col_n_iter, m, np.int32)]
+            cs = [int(v) for v in arr(r.col_status, m, np.int32)]
+            flat = arr(r.obj_trace, m * k, np.float64)
+            tr = [list(flat[j * k:j * k + cn[j]]) for j in range(m)]
+        else:
+            tr = list(arr(r.obj_trace, k, np.float64))
         return ServeResult(X=X, Z=Z, support=sup, trace=tr, n_iter=k, status=r.status,
                            t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done,
-                           uploaded=bool(r.uploaded))
+                           uploaded=bool(r.uploaded), col_n_iter=cn, col_status=cs)
 
     def poll(self, rid: int) -> Optional[ServeResult]:
         r = _Result()

@@ -95,6 +95,19 @@ def pick_gamma(A64, form, m, mu, X0, gamma0, iters=1, safety=8.0, tries=60):
     raise RuntimeError("could not place gamma away from ties")
 
 
+def pick_gamma_starts(A64, form, x0s, gamma0, iters=1):
+    """pick_gamma for several single-unit starts at once (multi-start solves):
+    a gamma whose trajectories from every start stay away from ties."""
+    g = gamma0
+    for _ in range(8):
+        g_prev = g
+        for x0 in x0s:
+            g = pick_gamma(A64, form, 1, None, x0, g, iters=iters)
+        if g == g_prev:
+            return g
+    raise RuntimeError("could not place gamma away from ties for every start")
+
+
 def fp32_round(X: np.ndarray) -> np.ndarray:
     return np.asarray(X, dtype=np.float32).astype(np.float64)
 

@@ -8,7 +8,8 @@ import pytest
 import oracle as O
 from workloads import generators as W
 
-from _util import fp32_round, is_l0, pick_gamma, rel, tie_mask, to_device, x_to_device
+from _util import (fp32_round, is_l0, pick_gamma, pick_gamma_starts, rel, tie_mask, to_device,
+                   x_to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -71,3 +72,41 @@ def test_path_default_start_and_single_solve_agree(gpu):
         np.testing.assert_allclose(res.traces[k], single.trace, rtol=1e-5)
         assert rel(res.X[:, k].cpu().numpy(), single.X[:, 0].cpu().numpy()) <= 1e-5
     assert res.status[-1] == O.DEGENERATE and res.traces[-1] == [0.0]
+
+
+@pytest.mark.parametrize("form,m,p,n", [(O.SL1, 5, 601, 3001), (O.SL0, 16, 257, 2000),
+                                        (O.SL1, 1, 300, 900)])
+def test_multistart_columns_match_single_solves(gpu, form, m, p, n):
+    """gpspca_solve_multistart: problem k starts at the column of the k-th
+    largest norm (ties to the lower index), normalized, and equals the oracle's
+    single-unit solve from there."""
+    print(f"\n[multistart] form={form} m={m} p={p} n={n}", flush=True)
+    A32, _, _, _ = W.planted_single(p, n, 31 + m, k=50)
+    A64 = A32.astype(np.float64)
+    idx = O.top_m(O.column_norms(A64), m)
+    frac = 0.1 if not is_l0(form) else 0.02
+    g = W.gamma_absolute(A64, is_l0(form), frac)
+    x0s = [fp32_round(A64[:, [i]] / np.linalg.norm(A64[:, i])) for i in idx]
+    iters = 8
+    g = pick_gamma_starts(A64, form, x0s, g, iters=iters)
+    res = gpu.solve_multistart(to_device(A32), form, m, g, tol=0.0, max_iter=iters)
+    X = res.X.cpu().numpy().astype(np.float64)
+    sup = res.support_mask().cpu().numpy()
+    for k in range(m):
+        ref = O.solve(A64, form, 1, g, X0=x0s[k], tol=0.0, max_iter=iters)
+        assert res.n_iter[k] == ref["n_iter"] and res.status[k] == ref["status"], k
+        np.testing.assert_allclose(res.traces[k], ref["trace"], rtol=1e-5)
+        if ref["trace"][-1] == 0.0:
+            continue
+        assert rel(X[:, k], ref["X"][:, 0]) <= 1e-5
+        ties = tie_mask(A64, ref["X"], form, g, None)[:, 0]
+        np.testing.assert_array_equal(sup[~ties, k], ref["support"][~ties, 0])
+
+
+def test_multistart_argument_checks(gpu):
+    import paper_1312_6182_amd as G
+    Ad = to_device(W.gaussian(100, 40, 5))
+    for bad in ((O.BL1, 2), (O.SL1, 41), (O.SL1, 0)):
+        with pytest.raises(G.GpspcaError) as e:
+            gpu.solve_multistart(Ad, bad[0], bad[1], 1.0, max_iter=3)
+        assert e.value.code == G.EINVAL

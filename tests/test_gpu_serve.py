@@ -9,7 +9,7 @@ import torch
 import oracle as O
 from workloads import generators as W
 
-from _util import fp32_round, is_l0, rel, to_device
+from _util import fp32_round, is_l0, pick_gamma_starts, rel, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -18,7 +18,24 @@ def _alone(gpu, A32, store, form, m, gamma, mu, tol, max_iter):
     Ad = to_device(A32)
     if store == "bf16":
         Ad, _ = gpu.quantize(Ad, torch.bfloat16)
+    if form < 2 and m > 1:
+        return gpu.solve_multistart(Ad, form, m, gamma, tol=tol, max_iter=max_iter)
     return gpu.solve(Ad, form, m, gamma, mu=mu, tol=tol, max_iter=max_iter)
+
+
+def _same_as_solo(r, solo):
+    """A served result equals the library's own solve of the same request bitwise."""
+    if isinstance(solo.n_iter, list):      # multi-start
+        assert r.col_n_iter == solo.n_iter and r.col_status == solo.status
+        assert r.n_iter == max(solo.n_iter)
+        for a, b in zip(r.trace, solo.traces):
+            np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
+    else:
+        assert r.status == solo.status and r.n_iter == solo.n_iter
+        np.testing.assert_array_equal(np.asarray(r.trace), np.asarray(solo.trace))
+    np.testing.assert_array_equal(r.X, solo.X.cpu().numpy())
+    np.testing.assert_array_equal(r.Z, solo.Z.cpu().numpy())
+    np.testing.assert_array_equal(r.support.view(np.int32), solo.support.cpu().numpy())
 
 
 def _mix(seed):
@@ -30,7 +47,7 @@ def _mix(seed):
     for r in range(14):
         i = int(rng.integers(len(mats)))
         form = int(rng.integers(4))
-        m = 1 if form < 2 else int(rng.choice([1, 4, 16]))
+        m = int(rng.choice([1, 4, 16]))        # single-unit forms: m starts
         frac = float(rng.uniform(0.01, 0.5)) if form in (0, 2) else float(rng.uniform(0.005, 0.1))
         A64 = mats[i].astype(np.float64)
         gamma = W.gamma_absolute(A64, is_l0(form), frac)
@@ -52,13 +69,10 @@ def test_mixed_requests_equal_solo_solves(gpu):
     overlapped = sum(1 for a in res for b in res
                      if a is not b and a.t_admit < b.t_done and b.t_admit < a.t_done)
     print(f"\n[serve] {len(reqs)} requests, {overlapped} overlapping pairs, stats {st}", flush=True)
+    assert any(form < 2 and m > 1 for (_, form, m, _, _) in reqs)
     for (i, form, m, g, mu), r in zip(reqs, res):
         solo = _alone(gpu, mats[i], shapes[i][2], form, m, g, mu, 1e-4, 200)
-        assert r.status == solo.status and r.n_iter == solo.n_iter
-        np.testing.assert_array_equal(r.X, solo.X.cpu().numpy())
-        np.testing.assert_array_equal(r.Z, solo.Z.cpu().numpy())
-        np.testing.assert_array_equal(np.asarray(r.trace), np.asarray(solo.trace))
-        np.testing.assert_array_equal(r.support.view(np.int32), solo.support.cpu().numpy())
+        _same_as_solo(r, solo)
 
 
 def test_served_results_match_the_oracle(gpu):
@@ -110,5 +124,26 @@ def test_oversized_request_is_rejected(gpu):
             srv.submit(mid, O.SL1, 1, 1.0)
         assert e.value.code == G.ENOMEM
         with pytest.raises(G.GpspcaError) as e:
-            srv.submit(mid, O.SL1, 2, 1.0)
+            srv.submit(mid, O.SL1, 65, 1.0)     # more starts than GPSPCA_MAX_M
         assert e.value.code == G.EINVAL
+
+
+def test_served_multistart_matches_the_oracle(gpu):
+    """A single-unit request with m = 4 is 4 starts: start k is the column of
+    the k-th largest norm, normalized, and each result is the oracle's
+    single-unit solve from it."""
+    from paper_1312_6182_amd.serve import Server
+    A32, _, _, _ = W.planted_single(500, 4000, 17, k=40, beta=10 * np.sqrt(500 * 4000))
+    A64 = A32.astype(np.float64)
+    idx = O.top_m(O.column_norms(A64), 4)
+    with Server(1 << 30, slots=2) as srv:
+        mid = srv.register(A32)
+        x0s = [fp32_round(A64[:, [i]] / np.linalg.norm(A64[:, i])) for i in idx]
+        for form, frac in ((O.SL1, 0.2), (O.SL0, 0.05)):
+            g = pick_gamma_starts(A64, form, x0s, W.gamma_absolute(A64, is_l0(form), frac), 12)
+            r = srv.wait(srv.submit(mid, form, 4, g, tol=0.0, max_iter=12))
+            for k in range(4):
+                ref = O.solve(A64, form, 1, g, X0=x0s[k], tol=0.0, max_iter=12)
+                assert r.col_n_iter[k] == ref["n_iter"] and r.col_status[k] == ref["status"]
+                np.testing.assert_allclose(r.trace[k], ref["trace"], rtol=1e-5)
+                assert rel(r.X[:, k], ref["X"][:, 0]) <= 1e-5

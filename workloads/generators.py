@@ -143,7 +143,8 @@ def serving_requests(count: int, seed: int = 1000, p_max: int = 20000, n_max: in
 
     p log-uniform in [200, p_max], n log-uniform in [2000, n_max] (20000 and
     200000 in the full setting), a formulation uniform over the four, m in
-    {1, 4, 16} (m = 1 for the single-unit forms), gamma fraction uniform in
+    {1, 4, 16} (for a single-unit form, m > 1 means m starts from the m columns
+    of largest norm), gamma fraction uniform in
     [0.01, 0.5], storage FP32 or bfloat16 (even odds), and with probability 1/2
     a repeat of an earlier request's matrix."""
     rng = np.random.default_rng(seed)
@@ -158,7 +159,7 @@ def serving_requests(count: int, seed: int = 1000, p_max: int = 20000, n_max: in
             mseed = seed + r
             dt = "f32" if rng.random() < 0.5 else "bf16"
         form = int(rng.integers(4))
-        m = 1 if form < 2 else int(rng.choice([1, 4, 16]))
+        m = int(rng.choice([1, 4, 16]))
         m = min(m, p)
         frac = float(rng.uniform(0.01, 0.5))
         out.append(dict(p=p, n=n, matrix_seed=mseed, dtype=dt, form=form, m=m, frac=frac))
