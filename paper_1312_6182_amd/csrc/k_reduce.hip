@@ -122,6 +122,57 @@ hipError_t launch_reduce_partials(const Plan& pl, const float* gpart, const int*
 // Row block r0..r0+nr: g_r = sum_y l1[y][.][r] (fixed order) -> g64 (p x m,
 // leading dim p); partial Gram matrices over the block ->
 // gram[blk][0|1|2][m*m] = G^T G, G^T X, X^T X.
+// G^T G, G^T X and X^T X of one row block held in LDS (gt, xt: rows x (m+1)),
+// R x R entries per thread; rows are added in order, as in the untiled loop.
+template <int R>
+__device__ __forceinline__ void gram_tiles(const double* gt, const double* xt, int mp, int nr,
+                                           int m, int with_x, int t, double* out) {
+    const int ta = t >> 4, tb = t & 15, mm = m * m;
+    int ia[R], ib[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        ia[i] = (ta + 16 * i < m) ? ta + 16 * i : m - 1;
+        ib[i] = (tb + 16 * i < m) ? tb + 16 * i : m - 1;
+    }
+    double sgg[R][R], sgx[R][R], sxx[R][R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < R; ++k) sgg[i][k] = sgx[i][k] = sxx[i][k] = 0.0;
+    for (int rr = 0; rr < nr; ++rr) {
+        const double* gr = gt + rr * mp;
+        const double* xr = xt + rr * mp;
+        double ga[R], gb[R], xa[R], xb[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            ga[i] = gr[ia[i]];
+            gb[i] = gr[ib[i]];
+            xa[i] = xr[ia[i]];
+            xb[i] = xr[ib[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                sgg[i][k] += ga[i] * gb[k];
+                sgx[i][k] += ga[i] * xb[k];
+                sxx[i][k] += xa[i] * xb[k];
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int a = ta + 16 * i, b = tb + 16 * k;
+            if (a < m && b < m) {
+                const int e = a * m + b;
+                out[e] = sgg[i][k];
+                out[mm + e] = with_x == 1 ? sgx[i][k] : 0.0;
+                out[2 * mm + e] = with_x == 1 ? sxx[i][k] : 0.0;
+            }
+        }
+}
+
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ l1, int nsplit, int m,
                                               int ldx, int p, int rows, const float* __restrict__ X,
                                               int with_x, double* __restrict__ g64,
@@ -191,6 +242,14 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ l1, int
             for (int rr = 0; rr < nr; ++rr) sgg += gt[rr * mp + a] * gt[rr * mp + a];
             out[a * m + a] = sgg;
         }
+        return;
+    }
+    if (m > 16 && blockDim.x == 256) {
+        // register tiles: thread (ta, tb) of a 16 x 16 grid owns entries
+        // (ta + 16 i, tb + 16 k), i, k < R, of the three products, so a row
+        // costs 4R LDS reads for 3 R^2 multiply-adds
+        if (m <= 32) gram_tiles<2>(gt, xt, mp, nr, m, with_x, t, out);
+        else gram_tiles<4>(gt, xt, mp, nr, m, with_x, t, out);
         return;
     }
     for (int e = t; e < mm; e += blockDim.x) {
@@ -396,10 +455,14 @@ hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* tou
 // A <- R A R^T as independent 2 x 2 blocks (rows of pair k1, columns of pair
 // k2: rows first, then columns, each block by one thread) and V <- V R^T, so
 // every entry is read and written once per step.
+// A pair is rotated while |a_pq| > 2^-40 sqrt(|a_pp a_qq|): the off-diagonal
+// then bounds the relative error of the inverse square root built from the
+// result far below the FP32 of the retracted X.
 // Executed by the whole workgroup.
 __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                            bool warm = false) {
     const int t = threadIdx.x, nt = blockDim.x;
+    constexpr double kTol = 9.094947017729282e-13;   // 2^-40
     if (!warm) {
         for (int e = t; e < msz * msz; e += nt) {
             const int i = e / msz, j = e % msz;
@@ -410,9 +473,9 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
     if (msz < 2) return;
     const int mm = msz + (msz & 1);
     const int half = mm / 2;
+    const int nblk = half * half, nitem = nblk + msz * half;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        // cyclic Jacobi stopping rule: a sweep that would apply no rotation
-        // (every |a_pq| <= eps sqrt(|a_pp a_qq|)) ends the iteration.  Every pair
+        // a sweep that would apply no rotation ends the iteration.  Every pair
         // is tested at once before the sweep: if none qualifies, no step of the
         // sweep would rotate (nothing changes), so the sweep is skipped.
         int need = 0;
@@ -420,7 +483,7 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
             const int i = e / msz, j = e % msz;
             if (i < j) {
                 const double apq = a[i * LDM + j];
-                need |= (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(a[i * LDM + i] * a[j * LDM + j])) &&
+                need |= (fabs(apq) > kTol * sqrt(fabs(a[i * LDM + i] * a[j * LDM + j])) &&
                          fabs(apq) > 1e-300) ? 1 : 0;
             }
         }
@@ -435,7 +498,7 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                 if (qq < msz) {
                     const double apq = a[pp * LDM + qq];
                     const double app = a[pp * LDM + pp], aqq = a[qq * LDM + qq];
-                    if (fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+                    if (fabs(apq) > kTol * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
                         const double tau = (aqq - app) / (2.0 * apq);
                         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + tt * tt);
@@ -448,10 +511,10 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                 prs[2 * t + 1] = qq;
             }
             __syncthreads();
-            // A <- R A R^T by 2 x 2 blocks; a pair whose second index is the
-            // padding position (odd msz) has a single row / column
-            const int nblk = half * half;
-            for (int e = t; e < nblk + msz * half; e += nt) {
+            // items: 2 x 2 blocks of A (e < nblk) and row pairs of V; a pair
+            // whose second index is the padding position (odd msz) has a single
+            // row / column.  A row of V is a block with an identity row rotation.
+            for (int e = t; e < nitem; e += nt) {
                 if (e < nblk) {
                     const int k1 = e / half, k2 = e % half;
                     const int p1 = prs[2 * k1], q1 = prs[2 * k1 + 1];
