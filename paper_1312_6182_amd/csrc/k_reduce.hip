@@ -707,10 +707,12 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
 }
 
 // One workgroup: objective, trace, stopping rule, retraction coefficients.
+// m = 1: ||g||^2 is summed here from the ngram Gram partials (no k_gram_sum).
 __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __restrict__ fpart,
                        const int* __restrict__ nnzpart, double* __restrict__ vprev,
                        double* __restrict__ trace, double* __restrict__ coef,
-                       double* __restrict__ fcomp, Ctrl* __restrict__ ctrl) {
+                       double* __restrict__ fcomp, const double* __restrict__ gram, int ngram,
+                       Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ StopShared ss;
     __shared__ double red[1024];
@@ -795,8 +797,16 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
 
     const int mm = m * m;
     if (m == 1) {
+        // ||g||^2 = sum of the partials (entry 0 of each 3-entry block): strided
+        // per-thread sums, added in thread order
+        double sg = 0.0;
+        for (int g = t; g < ngram; g += nt) sg += gram[(size_t)3 * g];
+        red[t] = sg;
+        __syncthreads();
         if (t == 0) {
-            const double g2 = coef[2];
+            double g2 = 0.0;
+            for (int u = 0; u < nt; ++u) g2 += red[u];
+            coef[2] = g2;
             const double om = 1.0 / sqrt(g2);
             coef[0] = om;
             coef[1] = 0.0;
@@ -830,15 +840,18 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
                        double* vprev, Ctrl* ctrl, hipStream_t st) {
-    hipError_t e = launch_gram_sum(pl, 3 * pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st);
-    if (e != hipSuccess) return e;
-    // threads: the Jacobi steps of m = 64 have 32 x 32 blocks plus 64 x 32 rotated pairs of V
-    const int threads = pl.m > 32 ? 1024 : pl.m > 16 ? 512 : 256;
+    if (pl.m > 1) {
+        hipError_t e = launch_gram_sum(pl, 3 * pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st);
+        if (e != hipSuccess) return e;
+    }
+    // threads: the Jacobi steps of m = 64 have 32 x 32 blocks plus 64 x 32 rotated pairs of V;
+    // m = 1 needs no eigen-solver, and one wave makes every barrier free
+    const int threads = pl.m > 32 ? 1024 : pl.m > 16 ? 512 : pl.m > 1 ? 256 : 64;
     const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
-                       nnzpart, vprev, trace, coef, fcomp, ctrl);
+                       nnzpart, vprev, trace, coef, fcomp, gram, pl.gram_blocks, ctrl);
     return hipGetLastError();
 }
 
