@@ -519,7 +519,7 @@ __global__ __launch_bounds__(T) void k_corr_vx(PassParams pp, const float* __res
 constexpr int kBpThrMax = 1024;
 
 __device__ __forceinline__ bool pass_is_dense(const PassParams& pp, int thr) {
-    if (thr > kBpThrMax) return false;
+    if (thr > kBpThrMax || !pp.nact) return false;
     const int64_t na = *pp.nact;
     return na > 0 && na * kBpThrMax >= (int64_t)thr * pp.n;
 }

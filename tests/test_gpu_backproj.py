@@ -1,5 +1,5 @@
-"""Back-projection G = A S N (Section 2, Table 1) on the matrix cores
-(k_backproj_mfma) against the FP64 oracle.
+"""Back-projection G = A S N (Section 2, Table 1) on the matrix cores (the
+dense form of k_backproj and k_backproj_dense) against the FP64 oracle.
 
 A pass is back-projected densely on the matrix cores when enough of its
 columns are active, else over the active columns only
