@@ -260,10 +260,13 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
             pl->corr_M = 16;
             // m <= 16: 2, 3 or 4 stages of 4 tiles, or "8": 2 stages of 8 tiles
             // (the default: a wave's columns then fit one chunk, so X is staged
-            // once per wave -- measured 3.5% faster than 4 stages of 4 tiles)
+            // once per wave -- measured 3.5% faster than 4 stages of 4 tiles);
+            // m <= 32: 3 stages of 4 tiles, or "8" (the default, 7.6% faster at
+            // m = 32: half the X instructions per byte of A)
             pl->mfma_stages = (m <= 16) ? (((tn.stages >= 2 && tn.stages <= 4) || tn.stages == 8)
                                                ? tn.stages : 8)
-                                        : (m <= 32 ? 3 : 2);
+                            : (m <= 32) ? (tn.stages == 3 ? 3 : 8)
+                                        : 2;
             pl->rd_depth = (tn.stages == 2 || tn.stages == 3 || tn.stages == 6) ? tn.stages : 4;
             int per_cu = tn.waves > 0 ? tn.waves : 4;
             if (!pl->use_rd && !pl->use_mv)
@@ -357,6 +360,7 @@ static std::vector<Tune> tune_candidates(const gpspca_matrix* A, int m, int path
     if (A->dtype != GPSPCA_F32) {
         c.push_back(Tune{kTuneMfma, 2, 4});
         c.push_back(Tune{kTuneMfma, 3, 4});
+        c.push_back(Tune{kTuneMfma, 8, 4});
         return c;
     }
     if (m == 1 && !path && A->p <= 20480) return c;  // the fused single-unit pass
@@ -369,6 +373,7 @@ static std::vector<Tune> tune_candidates(const gpspca_matrix* A, int m, int path
         c.push_back(Tune{kTuneWg, 4, 4});
     } else {
         c.push_back(Tune{kTuneMfma, 0, 4});
+        if (m <= 32) c.push_back(Tune{kTuneMfma, 3, 4});
         c.push_back(Tune{kTuneWg, 8, 4});
     }
     c.push_back(Tune{kTuneRd, 4, 4});

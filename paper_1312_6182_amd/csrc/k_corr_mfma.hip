@@ -1056,6 +1056,8 @@ int corr_mfma_blocks_per_cu(int m, int stages) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 2>, 64, 0);
     else if (m <= 16)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<1, 3>, 64, 0);
+    else if (m <= 32 && stages == 8)  // wide chunks for two component groups
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<2, 2, 8>, 64, 0);
     else if (m <= 32)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_mfma<2, 3>, 64, 0);
     else
@@ -1076,6 +1078,8 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
         hipLaunchKernelGGL((k_corr_mfma<1, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 16)
         hipLaunchKernelGGL((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+    else if (pl.m <= 32 && pl.mfma_stages == 8)
+        hipLaunchKernelGGL((k_corr_mfma<2, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 32)
         hipLaunchKernelGGL((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else

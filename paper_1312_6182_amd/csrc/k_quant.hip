@@ -86,8 +86,6 @@ __global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ A, i
 }
 
 // ------------------------------------------------------- correlation kernel
-constexpr int kTq = 4;                       // column tiles of 16 per chunk
-constexpr int kAStageQ = 16 * kTq * 8 * 16;  // 8192 B: 64 columns x 8 slots x 16 B
 
 __device__ __forceinline__ uint32_t q_slot(int c, int s) {
     return (uint32_t)(16 * (c * 8 + (s ^ ((c >> 1) & 7))));
@@ -164,7 +162,7 @@ __device__ __forceinline__ bool thresh_q(bool l0, double mu, double gamma, float
 
 // One chunk of NT tiles of 16 columns (NT <= 4) starting at column c0 (see
 // k_corr_q).  Columns at or past cend are clamped to cend - 1 and dropped.
-template <int NT, int ST, int J, int STAGES>
+template <int NT, int ST, int J, int STAGES, int TMAX>
 __device__ __forceinline__ void q_chunk(const PassParams& pp, int64_t c0, int64_t cend,
                                         uint32_t lbase, const float* const* xcol,
                                         const float* __restrict__ Xil, double* f_acc,
@@ -176,7 +174,8 @@ __device__ __forceinline__ void q_chunk(const PassParams& pp, int64_t c0, int64_
     constexpr int XQ = 2 * EPS;                      // X row quads per stage (8 slots)
     constexpr int XDMA = XQ / 4;                     // X DMA instructions per block
     constexpr int XBlk = XQ * 16 * 16;               // X bytes per component block
-    constexpr int StageBytes = kAStageQ + J * XBlk;
+    constexpr int AStage = 16 * TMAX * 8 * 16;       // A bytes per stage: TMAX tiles x 8 slots
+    constexpr int StageBytes = AStage + J * XBlk;
     constexpr int ADMA = 2 * NT;                     // A DMA instructions (8 columns each)
     constexpr int PER = ADMA + J * XDMA;
     constexpr int G8 = EPS / 8;                      // 8-row operand groups per slot
@@ -218,7 +217,7 @@ __device__ __forceinline__ void q_chunk(const PassParams& pp, int64_t c0, int64_
                 int q = XQ * st + 4 * i + lk;
                 q = (q < nxq) ? q : nqx - 1;
                 dma(Xil + ((size_t)(jb * nqx + q) * 16 + lj) * 4,
-                    sb + kAStageQ + XBlk * jb + 1024 * i);
+                    sb + AStage + XBlk * jb + 1024 * i);
             }
     };
 
@@ -255,7 +254,7 @@ __device__ __forceinline__ void q_chunk(const PassParams& pp, int64_t c0, int64_
             for (int jb = 0; jb < J; ++jb)
 #pragma unroll
                 for (int u = 0; u < EPS / 4; ++u)
-                    xr[jb][u] = lds16(sb + kAStageQ + XBlk * jb +
+                    xr[jb][u] = lds16(sb + AStage + XBlk * jb +
                                       16u * (uint32_t)(((EPS / 4) * slot + u) * 16 + lj));
             wait_lgkm();
 #pragma unroll
@@ -354,7 +353,7 @@ __device__ __forceinline__ void q_chunk(const PassParams& pp, int64_t c0, int64_
 
 // ST: kStBF16 | kStF8;  J: component blocks of 16;  STAGES: stages in flight.
 // Work partition as in k_corr_mfma: whole tiles of 16 columns per wave.
-template <int ST, int J, int STAGES>
+template <int ST, int J, int STAGES, int TMAX = 4>
 __global__ __launch_bounds__(64) void k_corr_q(PassParams pp, const float* __restrict__ X,
                                                const float* __restrict__ Xil,
                                                float* __restrict__ S, uint8_t* __restrict__ act,
@@ -364,7 +363,7 @@ __global__ __launch_bounds__(64) void k_corr_q(PassParams pp, const float* __res
     if (ctrl->done) return;
     constexpr int EPS = (ST == kStBF16) ? 8 : 16;
     constexpr int XBlk = 2 * EPS * 16 * 16;
-    constexpr int StageBytes = kAStageQ + J * XBlk;
+    constexpr int StageBytes = 16 * TMAX * 8 * 16 + J * XBlk;
     __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
 
@@ -386,16 +385,31 @@ __global__ __launch_bounds__(64) void k_corr_q(PassParams pp, const float* __res
 #pragma unroll
     for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
 
-    for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kTq) {
+    // chunks of up to TMAX tiles; the chunk code is specialized per tile count
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * TMAX) {
         const int64_t left = cend - c0;
-        if (left > 48)
-            q_chunk<4, ST, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
-        else if (left > 32)
-            q_chunk<3, ST, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
-        else if (left > 16)
-            q_chunk<2, ST, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
-        else
-            q_chunk<1, ST, J, STAGES>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act);
+        const int nt = left >= 16 * TMAX ? TMAX : (int)((left + 15) / 16);
+#define GPSPCA_QC(NT) q_chunk<NT, ST, J, STAGES, TMAX>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act)
+        if constexpr (TMAX == 8) {
+            switch (nt) {
+                case 8: GPSPCA_QC(8); break;
+                case 7: GPSPCA_QC(7); break;
+                case 6: GPSPCA_QC(6); break;
+                case 5: GPSPCA_QC(5); break;
+                case 4: GPSPCA_QC(4); break;
+                case 3: GPSPCA_QC(3); break;
+                case 2: GPSPCA_QC(2); break;
+                default: GPSPCA_QC(1); break;
+            }
+        } else {
+            switch (nt) {
+                case 4: GPSPCA_QC(4); break;
+                case 3: GPSPCA_QC(3); break;
+                case 2: GPSPCA_QC(2); break;
+                default: GPSPCA_QC(1); break;
+            }
+        }
+#undef GPSPCA_QC
     }
 
 #pragma unroll
@@ -426,19 +440,26 @@ hipError_t launch_quantize(const float* A, int64_t lda, int p, int64_t n, int to
 }
 
 // Component blocks of the quantized kernel, and the stage counts it is built
-// for: (storage, J) -> stages {2, 3} for bfloat16 with J <= 2, else {2}.
+// for: (storage, J) -> {2, 3, 8} for bfloat16 with J <= 2, {2, 8} for e4m3
+// with J <= 2, else {2}.
 static int q_blocks(int m) { return m <= 16 ? 1 : m <= 32 ? 2 : 4; }
 
+// "8": 2 stages of chunks of up to 8 tiles, half the X instructions per byte
+// of A -- the bfloat16 default for J <= 2 (24% faster at J = 2); e4m3 keeps
+// 4-tile chunks (its 8-tile stages leave room for only two waves per CU, 10%
+// slower at J = 2).
 int corr_q_stages(int dtype, int m, int want) {
     const int J = q_blocks(m);
-    if (dtype == GPSPCA_BF16 && J <= 2) return want == 2 ? 2 : 3;
+    if (dtype == GPSPCA_BF16 && J <= 2) return (want == 2 || want == 3) ? want : 8;
+    if (J <= 2 && want == 8) return 8;
     return 2;
 }
 
-template <int ST, int J, int S>
+template <int ST, int J, int S, int TMAX = 4>
 static int occ_q() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_q<ST, J, S>, 64, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_corr_q<ST, J, S, TMAX>, 64, 0) !=
+        hipSuccess)
         nb = 1;
     (void)hipGetLastError();
     return nb;
@@ -447,7 +468,10 @@ static int occ_q() {
 int corr_q_blocks_per_cu(int dtype, int m, int stages) {
     const int J = q_blocks(m);
     int nb;
-    if (dtype == GPSPCA_BF16) {
+    if (stages == 8 && J <= 2) {
+        if (dtype == GPSPCA_BF16) nb = J == 1 ? occ_q<kStBF16, 1, 2, 8>() : occ_q<kStBF16, 2, 2, 8>();
+        else nb = J == 1 ? occ_q<kStF8, 1, 2, 8>() : occ_q<kStF8, 2, 2, 8>();
+    } else if (dtype == GPSPCA_BF16) {
         if (J == 1) nb = stages == 2 ? occ_q<kStBF16, 1, 2>() : occ_q<kStBF16, 1, 3>();
         else if (J == 2) nb = stages == 2 ? occ_q<kStBF16, 2, 2>() : occ_q<kStBF16, 2, 3>();
         else nb = occ_q<kStBF16, 4, 2>();
@@ -467,7 +491,18 @@ hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, c
 #define GPSPCA_CQ(STT, JJ, SS) \
     hipLaunchKernelGGL((k_corr_q<STT, JJ, SS>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
                        nnzpart, ctrl)
-    if (pl.dtype == GPSPCA_BF16) {
+#define GPSPCA_CQW(STT, JJ) \
+    hipLaunchKernelGGL((k_corr_q<STT, JJ, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
+                       nnzpart, ctrl)
+    if (Sg == 8 && J <= 2) {
+        if (pl.dtype == GPSPCA_BF16) {
+            if (J == 1) GPSPCA_CQW(kStBF16, 1);
+            else GPSPCA_CQW(kStBF16, 2);
+        } else {
+            if (J == 1) GPSPCA_CQW(kStF8, 1);
+            else GPSPCA_CQW(kStF8, 2);
+        }
+    } else if (pl.dtype == GPSPCA_BF16) {
         if (J == 1 && Sg == 2) GPSPCA_CQ(kStBF16, 1, 2);
         else if (J == 1) GPSPCA_CQ(kStBF16, 1, 3);
         else if (J == 2 && Sg == 2) GPSPCA_CQ(kStBF16, 2, 2);
@@ -478,6 +513,7 @@ hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, c
         else if (J == 2) GPSPCA_CQ(kStF8, 2, 2);
         else GPSPCA_CQ(kStF8, 4, 2);
     }
+#undef GPSPCA_CQW
 #undef GPSPCA_CQ
     return hipGetLastError();
 }

@@ -146,3 +146,27 @@ def test_register_direct_kernels_component_groups(gpu, kernel, m, p, n, monkeypa
     np.testing.assert_array_equal((S != 0)[~ties], (ref["S"] != 0)[~ties])
     assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
     np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
+
+
+@pytest.mark.parametrize("stages", ["3", "8"])
+@pytest.mark.parametrize("m,p,n", [(20, 1003, 3001), (32, 2050, 1999), (17, 257, 700)])
+def test_matrix_core_two_groups_stage_variants(gpu, stages, m, p, n, monkeypatch):
+    """The LDS-DMA matrix-core kernel with two component groups, in chunks of
+    up to 4 tiles (3 stages) and of up to 8 tiles (2 stages): one step against
+    the oracle, with ragged rows and ragged tiles."""
+    monkeypatch.setenv("GPSPCA_CORR_KERNEL", "mfma")
+    monkeypatch.setenv("GPSPCA_MFMA_STAGES", stages)
+    print(f"\n[corr mfma stages={stages}] m={m} p={p} n={n}", flush=True)
+    A32, _, _ = W.planted_block(p, n, 4, 120 + m, k=min(40, n // 4))
+    A64 = A32.astype(np.float64)
+    mu = np.linspace(1.0, 0.7, m)
+    X0 = fp32_round(O.init(A64, m)[0])
+    gamma = W.gamma_absolute(A64, False, 0.05)
+    Ad = to_device(A32, lda=(p + 3) // 4 * 4)
+    ref = O.step(A64, O.BL1, X0, gamma, mu=mu)
+    out = gpu.step(Ad, O.BL1, x_to_device(X0), gamma, mu=list(mu))
+    ties = tie_mask(A64, X0, O.BL1, gamma, mu)
+    S = out.S.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal((S != 0)[~ties], (ref["S"] != 0)[~ties])
+    assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
+    np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
