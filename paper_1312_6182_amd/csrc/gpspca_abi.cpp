@@ -292,7 +292,13 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         }
         pl->bp_kq = 2;
         pl->bp_rb = (int)cdiv(nq, 256 * pl->bp_kq);
-        int64_t cr = std::min<int64_t>(cdiv(A->n, 1024), std::max<int64_t>(1, (4LL * ncu) / pl->bp_rb));
+        // column ranges of >= 1024 columns, about 4 workgroups per CU in all; a
+        // matrix too small to give every CU a workgroup that way takes ranges of
+        // >= 128 columns instead (each workgroup walks its range's active
+        // columns in dependent batches, so long ranges are latency-bound)
+        const int64_t want = std::max<int64_t>(1, (4LL * ncu) / pl->bp_rb);
+        int64_t cr = std::min<int64_t>(cdiv(A->n, 1024), want);
+        if (cr * pl->bp_rb < ncu) cr = std::min<int64_t>(cdiv(A->n, 128), want);
         pl->bp_cr = (int)std::max<int64_t>(1, cr);
         pl->npart = pl->bp_cr;
         pl->bp_thr = backproj_threshold(A, m, pl->vec4, restricted);
@@ -307,11 +313,15 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     split = std::min<int64_t>(split, std::max<int64_t>(1, pl->npart / 8));
     split = std::min<int64_t>(split, 64);
     pl->red_split = (int)std::max<int64_t>(1, split);
+    // row blocks of the Gram products: 256 rows, 128 when the LDS tile would
+    // not fit, and (m > 1) 64 when 128-row blocks would leave CUs without one
     pl->gram_rows = ((size_t)(m + 1) * 256 * 16 <= 140000) ? 256 : 128;
+    if (m > 1 && cdiv(A->p, 128) < ncu) pl->gram_rows = 64;
     pl->gram_grid = (int)cdiv(A->p, pl->gram_rows);
-    // the fused m = 1 pass leaves one partial per workgroup (hundreds): those
-    // are summed faster by the split reduction
-    pl->fused_gram = (m <= 16 && !pl->fused_m1) ? 1 : 0;
+    // the fused m = 1 pass leaves one partial per workgroup (hundreds), and
+    // small matrices take many short column ranges: hundreds of partials are
+    // summed faster by the split reduction, whose grid also spans the partials
+    pl->fused_gram = (m <= 16 && !pl->fused_m1 && pl->npart <= 128) ? 1 : 0;
     pl->gram_blocks = pl->fused_gram ? (int)cdiv(A->p, 64) : pl->gram_grid;
     pl->fin_grid = (int)std::max<int64_t>(1, cdiv(cdiv(A->n, 32), 256));
     pl->topm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(A->n, 1024)));
