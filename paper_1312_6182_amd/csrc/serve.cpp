@@ -97,6 +97,8 @@ struct Server {
     }
     void worker(int slot);
     int upload(SMatrix& M, size_t off, int slot, hipStream_t st, std::string* err);
+    hipError_t download(const void* const* src, void* const* dst, const size_t* bytes, int count,
+                        int slot, hipStream_t st);
 };
 
 // Copy a registered host matrix into the arena at `off`, then its column
@@ -171,6 +173,43 @@ int Server::upload(SMatrix& M, size_t off, int slot, hipStream_t st, std::string
     }
     if (!hip_ok(hipStreamSynchronize(st), "upload")) return GPSPCA_EDEVICE;
     return GPSPCA_OK;
+}
+
+// Device-to-host copies of a request's results through the slot's pinned
+// buffer (into pageable memory the runtime would stage each copy itself, at a
+// fraction of the bandwidth): as many arrays per round trip as fit, larger
+// ones in chunks.
+hipError_t Server::download(const void* const* src, void* const* dst, const size_t* bytes,
+                            int count, int slot, hipStream_t st) {
+    uint8_t* buf = pinned[slot];
+    int i = 0;
+    size_t done_i = 0;   // bytes of array i already copied
+    while (i < count) {
+        // fill the buffer with the rest of array i and as many next arrays as fit
+        struct Piece { int a; size_t from, nb, at; };
+        Piece pc[8];
+        int np = 0;
+        size_t used = 0;
+        while (i < count && np < 8 && used < kPinnedBytes) {
+            const size_t nb = std::min(bytes[i] - done_i, kPinnedBytes - used);
+            if (nb > 0) {
+                const hipError_t e = hipMemcpyAsync(buf + used,
+                                                    static_cast<const uint8_t*>(src[i]) + done_i, nb,
+                                                    hipMemcpyDeviceToHost, st);
+                if (e != hipSuccess) return e;
+                pc[np++] = Piece{i, done_i, nb, used};
+                used += (nb + 255) & ~(size_t)255;
+            }
+            done_i += nb;
+            if (done_i == bytes[i]) { ++i; done_i = 0; }
+            if (used >= kPinnedBytes) break;
+        }
+        const hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        for (int k = 0; k < np; ++k)
+            std::memcpy(static_cast<uint8_t*>(dst[pc[k].a]) + pc[k].from, buf + pc[k].at, pc[k].nb);
+    }
+    return hipSuccess;
 }
 
 void Server::worker(int slot) {
@@ -261,15 +300,11 @@ void Server::worker(int slot) {
                 R->X.resize((size_t)M->p * R->m);
                 R->Z.resize((size_t)M->n * R->m);
                 R->support.resize(words * R->m);
-                hipError_t e = hipMemcpyAsync(R->X.data(), Xd, sizeof(float) * R->X.size(),
-                                              hipMemcpyDeviceToHost, st);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(R->Z.data(), Zd, sizeof(float) * R->Z.size(),
-                                       hipMemcpyDeviceToHost, st);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(R->support.data(), Sd, sizeof(uint32_t) * R->support.size(),
-                                       hipMemcpyDeviceToHost, st);
-                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                const void* src[3] = {Xd, Zd, Sd};
+                void* dst[3] = {R->X.data(), R->Z.data(), R->support.data()};
+                const size_t nbytes[3] = {sizeof(float) * R->X.size(), sizeof(float) * R->Z.size(),
+                                          sizeof(uint32_t) * R->support.size()};
+                hipError_t e = download(src, dst, nbytes, 3, slot, st);
                 if (e != hipSuccess) {
                     rc = GPSPCA_EDEVICE;
                     err = hipGetErrorString(e);
