@@ -210,6 +210,35 @@ def solve(A, form: int, m: int, gamma: float, mu=None, X0=None, tol: float = 1e-
     return dict(X=X, Z=Z, support=sup.astype(bool), trace=trace[:k].copy(), n_iter=k, status=rc)
 
 
+def solve_deflated(A, form: int, m: int, gamma: float, tol: float = 1e-4, max_iter: int = 1000):
+    """m single-unit components by projection deflation (the paper times its
+    single-unit formulations with several components, Section 4.1, without
+    stating how they are obtained; this is the reading): component k is the
+    single-unit solve (form SL1 or SL0) on A_k = (I - X_{<k} X_{<k}^T) A from
+    the default start of A_k, its normalized column of largest norm.  Each
+    deflation is applied explicitly in FP64.  Returns dict(X, Z, support,
+    traces, n_iter, status) with one column / entry per component."""
+    A = np.asarray(A, dtype=np.float64)
+    p, n = A.shape
+    X = np.zeros((p, m), order="F")
+    Z = np.zeros((n, m), order="F")
+    sup = np.zeros((n, m), dtype=bool)
+    traces, n_iter, status = [], [], []
+    Ak = np.array(A, order="F")
+    for k in range(m):
+        if k > 0:
+            q = X[:, k - 1:k]
+            Ak = np.asfortranarray(Ak - q @ (q.T @ Ak))
+        r = solve(Ak, form, 1, gamma, tol=tol, max_iter=max_iter)
+        X[:, k] = r["X"][:, 0]
+        Z[:, k] = r["Z"][:, 0]
+        sup[:, k] = r["support"][:, 0]
+        traces.append(r["trace"])
+        n_iter.append(r["n_iter"])
+        status.append(r["status"])
+    return dict(X=X, Z=Z, support=sup, traces=traces, n_iter=n_iter, status=status)
+
+
 # ---------------------------------------------------------------- storage
 BF16, E4M3 = 1, 2
 
