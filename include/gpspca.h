@@ -175,6 +175,36 @@ int gpspca_solve_multistart(const gpspca_matrix* A, int form, int m, double gamm
                             int* n_iter, int* status);
 
 /*
+ * m sparse components of a single-unit formulation (form GPSPCA_SL1 or
+ * GPSPCA_SL0, Section 2, Table 1, rows 1-2) by projection deflation: component
+ * k is the single-unit solve on A_k = (I - Q Q^T) A, Q = [x_0 .. x_{k-1}] the
+ * components already found, from the default start of A_k (its column of
+ * largest norm, ties to the lower index, normalized).  The paper reports
+ * single-unit timings for several components (Section 4.1) without fixing how
+ * they are obtained; deflation of the data matrix is the reading taken here.
+ * A_k is never formed: A_k^T x = A^T x for x in the range of I - Q Q^T, so each
+ * pass runs on A and the new iterate is projected back, x <- P x / ||P x||, in
+ * FP64 (P = I - Q Q^T).  FP32 storage only.
+ *
+ *  m          1 <= m <= min(p, n, GPSPCA_MAX_M) components.
+ *  gamma      absolute weight >= 0, the same for every component.
+ *  workspace  >= gpspca_deflated_workspace_bytes(A, m, max_iter) bytes,
+ *             256-aligned (device; holds Q in FP64 besides one solve's memory).
+ * Outputs: X (device p x m, leading dim p), Z (device n x m), support (device
+ * ceil(n/32) x m words) as in gpspca_solve, component k in column k;
+ * obj_trace (host, m x max_iter doubles, component k's trace at
+ * obj_trace[k * max_iter ...], n_iter[k] entries valid); n_iter and status
+ * (host, m ints).  Returns GPSPCA_OK when every component converged, the
+ * largest per-component status otherwise, or a negative error (EDTYPE for
+ * 16/8-bit storage).  Synchronizes `stream`.
+ */
+size_t gpspca_deflated_workspace_bytes(const gpspca_matrix* A, int m, int max_iter);
+int gpspca_solve_deflated(const gpspca_matrix* A, int form, int m, double gamma, double tol,
+                          int max_iter, void* workspace, size_t ws_bytes, void* stream,
+                          float* X, float* Z, uint32_t* support, double* obj_trace,
+                          int* n_iter, int* status);
+
+/*
  * Refinement on a frozen support (for results of a reduced-precision solve).
  * Runs passes of the iteration of gpspca_solve on the FP32 matrix A in which
  * s_ij is forced to 0 wherever bit (i % 32) of word (j * ceil(n/32) + i/32) of

@@ -16,7 +16,7 @@ def __getattr__(name):
     # (e.g. for symbol checks) does not require a GPU.
     if name in ("solve", "step", "column_norms", "workspace_bytes", "matrix", "column_major",
                 "profile_enable", "profile_read", "SolveResult", "StepResult", "solve_path",
-                "solve_multistart",
+                "solve_multistart", "solve_deflated",
                 "PathResult", "quantize", "refine", "refine_path", "autotune", "autotune_clear"):
         from . import api
         return getattr(api, name)

@@ -52,6 +52,9 @@ SIGNATURES = {
     "gpspca_solve_path": (_I, [_MP, _I, _I, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P, _P]),
     "gpspca_solve_multistart": (_I, [_MP, _I, _I, _D, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P,
                                      _P]),
+    "gpspca_deflated_workspace_bytes": (_SZ, [_MP, _I, _I]),
+    "gpspca_solve_deflated": (_I, [_MP, _I, _I, _D, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P,
+                                   _P]),
     "gpspca_refine": (_I, [_MP, _I, _I, _D, _P, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P]),
     "gpspca_refine_path": (_I, [_MP, _I, _I, _P, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P,
                                 _P]),

@@ -261,6 +261,34 @@ def solve_multistart(A: torch.Tensor, form: int, m: int, gamma: float, tol: floa
                       status=list(sts), rc=rc)
 
 
+def solve_deflated(A: torch.Tensor, form: int, m: int, gamma: float, tol: float = 1e-4,
+                   max_iter: int = 1000,
+                   stream: Optional[torch.cuda.Stream] = None) -> PathResult:
+    """m single-unit components by projection deflation, component k solved on
+    (I - X_{<k} X_{<k}^T) A from that matrix's default start
+    (gpspca_solve_deflated; FP32 A)."""
+    lib = L.load()
+    M = matrix(A)
+    p, n = A.shape
+    nb = lib.gpspca_deflated_workspace_bytes(ctypes.byref(M), m, max_iter)
+    if nb == 0:
+        raise L.GpspcaError(L.EINVAL, L.last_error())
+    ws = _workspace(int(nb), A.device)
+    Xt = torch.empty((m, p), dtype=torch.float32, device=A.device)
+    Zt = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    sup = torch.empty((m, (n + 31) // 32), dtype=torch.int32, device=A.device)
+    tr = (ctypes.c_double * (m * max_iter))()
+    nit = (ctypes.c_int * m)()
+    sts = (ctypes.c_int * m)()
+    rc = lib.gpspca_solve_deflated(ctypes.byref(M), form, m, float(gamma), float(tol),
+                                   int(max_iter), ws.data_ptr(), ws.numel(), _stream_ptr(stream),
+                                   Xt.data_ptr(), Zt.data_ptr(), sup.data_ptr(), tr, nit, sts)
+    L.check(rc, "gpspca_solve_deflated")
+    traces = [list(tr[k * max_iter:k * max_iter + nit[k]]) for k in range(m)]
+    return PathResult(X=Xt.t(), Z=Zt.t(), support=sup, traces=traces, n_iter=list(nit),
+                      status=list(sts), rc=rc)
+
+
 def quantize(A: torch.Tensor, dtype: torch.dtype, stream: Optional[torch.cuda.Stream] = None):
     """Reduced-precision copy of the FP32 device matrix A (p, n) (gpspca_quantize).
 

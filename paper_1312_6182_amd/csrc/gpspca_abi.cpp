@@ -590,6 +590,12 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
     }
     GPSPCA_HIP(launch_apply(pl, P.g64, Xk, P.coef, Xn,
                             (pl.use_mfma || pl.use_q) ? P.xil[(k + 1) & 1] : nullptr, P.ctrl, st));
+    if (pl.defl_k > 0) {
+        // deflated component: x <- P x / ||P x|| (g64 is free once applied)
+        GPSPCA_HIP(launch_deflate((int)pl.p, pl.defl_k, pl.defl_q, Xn, nullptr, Xn, P.g64,
+                                  P.ctrl, st));
+        if (pl.use_mfma || pl.use_q) GPSPCA_HIP(launch_x_interleave(pl, Xn, P.xil[(k + 1) & 1], st));
+    }
     return GPSPCA_OK;
 }
 
@@ -725,7 +731,8 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
                const double* gammas, int path, const uint32_t* mask, const float* X0,
                double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
                float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
-               int* status_out, const double* norms_in, int multistart) {
+               int* status_out, const double* norms_in, int multistart, const double* defl_q,
+               int defl_k) {
     int ncu = 0;
     int rc = device_cus(&ncu);
     if (rc) return rc;
@@ -733,6 +740,8 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
     Plan pl;
     make_plan(A, pform, m, max_iter, ncu, &pl, path, mask ? 1 : 0);
     if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
+    pl.defl_q = defl_q;
+    pl.defl_k = defl_q ? defl_k : 0;
     const Ptrs P = carve(pl, workspace);
     PassParams pp = make_params(A, pl, gamma, mu, gammas);
     pp.nact = &P.ctrl->nact;
@@ -1006,6 +1015,92 @@ int gpspca_solve_multistart(const gpspca_matrix* A, int form, int m, double gamm
     return solve_core(A, form, m, 0.0, nullptr, gammas.data(), 1, nullptr, nullptr, tol,
                       max_iter, workspace, ws_bytes, static_cast<hipStream_t>(stream), X, Z,
                       support, obj_trace, n_iter, status, nullptr, 1);
+}
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The single-unit solve's share of a deflation workspace (either form).
+static size_t deflated_core(const gpspca_matrix* A, int max_iter, int ncu) {
+    return al256(std::max(workspace_all(A, GPSPCA_SL1, 1, max_iter, ncu, 0),
+                          workspace_all(A, GPSPCA_SL0, 1, max_iter, ncu, 0)));
+}
+
+size_t gpspca_deflated_workspace_bytes(const gpspca_matrix* A, int m, int max_iter) {
+    if (check_problem(A, GPSPCA_SL1, 1, 0.0, nullptr) != GPSPCA_OK) return 0;
+    if (m < 1 || m > kMaxM || m > A->p || m > A->n) {
+        fail(GPSPCA_EINVAL, "need 1 <= m <= min(p, n, GPSPCA_MAX_M)");
+        return 0;
+    }
+    if (max_iter < 1) {
+        fail(GPSPCA_EINVAL, "max_iter must be >= 1");
+        return 0;
+    }
+    int ncu = 0;
+    if (device_cus(&ncu) != GPSPCA_OK) return 0;
+    const size_t P = (size_t)A->p;
+    return deflated_core(A, max_iter, ncu) + al256(sizeof(double) * P * m) +
+           al256(sizeof(float) * P) + al256(sizeof(double) * P);
+}
+
+int gpspca_solve_deflated(const gpspca_matrix* A, int form, int m, double gamma, double tol,
+                          int max_iter, void* workspace, size_t ws_bytes, void* stream, float* X,
+                          float* Z, uint32_t* support, double* obj_trace, int* n_iter,
+                          int* status) {
+    if (form != GPSPCA_SL1 && form != GPSPCA_SL0)
+        return fail(GPSPCA_EINVAL, "deflation takes a single-unit formulation");
+    int rc = check_problem(A, form, 1, gamma, nullptr);
+    if (rc) return rc;
+    if (A->dtype != GPSPCA_F32) return fail(GPSPCA_EDTYPE, "deflation runs on FP32 storage");
+    rc = check_run(tol, max_iter, X, workspace);
+    if (rc) return rc;
+    if (!Z || !support || !obj_trace || !n_iter || !status)
+        return fail(GPSPCA_EINVAL, "NULL output");
+    const size_t need = gpspca_deflated_workspace_bytes(A, m, max_iter);
+    if (need == 0) return GPSPCA_EINVAL;
+    if (ws_bytes < need) return fail(GPSPCA_ENOMEM, "workspace too small");
+    int ncu = 0;
+    rc = device_cus(&ncu);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t P = (size_t)A->p;
+    const int64_t words = cdiv(A->n, 32);
+    // the single-unit solve's workspace, then Q, the start and a scratch vector
+    const size_t core = deflated_core(A, max_iter, ncu);
+    uint8_t* base = static_cast<uint8_t*>(workspace);
+    double* Q = reinterpret_cast<double*>(base + core);
+    float* x0 = reinterpret_cast<float*>(base + core + al256(sizeof(double) * P * m));
+    double* scratch = reinterpret_cast<double*>(base + core + al256(sizeof(double) * P * m) +
+                                                al256(sizeof(float) * P));
+    Plan p1;
+    make_plan(A, form, 1, max_iter, ncu, &p1);
+    int worst = GPSPCA_OK;
+    for (int k = 0; k < m; ++k) {
+        const float* start = nullptr;
+        if (k > 0) {
+            // default start of the deflated matrix: its column of largest norm,
+            // projected and normalized
+            const Ptrs W = carve(p1, workspace);
+            const PassParams pp1 = make_params(A, p1, gamma, nullptr);
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 4)));
+            GPSPCA_HIP(launch_defl_norms(static_cast<const float*>(A->data), A->lda, (int)A->p,
+                                         A->n, k, Q, W.norms, grid, st));
+            GPSPCA_HIP(launch_topm(p1, W.norms, W.cand_v, W.cand_i, W.idx, st));
+            GPSPCA_HIP(launch_gather(p1, pp1, W.idx, W.g64, st));
+            GPSPCA_HIP(launch_deflate((int)A->p, k, Q, nullptr, W.g64, x0, scratch, nullptr, st));
+            start = x0;
+        }
+        rc = solve_core(A, form, 1, gamma, nullptr, nullptr, 0, nullptr, start, tol, max_iter,
+                        workspace, core, st, X + (size_t)k * P, Z + (size_t)k * A->n,
+                        support + (size_t)k * words, obj_trace + (size_t)k * max_iter,
+                        &n_iter[k], nullptr, nullptr, 0, k > 0 ? Q : nullptr, k);
+        if (rc < 0) return rc;
+        status[k] = rc;
+        if (rc > worst) worst = rc;
+        GPSPCA_HIP(launch_append_basis((int)A->p, X + (size_t)k * P, Q + (size_t)k * P, st));
+    }
+    GPSPCA_HIP(hipStreamSynchronize(st));
+    if (worst != GPSPCA_OK) g_err = "some component flagged (see status)";
+    return worst;
 }
 
 int gpspca_refine_path(const gpspca_matrix* A, int form, int K, const double* gammas,

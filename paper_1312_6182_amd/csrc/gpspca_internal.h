@@ -102,6 +102,8 @@ struct Plan {
     int vx_threads, vx_kq;
     int use_mv;            // block correlation on the matrix cores, A staged through registers
     int path;              // gamma path: independent single-unit columns (normalize, per-column stop)
+    const double* defl_q;  // deflated component: basis of the earlier components (p x defl_k, FP64)
+    int defl_k;            // ... and their count (0: no deflation)
     // workspace offsets (bytes)
     size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
         o_l1, o_g64, o_gram, o_coef, o_norms, o_cand_v, o_cand_i, o_idx, o_fin, o_invn, o_fcomp,
@@ -209,12 +211,19 @@ inline size_t coef_omega(int m) { return 0; }
 inline size_t coef_psi(int m) { return (size_t)m * m; }
 
 // ---- host driver (gpspca_abi.cpp), shared with the server (serve.cpp) ----
+hipError_t launch_deflate(int p, int k, const double* Q, const float* xf, const double* xd,
+                          float* out, double* scratch, const Ctrl* ctrl, hipStream_t st);
+hipError_t launch_defl_norms(const float* A, int64_t lda, int p, int64_t n, int k,
+                             const double* Q, double* norms, int grid, hipStream_t st);
+hipError_t launch_append_basis(int p, const float* x, double* q, hipStream_t st);
+
 int fail(int code, const std::string& msg);
 int check_problem(const gpspca_matrix* A, int form, int m, double gamma, const double* mu);
 int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
                const double* gammas, int path, const uint32_t* mask, const float* X0,
                double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
                float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
-               int* status_out, const double* norms_in, int multistart = 0);
+               int* status_out, const double* norms_in, int multistart = 0,
+               const double* defl_q = nullptr, int defl_k = 0);
 
 }  // namespace gpspca

@@ -1101,6 +1101,103 @@ hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, cons
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Deflated single-unit components.  P = I - Q Q^T with Q (p x k, leading dim
+// p, FP64) the earlier components.
+//
+// k_deflate: out = P x / ||P x|| in FP64 from FP32 x (xf) or FP64 x (xd), to
+// FP32; one workgroup of 1024 threads, fixed-order tree sums.  P x = 0 gives 0
+// (the next pass then has F = 0 and stops).  In place (out == xf) is allowed.
+__global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __restrict__ Q,
+                                                  const float* xf, const double* xd, float* out,
+                                                  double* __restrict__ scratch,
+                                                  const Ctrl* __restrict__ ctrl) {
+    if (ctrl && ctrl->done) return;
+    __shared__ double red[1024];
+    __shared__ double c[kMaxM];
+    const int t = threadIdx.x, nt = blockDim.x;
+    auto xin = [&](int r) { return xd ? xd[r] : (double)xf[r]; };
+    auto block_sum = [&](double v) -> double {
+        red[t] = v;
+        __syncthreads();
+        for (int h = nt / 2; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        const double r0 = red[0];
+        __syncthreads();
+        return r0;
+    };
+    for (int j = 0; j < k; ++j) {
+        double sj = 0.0;
+        for (int r = t; r < p; r += nt) sj += Q[(size_t)j * p + r] * xin(r);
+        const double cj = block_sum(sj);
+        if (t == 0) c[j] = cj;
+    }
+    __syncthreads();
+    double s2 = 0.0;
+    for (int r = t; r < p; r += nt) {
+        double y = xin(r);
+        for (int j = 0; j < k; ++j) y -= Q[(size_t)j * p + r] * c[j];
+        scratch[r] = y;
+        s2 += y * y;
+    }
+    const double nrm2 = block_sum(s2);
+    const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+    for (int r = t; r < p; r += nt) out[r] = (float)(scratch[r] * inv);
+}
+
+hipError_t launch_deflate(int p, int k, const double* Q, const float* xf, const double* xd,
+                          float* out, double* scratch, const Ctrl* ctrl, hipStream_t st) {
+    hipLaunchKernelGGL(k_deflate, dim3(1), dim3(1024), 0, st, p, k, Q, xf, xd, out, scratch, ctrl);
+    return hipGetLastError();
+}
+
+// k_defl_norms: ||P a_i|| = sqrt(||a_i||^2 - sum_j (q_j^T a_i)^2) in FP64 for
+// every column of the FP32 matrix (one wave per column at a time; the column
+// is read k + 1 times, from cache after the first): the default start of a
+// deflated component.
+__global__ __launch_bounds__(256) void k_defl_norms(const float* __restrict__ A, int64_t lda,
+                                                    int p, int64_t n, int k,
+                                                    const double* __restrict__ Q,
+                                                    double* __restrict__ norms) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += nw) {
+        const float* a = A + i * lda;
+        double ss = 0.0;
+        for (int r = lane; r < p; r += 64) ss += (double)a[r] * a[r];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+        double dd = 0.0;
+        for (int j = 0; j < k; ++j) {
+            double d = 0.0;
+            for (int r = lane; r < p; r += 64) d += Q[(size_t)j * p + r] * a[r];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+            dd += d * d;
+        }
+        if (lane == 0) norms[i] = sqrt(fmax(ss - dd, 0.0));
+    }
+}
+
+hipError_t launch_defl_norms(const float* A, int64_t lda, int p, int64_t n, int k,
+                             const double* Q, double* norms, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_defl_norms, dim3(grid), dim3(256), 0, st, A, lda, p, n, k, Q, norms);
+    return hipGetLastError();
+}
+
+// Q[:, k] = x (FP32 -> FP64)
+__global__ void k_append_basis(int p, const float* __restrict__ x, double* __restrict__ q) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < p) q[r] = (double)x[r];
+}
+
+hipError_t launch_append_basis(int p, const float* x, double* q, hipStream_t st) {
+    hipLaunchKernelGGL(k_append_basis, dim3((p + 255) / 256), dim3(256), 0, st, p, x, q);
+    return hipGetLastError();
+}
+
 // One thread per (block, quad, component): a 16-byte vector of 4 rows.
 __global__ __launch_bounds__(256) void k_x_interleave(int mpad, int ldx,
                                                       const float* __restrict__ X,
