@@ -588,13 +588,16 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
         GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp,
                                P.coef + 5 * (size_t)pl.m * pl.m, P.ctrl, st));
     }
-    GPSPCA_HIP(launch_apply(pl, P.g64, Xk, P.coef, Xn,
-                            (pl.use_mfma || pl.use_q) ? P.xil[(k + 1) & 1] : nullptr, P.ctrl, st));
     if (pl.defl_k > 0) {
-        // deflated component: x <- P x / ||P x|| (g64 is free once applied)
-        GPSPCA_HIP(launch_deflate((int)pl.p, pl.defl_k, pl.defl_q, Xn, nullptr, Xn, P.g64,
+        // deflated component (m = 1): x_{k+1} = P g / ||P g|| straight from the
+        // FP64 g, which the normalization of the plain retraction would only scale
+        GPSPCA_HIP(launch_deflate((int)pl.p, pl.defl_k, pl.defl_q, nullptr, P.g64, Xn, P.g64,
                                   P.ctrl, st));
         if (pl.use_mfma || pl.use_q) GPSPCA_HIP(launch_x_interleave(pl, Xn, P.xil[(k + 1) & 1], st));
+    } else {
+        GPSPCA_HIP(launch_apply(pl, P.g64, Xk, P.coef, Xn,
+                                (pl.use_mfma || pl.use_q) ? P.xil[(k + 1) & 1] : nullptr, P.ctrl,
+                                st));
     }
     return GPSPCA_OK;
 }

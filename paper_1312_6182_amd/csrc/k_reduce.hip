@@ -90,6 +90,16 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
     double s = 0.0;
     int c = c0;
     if (staged) {
+        // in order of c, skipping untouched partials; the loads of 4 partials
+        // are issued together (an untouched one is read but not added)
+        for (; c + 4 <= c1; c += 4) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = gpart[(size_t)(c + u) * ne + e];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (tf[c + u - c0]) s += (double)v[u];
+        }
         for (; c < c1; ++c)
             if (tf[c - c0]) s += (double)gpart[(size_t)c * ne + e];
     } else if (!touched) {
@@ -191,8 +201,18 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ l1, int
         const int rr = e % nr, j = e / nr;
         double s;
         if (l1) {
+            // in order of y; the loads of 8 splits are issued together
+            const double* src = l1 + (size_t)j * ldx + r0 + rr;
             s = 0.0;
-            for (int y = 0; y < nsplit; ++y) s += l1[(size_t)y * ne + (size_t)j * ldx + r0 + rr];
+            int y = 0;
+            for (; y + 8 <= nsplit; y += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(y + u) * ne];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += v[u];
+            }
+            for (; y < nsplit; ++y) s += src[(size_t)y * ne];
             g64[(size_t)j * p + r0 + rr] = s;
         } else {
             s = g64[(size_t)j * p + r0 + rr];
@@ -1106,45 +1126,70 @@ hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, cons
 // p, FP64) the earlier components.
 //
 // k_deflate: out = P x / ||P x|| in FP64 from FP32 x (xf) or FP64 x (xd), to
-// FP32; one workgroup of 1024 threads, fixed-order tree sums.  P x = 0 gives 0
-// (the next pass then has F = 0 and stops).  In place (out == xf) is allowed.
+// FP32; one workgroup of 1024 threads.  Every sum is a fixed-order butterfly
+// within each wave followed by the 16 wave sums added in wave order, eight dot
+// products per barrier.  P x = 0 gives 0 (the next pass then has F = 0 and
+// stops).  In place (out == xf, or scratch == xd) is allowed: each thread
+// reads and writes only its own rows.
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __restrict__ Q,
                                                   const float* xf, const double* xd, float* out,
-                                                  double* __restrict__ scratch,
+                                                  double* scratch,
                                                   const Ctrl* __restrict__ ctrl) {
     if (ctrl && ctrl->done) return;
-    __shared__ double red[1024];
-    __shared__ double c[kMaxM];
-    const int t = threadIdx.x, nt = blockDim.x;
+    constexpr int NW = 16;
+    __shared__ double wpart[8][NW];
+    __shared__ double c[kMaxM + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     auto xin = [&](int r) { return xd ? xd[r] : (double)xf[r]; };
-    auto block_sum = [&](double v) -> double {
-        red[t] = v;
-        __syncthreads();
-        for (int h = nt / 2; h > 0; h >>= 1) {
-            if (t < h) red[t] += red[t + h];
-            __syncthreads();
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        const int nj = (k - j0 < 8) ? k - j0 : 8;
+        double d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = 0.0;
+        for (int r = t; r < p; r += 1024) {
+            const double xr = xin(r);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (u < nj) d[u] += Q[(size_t)(j0 + u) * p + r] * xr;
         }
-        const double r0 = red[0];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double v = wave_sum_d(d[u]);
+            if (lane == 0) wpart[u][w] = v;
+        }
         __syncthreads();
-        return r0;
-    };
-    for (int j = 0; j < k; ++j) {
-        double sj = 0.0;
-        for (int r = t; r < p; r += nt) sj += Q[(size_t)j * p + r] * xin(r);
-        const double cj = block_sum(sj);
-        if (t == 0) c[j] = cj;
+        if (t < nj) {
+            double v = 0.0;
+            for (int i = 0; i < NW; ++i) v += wpart[t][i];
+            c[j0 + t] = v;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     double s2 = 0.0;
-    for (int r = t; r < p; r += nt) {
+    for (int r = t; r < p; r += 1024) {
         double y = xin(r);
         for (int j = 0; j < k; ++j) y -= Q[(size_t)j * p + r] * c[j];
         scratch[r] = y;
         s2 += y * y;
     }
-    const double nrm2 = block_sum(s2);
+    s2 = wave_sum_d(s2);
+    if (lane == 0) wpart[0][w] = s2;
+    __syncthreads();
+    if (t == 0) {
+        double v = 0.0;
+        for (int i = 0; i < NW; ++i) v += wpart[0][i];
+        c[kMaxM] = v;
+    }
+    __syncthreads();
+    const double nrm2 = c[kMaxM];
     const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-    for (int r = t; r < p; r += nt) out[r] = (float)(scratch[r] * inv);
+    for (int r = t; r < p; r += 1024) out[r] = (float)(scratch[r] * inv);
 }
 
 hipError_t launch_deflate(int p, int k, const double* Q, const float* xf, const double* xd,
