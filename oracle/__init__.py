@@ -16,6 +16,9 @@ import threading
 import numpy as np
 
 SL1, SL0, BL1, BL0 = 0, 1, 2, 3
+# block L1 read from its original form (objective sum_j ||s_j||, direction
+# mu_j A s_j / ||s_j||); see orc_bl1x_direction
+BL1X = 4
 OK, MAXITER, DEGENERATE = 0, 1, 2
 EINVAL, ENOMEM, ENONFINITE = -1, -3, -5
 
@@ -49,6 +52,8 @@ def lib():
             L.orc_polar.argtypes = [P, i64, i32, P, P, P]
             L.orc_pass.argtypes = [P, i64, i64, i64, i32, i32, d, P, P, P, P, P, P, P, P]
             L.orc_retract.argtypes = [i64, i32, P, P, P, P, P]
+            L.orc_bl1x_direction.argtypes = [i64, i32, P, P]
+            L.orc_bl1x_direction.restype = d
             L.orc_project.argtypes = [i64, i32, P, P]
             L.orc_init.argtypes = [P, i64, i64, i64, i32, P, P]
             L.orc_solve.argtypes = [P, i64, i64, i64, i32, i32, d, P, P, P, d, i32, P, P, P, P, P]
@@ -149,6 +154,10 @@ def step(A, form: int, X, gamma: float, mu=None, mask=None):
                         _ptr(Y), _ptr(S), _ptr(G), _ptr(f), _ptr(nnz))
     if rc:
         raise OracleError(rc, "orc_pass")
+    if form == BL1X:
+        # objective sum_j ||s_j|| and direction mu_j A s_j / ||s_j||
+        F = float(lib().orc_bl1x_direction(p, m, _ptr(f), _ptr(G)))
+        return dict(Y=Y, S=S, G=G, f=f, nnz=nnz, F=F)
     return dict(Y=Y, S=S, G=G, f=f, nnz=nnz, F=float(f.sum()))
 
 

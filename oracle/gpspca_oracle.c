@@ -1,7 +1,8 @@
 /*
  * FP64 reference ("oracle") of the generalized power method for sparse PCA
  * (GP-SPCA), all four formulations of Table 1 of the paper: single-unit L1
- * (SL1), single-unit L0 (SL0), block L1 (BL1) and block L0 (BL0).
+ * (SL1), single-unit L0 (SL0), block L1 (BL1) and block L0 (BL0), plus the
+ * other reading of the block-L1 row (BL1X, below).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is compiled into its own shared
  * library and is used by the tests, the smoke check and the CPU-baseline leg
@@ -27,6 +28,12 @@
  * notes):
  *  - the block-L1 reformulation is read with the bracket squared, so that
  *    m = 1, mu = 1 reduces to the single-unit L1 row of Table 1;
+ *  - BL1X is the block-L1 row read from its original form instead: for fixed
+ *    X the maximum over unit-norm z_j of mu_j x_j^T A z_j - gamma ||z_j||_1 is
+ *    ||s_j|| (s_ij the soft-thresholded correlation), so the objective is
+ *    F = sum_j ||s_j|| and its gradient in x_j is mu_j A s_j / ||s_j||: the
+ *    pass of BL1 with column j of G divided by ||s_j||, and F summed from the
+ *    square roots of the per-component terms;
  *  - the block-L0 row is read with x_j for x;
  *  - the Stiefel manifold is read in R^{p x m};
  *  - gamma_j = gamma for every component;
@@ -52,6 +59,7 @@
 #define ORC_SL0 1
 #define ORC_BL1 2
 #define ORC_BL0 3
+#define ORC_BL1X 4
 
 #define ORC_OK 0
 #define ORC_MAXITER 1
@@ -63,7 +71,7 @@
 #define ORC_CHUNK 1024
 
 static int is_l0(int form) { return form == ORC_SL0 || form == ORC_BL0; }
-static int is_block(int form) { return form == ORC_BL1 || form == ORC_BL0; }
+static int is_block(int form) { return form == ORC_BL1 || form == ORC_BL0 || form == ORC_BL1X; }
 
 int orc_num_threads(void) {
 #ifdef _OPENMP
@@ -266,6 +274,23 @@ int orc_pass(const double* A, int64_t p, int64_t n, int64_t lda, int form, int m
 }
 
 /*
+ * BL1X (original form of the block-L1 row): objective and ascent direction
+ * from the pass's per-component terms f_j = ||s_j||^2.  Returns
+ * F = sum_j sqrt(f_j) and divides column j of G (p x m) by sqrt(f_j) where
+ * f_j > 0 (an empty column stays 0: a dead component).
+ */
+double orc_bl1x_direction(int64_t p, int m, const double* f, double* G) {
+    double F = 0.0;
+    for (int j = 0; j < m; ++j) {
+        if (!(f[j] > 0.0)) continue;
+        const double nr = sqrt(f[j]);
+        F += nr;
+        for (int64_t r = 0; r < p; ++r) G[(int64_t)j * p + r] /= nr;
+    }
+    return F;
+}
+
+/*
  * Retraction of the gradient direction G onto the feasible set.
  *  m = 1 (single-unit): x = g / ||g||.
  *  block: X = polar(G) when every component is live.  With dead components
@@ -388,7 +413,7 @@ int orc_solve(const double* A, int64_t p, int64_t n, int64_t lda, int form, int 
               double* X, double* Z, unsigned char* support, double* trace, int* n_iter) {
     if (!A || !X || !trace || !n_iter) return ORC_EINVAL;
     if (p < 1 || n < 1 || lda < p) return ORC_EINVAL;
-    if (form < 0 || form > 3) return ORC_EINVAL;
+    if (form < 0 || form > 4) return ORC_EINVAL;
     if (!is_block(form) && m != 1) return ORC_EINVAL;
     if (m < 1 || m > p) return ORC_EINVAL;
     if (!(gamma >= 0.0) || !isfinite(gamma)) return ORC_EINVAL;
@@ -421,7 +446,8 @@ int orc_solve(const double* A, int64_t p, int64_t n, int64_t lda, int form, int 
         rc = orc_pass(A, p, n, lda, form, m, gamma, muv, Xk, mask, NULL, S, G, f, nnz);
         if (rc != ORC_OK) goto done;
         double F = 0.0;
-        for (int j = 0; j < m; ++j) F += f[j];
+        if (form == ORC_BL1X) F = orc_bl1x_direction(p, m, f, G);
+        else for (int j = 0; j < m; ++j) F += f[j];
         trace[k] = F;
         if (F == 0.0) { degenerate_seen = 1; break; }
         if (k >= 1 && fabs(F - trace[k - 1]) < tol * fabs(trace[k - 1])) { converged = 1; break; }
