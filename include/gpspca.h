@@ -50,6 +50,14 @@ extern "C" {
 #define GPSPCA_SL0 1
 #define GPSPCA_BL1 2
 #define GPSPCA_BL0 3
+/* Block L1 read from its original form (Table 1, left column): for fixed X the
+ * maximum over unit-norm z_j of mu_j x_j^T A z_j - gamma ||z_j||_1 is ||s_j||,
+ * so F(X) = sum_j ||s_j|| = sum_j sqrt(sum_i [mu_j |a_i^T x_j| - gamma]_+^2) and
+ * the ascent direction is column j of A S N divided by ||s_j||.  The pass is
+ * BL1's; the objective and the retraction X = polar(A S N Diag(1/||s_j||))
+ * differ for m > 1 (for m = 1 the iterates are SL1's and F is the square root
+ * of SL1's).  Accepted by gpspca_workspace_bytes and gpspca_solve only. */
+#define GPSPCA_BL1X 4
 
 /* Storage types of A.  The paper stores A in full precision; 16- and 8-bit
  * storage is an extension that moves 2 or 1 bytes per element per pass while
@@ -93,7 +101,8 @@ size_t gpspca_workspace_bytes(const gpspca_matrix* A, int form, int m, int max_i
  * Solve one GP-SPCA problem by the power iteration (Section 2, Table 1).
  *
  *  A          data matrix (F32, BF16 or F8E4M3 storage; FP32 arithmetic).
- *  form       GPSPCA_SL1 | SL0 (then m must be 1) | BL1 | BL0 (1 <= m <= min(p, 64)).
+ *  form       GPSPCA_SL1 | SL0 (then m must be 1) | BL1 | BL0 | BL1X
+ *             (1 <= m <= min(p, 64)).
  *  gamma      absolute sparsity weight >= 0.
  *  mu         host, m weights > 0 for block forms; NULL = all ones; ignored for SL*.
  *  X0         device p x m starting point (leading dim p), or NULL for the default

@@ -5,7 +5,7 @@ this package is a thin binding over it.  PyTorch is used only for device
 memory and streams.
 """
 from ._lib import (  # noqa: F401
-    SL1, SL0, BL1, BL0, F32, BF16, F8E4M3,
+    SL1, SL0, BL1, BL0, BL1X, F32, BF16, F8E4M3,
     OK, MAXITER, DEGENERATE, EINVAL, EDTYPE, ENOMEM, EDEVICE, ENONFINITE, MAX_M,
     GpspcaError, load, last_error, LIB_PATH, SIGNATURES,
 )

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgpspca.so")
 
 SL1, SL0, BL1, BL0 = 0, 1, 2, 3
+BL1X = 4  # block L1 from its original form (gpspca_solve only)
 F32, BF16, F8E4M3 = 0, 1, 2
 OK, MAXITER, DEGENERATE = 0, 1, 2
 EINVAL, EDTYPE, ENOMEM, EDEVICE, ENONFINITE = -1, -2, -3, -4, -5

@@ -735,7 +735,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
                double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
                float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
                int* status_out, const double* norms_in, int multistart, const double* defl_q,
-               int defl_k) {
+               int defl_k, int exact) {
     int ncu = 0;
     int rc = device_cus(&ncu);
     if (rc) return rc;
@@ -745,6 +745,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
     if (ws_bytes < pl.total) return fail(GPSPCA_ENOMEM, "workspace too small");
     pl.defl_q = defl_q;
     pl.defl_k = defl_q ? defl_k : 0;
+    pl.exact = (exact && !path) ? 1 : 0;
     const Ptrs P = carve(pl, workspace);
     PassParams pp = make_params(A, pl, gamma, mu, gammas);
     pp.nact = &P.ctrl->nact;
@@ -890,6 +891,7 @@ const char* gpspca_last_error(void) { return g_err.c_str(); }
 const char* gpspca_version(void) { return "gpspca-gfx950 0.1"; }
 
 size_t gpspca_workspace_bytes(const gpspca_matrix* A, int form, int m, int max_iter) {
+    if (form == GPSPCA_BL1X) form = GPSPCA_BL1;  // the same passes
     if (check_problem(A, form, m, 0.0, nullptr) != GPSPCA_OK) return 0;
     if (max_iter < 1) {
         fail(GPSPCA_EINVAL, "max_iter must be >= 1");
@@ -904,6 +906,9 @@ int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const do
                  const float* X0, double tol, int max_iter, void* workspace, size_t ws_bytes,
                  void* stream, float* X, float* Z, uint32_t* support, double* obj_trace,
                  int* n_iter) {
+    // BL1X runs BL1's passes with the original form's objective and retraction
+    const int exact = form == GPSPCA_BL1X ? 1 : 0;
+    if (exact) form = GPSPCA_BL1;
     int rc = check_problem(A, form, m, gamma, mu);
     if (rc) return rc;
     rc = check_run(tol, max_iter, X, workspace);
@@ -911,7 +916,7 @@ int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const do
     if (!X0 && m > A->n) return fail(GPSPCA_EINVAL, "default start needs m <= n");
     return solve_core(A, form, m, gamma, mu, nullptr, 0, nullptr, X0, tol, max_iter, workspace,
                       ws_bytes, static_cast<hipStream_t>(stream), X, Z, support, obj_trace,
-                      n_iter, nullptr, nullptr);
+                      n_iter, nullptr, nullptr, 0, nullptr, 0, exact);
 }
 
 int gpspca_refine(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,

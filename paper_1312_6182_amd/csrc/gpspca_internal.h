@@ -103,6 +103,7 @@ struct Plan {
     int use_mv;            // block correlation on the matrix cores, A staged through registers
     int path;              // gamma path: independent single-unit columns (normalize, per-column stop)
     const double* defl_q;  // deflated component: basis of the earlier components (p x defl_k, FP64)
+    int exact;             // block L1 from its original form: F = sum_j ||s_j||, G column j / ||s_j||
     int defl_k;            // ... and their count (0: no deflation)
     // workspace offsets (bytes)
     size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
@@ -224,6 +225,6 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
                double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
                float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
                int* status_out, const double* norms_in, int multistart = 0,
-               const double* defl_q = nullptr, int defl_k = 0);
+               const double* defl_q = nullptr, int defl_k = 0, int exact = 0);
 
 }  // namespace gpspca

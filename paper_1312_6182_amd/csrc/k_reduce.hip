@@ -606,6 +606,7 @@ struct StopShared {
     int nj[kMaxM];
     int live[kMaxM];
     int dead[kMaxM];
+    double dsc[kMaxM];  // original-form block L1: 1/||s_j|| (0 for a dead component)
     int nlive, ndead, rankdef, stop;
 };
 
@@ -732,7 +733,7 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
                        const int* __restrict__ nnzpart, double* __restrict__ vprev,
                        double* __restrict__ trace, double* __restrict__ coef,
                        double* __restrict__ fcomp, const double* __restrict__ gram, int ngram,
-                       Ctrl* __restrict__ ctrl) {
+                       int exact, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ StopShared ss;
     __shared__ double red[1024];
@@ -781,7 +782,9 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
         double F = 0.0;
         int nl = 0, nd = 0;
         for (int j = 0; j < m; ++j) {
-            F += ss.fj[j];
+            // original form of block L1: F = sum_j ||s_j||
+            F += exact ? sqrt(ss.fj[j]) : ss.fj[j];
+            ss.dsc[j] = (ss.fj[j] > 0.0) ? 1.0 / sqrt(ss.fj[j]) : 0.0;
             fcomp[j] = ss.fj[j];
             reinterpret_cast<int64_t*>(fcomp + m)[j] = ss.nj[j];
             if (ss.nj[j] > 0) ss.live[nl++] = j;
@@ -839,7 +842,22 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
         }
         __syncthreads();
     } else {
+        if (exact) {
+            // direction G D, D = Diag(1/||s_j||): G^T G <- D G^T G D, G^T X <- D G^T X
+            for (int e = t; e < mm; e += nt) {
+                const int a = e / m, b = e % m;
+                coef[2 * mm + e] *= ss.dsc[a] * ss.dsc[b];
+                coef[3 * mm + e] *= ss.dsc[a];
+            }
+            __syncthreads();
+        }
         block_coefficients(m, coef, vprev, ss, A0, A1, A2, ctrl);
+        if (exact) {
+            // X_{k+1} = (G D) Omega + X_k Psi: row l of Omega takes 1/||s_l||
+            __syncthreads();
+            for (int e = t; e < mm; e += nt) coef[e] *= ss.dsc[e / m];
+            __syncthreads();
+        }
         // finiteness of the coefficients (every thread checks its share)
         int bad = 0;
         for (int e = t; e < 2 * mm; e += nt) bad |= isfinite(coef[e]) ? 0 : 1;
@@ -871,7 +889,7 @@ hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
-                       nnzpart, vprev, trace, coef, fcomp, gram, pl.gram_blocks, ctrl);
+                       nnzpart, vprev, trace, coef, fcomp, gram, pl.gram_blocks, pl.exact, ctrl);
     return hipGetLastError();
 }
 
