@@ -385,32 +385,45 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const float* __restrict__ g
     double g[MB];
 #pragma unroll
     for (int j = 0; j < MB; ++j) g[j] = 0.0;
+    // component offsets: components >= m re-read component m - 1 (a valid
+    // address) and are dropped by a select, so the loads stay unconditional and
+    // are issued together instead of one branch and one wait per component
+    size_t joff[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) joff[j] = (size_t)(j < m ? j : m - 1) * ldx + r;
     if (r < p && nlist <= 1024) {
         int e = sl;
         for (; e + 12 < nlist; e += 16) {
             float v[4][MB];
 #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float* src = gpart + (size_t)plist[e + 4 * u] * stride;
+#pragma unroll
+                for (int j = 0; j < MB; ++j) v[u][j] = src[joff[j]];
+            }
+#pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int j = 0; j < MB; ++j)
-                    v[u][j] = (j < m) ? gpart[(size_t)plist[e + 4 * u] * stride + (size_t)j * ldx + r] : 0.f;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int j = 0; j < MB; ++j) g[j] += (double)v[u][j];
+                for (int j = 0; j < MB; ++j) g[j] += (j < m) ? (double)v[u][j] : 0.0;
         }
         for (; e < nlist; e += 4) {
+            float v[MB];
+            const float* src = gpart + (size_t)plist[e] * stride;
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
-                if (j < m) g[j] += (double)gpart[(size_t)plist[e] * stride + (size_t)j * ldx + r];
+            for (int j = 0; j < MB; ++j) v[j] = src[joff[j]];
+#pragma unroll
+            for (int j = 0; j < MB; ++j) g[j] += (j < m) ? (double)v[j] : 0.0;
         }
     } else if (r < p) {
         // more than 1024 partials: walk the flags directly
         for (int c = sl; c < npart; c += 4) {
             if (touched && !touched[c]) continue;
+            float v[MB];
+            const float* src = gpart + (size_t)c * stride;
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
-                if (j < m) g[j] += (double)gpart[(size_t)c * stride + (size_t)j * ldx + r];
+            for (int j = 0; j < MB; ++j) v[j] = src[joff[j]];
+#pragma unroll
+            for (int j = 0; j < MB; ++j) g[j] += (j < m) ? (double)v[j] : 0.0;
         }
     }
 #pragma unroll
@@ -1123,7 +1136,15 @@ __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
     const int r = blockIdx.x * 256 + t;
     if (r >= p) return;
     double acc = 0.0;
-    for (int l = 0; l < m; ++l) acc += g64[(size_t)l * p + r] * om[l];
+    int l = 0;
+    for (; l + 4 <= m; l += 4) {  // in order of l, 4 loads issued together
+        double gv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gv[u] = g64[(size_t)(l + u) * p + r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += gv[u] * om[l + u];
+    }
+    for (; l < m; ++l) acc += g64[(size_t)l * p + r] * om[l];
     if (dead)
         for (int l = 0; l < m; ++l) acc += (double)Xk[(size_t)l * ldx + r] * ps[l];
     Xn[(size_t)j * ldx + r] = (float)acc;
@@ -1170,11 +1191,18 @@ __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __
         double d[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) d[u] = 0.0;
+        // basis vectors past the last re-read vector j0 + nj - 1 (a valid
+        // address) and are dropped by a select: the 8 loads are issued together
+        size_t qo[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) qo[u] = (size_t)(j0 + (u < nj ? u : nj - 1)) * p;
         for (int r = t; r < p; r += 1024) {
             const double xr = xin(r);
+            double q[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (u < nj) d[u] += Q[(size_t)(j0 + u) * p + r] * xr;
+            for (int u = 0; u < 8; ++u) q[u] = Q[qo[u] + r];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) d[u] += (u < nj) ? q[u] * xr : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -1192,7 +1220,15 @@ __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __
     double s2 = 0.0;
     for (int r = t; r < p; r += 1024) {
         double y = xin(r);
-        for (int j = 0; j < k; ++j) y -= Q[(size_t)j * p + r] * c[j];
+        int j = 0;
+        for (; j + 4 <= k; j += 4) {
+            double q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = Q[(size_t)(j + u) * p + r];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) y -= q[u] * c[j + u];
+        }
+        for (; j < k; ++j) y -= Q[(size_t)j * p + r] * c[j];
         scratch[r] = y;
         s2 += y * y;
     }
