@@ -164,7 +164,7 @@ def gamma_path_leg(G, torch, W, Ad, A32, cmax, passes, K=32):
     return res
 
 
-def serving_leg(W, count, full, slots=8, arena_gb=64, seed=1000):
+def serving_leg(W, count, full, slots=12, arena_gb=64, seed=1000):
     """The serving mix through the solve server: every request a default-start
     solve (tol 1e-4, up to 1000 passes) on a planted-spike matrix (k =
     max(10, n/100), beta = 5 sqrt(n)).  A closed-loop run (all requests at once)

@@ -579,6 +579,18 @@ __device__ __forceinline__ typename QuadRaw<ST>::T load_quad_raw(const void* col
         return *reinterpret_cast<const T*>(static_cast<const uint8_t*>(colv) + 4 * q);
 }
 
+// Raw full quad for the support-restricted back-projection: FP32 columns
+// whose leading dimension is not a multiple of 4 are read element-wise.
+template <int ST, bool VEC>
+__device__ __forceinline__ typename QuadRaw<ST>::T load_raw_sp(const void* colv, int q) {
+    if constexpr (ST == kStF32 && !VEC) {
+        const float* c = static_cast<const float*>(colv) + 4 * q;
+        return f4{c[0], c[1], c[2], c[3]};
+    } else {
+        return load_quad_raw<ST>(colv, q);
+    }
+}
+
 template <int ST>
 __device__ __forceinline__ f4 decode_quad(typename QuadRaw<ST>::T w) {
     if constexpr (ST == kStF32) {
@@ -789,6 +801,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int j = 0; j < M; ++j) g[k][j] = zero4();
     bool any = false;
+    // mu of the group's components, 0 past the group (those weights vanish)
+    float mw[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) mw[j] = (j < mg) ? pp.muf[j0 + j] : 0.f;
+    // this thread's quads (the same in every column): full ones, the ragged
+    // tail quad of rows 4 nqf .. p - 1, or none
+    using RawT = typename QuadRaw<ST>::T;
+    const bool ragged = (p & 3) != 0;
+    int qa[KQ2];
+    bool full[KQ2], tq[KQ2];
+#pragma unroll
+    for (int k = 0; k < KQ2; ++k) {
+        const int q = qbase + t + 256 * k;
+        qa[k] = (q < nqf) ? q : (nqf > 0 ? nqf - 1 : 0);
+        full[k] = q < nqf;
+        tq[k] = ragged && q == nqf;
+    }
+    int trow[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) trow[x] = (4 * nqf + x < p) ? 4 * nqf + x : p - 1;
 
     for (int64_t base = cb; base < ce; base += 256) {
         const int64_t i = base + t;
@@ -804,6 +836,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int e = 0; e < total; e += U) {
             f4 a[U][KQ2];
             float w[U][M];
+            // Every load below is unconditional and only fills registers
+            // (components past the group re-read its last one with weight 0;
+            // quads past the last full one re-read it and are replaced by the
+            // ragged rows or zeros at decoding), so the loads of the U columns
+            // are issued together instead of each behind its own branch and wait.
+            RawT ra[U][KQ2];
+            uint32_t rt[U][4];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int li = (e + u < total) ? list[e + u] : list[e];
@@ -812,17 +851,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 const float sc = (ST == kStF32) ? 1.0f : column_scale(pp, col);
 #pragma unroll
                 for (int j = 0; j < M; ++j)
-                    w[u][j] = (j < mg) ? pp.muf[j0 + j] * S[col * m + j0 + j] * sc : 0.f;
+                    w[u][j] = mw[j] * S[col * m + j0 + (j < mg ? j : mg - 1)] * sc;
+                if (nqf > 0) {
 #pragma unroll
-                for (int k = 0; k < KQ2; ++k) {
-                    const int q = qbase + t + 256 * k;
-                    if constexpr (ST == kStF32)
-                        a[u][k] = (q < nq) ? load_quad<VEC>(static_cast<const float*>(colv), q, nqf, p)
-                                           : zero4();
-                    else
-                        a[u][k] = (q < nq) ? load_quad_st<ST>(colv, q, nqf, p) : zero4();
+                    for (int k = 0; k < KQ2; ++k) ra[u][k] = load_raw_sp<ST, VEC>(colv, qa[k]);
+                }
+                if (ragged) {
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) rt[u][x] = load_elem_raw<ST>(colv, trow[x]);
                 }
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < KQ2; ++k) {
+                    f4 v = zero4();
+                    if (nqf > 0) v = decode_quad<ST>(ra[u][k]);
+                    if (ragged) {
+                        f4 rag;
+#pragma unroll
+                        for (int x = 0; x < 4; ++x)
+                            rag[x] = (4 * nqf + x < p) ? decode_elem<ST>(rt[u][x]) : 0.f;
+                        v = tq[k] ? rag : v;
+                    }
+                    a[u][k] = (full[k] || tq[k]) ? v : zero4();
+                }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (e + u < total) {
