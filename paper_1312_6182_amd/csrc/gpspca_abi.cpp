@@ -294,11 +294,15 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         pl->bp_rb = (int)cdiv(nq, 256 * pl->bp_kq);
         // column ranges of >= 1024 columns, about 4 workgroups per CU in all; a
         // matrix too small to give every CU a workgroup that way takes ranges of
-        // >= 128 columns instead (each workgroup walks its range's active
-        // columns in dependent batches, so long ranges are latency-bound)
+        // >= 128 columns instead, and a smaller one still ranges of >= 32 up to
+        // 128 ranges (each workgroup walks its range's active columns in
+        // dependent batches, so long ranges are latency-bound; 128 partials
+        // still take the fused reduction)
         const int64_t want = std::max<int64_t>(1, (4LL * ncu) / pl->bp_rb);
         int64_t cr = std::min<int64_t>(cdiv(A->n, 1024), want);
         if (cr * pl->bp_rb < ncu) cr = std::min<int64_t>(cdiv(A->n, 128), want);
+        if (cr * pl->bp_rb < ncu)
+            cr = std::min<int64_t>(std::min<int64_t>(cdiv(A->n, 32), want), std::max<int64_t>(cr, 128));
         pl->bp_cr = (int)std::max<int64_t>(1, cr);
         pl->npart = pl->bp_cr;
         pl->bp_thr = backproj_threshold(A, m, pl->vec4, restricted);
