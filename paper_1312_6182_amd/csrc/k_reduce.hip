@@ -611,6 +611,37 @@ __device__ void inv_sqrt_from_eig(const double* a, const double* v, double* out,
     __syncthreads();
 }
 
+// s, c = sum of fp[w], cp[w] over w = sl, sl + step, ... < nwp, in that
+// order.  The loads of 16 terms are issued together (indices past the end
+// re-read the last term and add 0, which leaves the non-negative sums as they
+// were), instead of one dependent load at a time.
+__device__ __forceinline__ void slice_sum(const double* __restrict__ fp,
+                                          const int* __restrict__ cp, int nwp, int sl, int step,
+                                          double* s_out, int* c_out) {
+    constexpr int B = 16;
+    double s = 0.0;
+    int c = 0;
+    for (int w0 = sl; w0 < nwp; w0 += B * step) {
+        double fv[B];
+        int cv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int w = w0 + u * step;
+            const int wc = w < nwp ? w : nwp - 1;
+            fv[u] = fp[wc];
+            cv[u] = cp[wc];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const bool in = w0 + u * step < nwp;
+            s += in ? fv[u] : 0.0;
+            c += in ? cv[u] : 0;
+        }
+    }
+    *s_out = s;
+    *c_out = c;
+}
+
 struct StopShared {
     double rot[kMaxM];
     int prs[kMaxM];
@@ -766,15 +797,9 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
             const int j = j0 + t / tpc, sl = t % tpc;
             double s = 0.0;
             int c = 0;
-            if (j < m && t / tpc < nt / tpc) {
-                const double* fp = fpart + (size_t)j * nwp;
-                const int* cp = nnzpart + (size_t)j * nwp;
-#pragma unroll 8
-                for (int w = sl; w < nwp; w += tpc) {
-                    s += fp[w];
-                    c += cp[w];
-                }
-            }
+            if (j < m && t / tpc < nt / tpc) slice_sum(fpart + (size_t)j * nwp,
+                                                       nnzpart + (size_t)j * nwp, nwp, sl, tpc,
+                                                       &s, &c);
             red[t] = s;
             redi[t] = c;
             __syncthreads();
@@ -911,13 +936,13 @@ hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
 // Per column: objective trace, stopping rule, and the sphere retraction
 // x_j <- g_j / ||g_j||; a column whose rule fired is frozen (Psi_jj = 1), so
 // its x, and with it S, F and Z, stay those of its stopping pass.
-__global__ void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
+__global__ __launch_bounds__(1024) void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
                             const int* __restrict__ nnzpart, double* __restrict__ trace,
                             double* __restrict__ coef, double* __restrict__ fcomp,
                             PathState* __restrict__ ps, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    __shared__ double red[256];
-    __shared__ int redi[256];
+    __shared__ double red[1024];
+    __shared__ int redi[1024];
     __shared__ double fj[kMaxM];
     __shared__ int nj[kMaxM];
     __shared__ int nfrozen;
@@ -925,31 +950,31 @@ __global__ void k_stop_path(int m, int nwp, const double* __restrict__ fpart,
     const int k = ctrl->k;
     const int max_iter = ctrl->max_iter;
     const double tol = ctrl->tol;
-    for (int j = 0; j < m; ++j) {
-        double s = 0.0;
-        int c = 0;
-        const double* fp = fpart + (size_t)j * nwp;
-        const int* cp = nnzpart + (size_t)j * nwp;
-#pragma unroll 8
-        for (int w = t; w < nwp; w += nt) {
-            s += fp[w];
-            c += cp[w];
-        }
-        red[t] = s;
-        redi[t] = c;
-        __syncthreads();
-        for (int h = nt / 2; h > 0; h >>= 1) {
-            if (t < h) {
-                red[t] += red[t + h];
-                redi[t] += redi[t + h];
+    // per-column objective and support size: tpc threads per column, each
+    // summing a strided slice, the slices added in order (fixed order)
+    {
+        const int tpc = nt / m >= 1 ? nt / m : 1;
+        for (int j0 = 0; j0 < m; j0 += nt / tpc) {
+            const int j = j0 + t / tpc, sl = t % tpc;
+            double s = 0.0;
+            int c = 0;
+            if (j < m && t / tpc < nt / tpc)
+                slice_sum(fpart + (size_t)j * nwp, nnzpart + (size_t)j * nwp, nwp, sl, tpc, &s, &c);
+            red[t] = s;
+            redi[t] = c;
+            __syncthreads();
+            if (sl == 0 && j < m && t / tpc < nt / tpc) {
+                double a = 0.0;
+                int b = 0;
+                for (int q = 0; q < tpc; ++q) {
+                    a += red[t + q];
+                    b += redi[t + q];
+                }
+                fj[j] = a;
+                nj[j] = b;
             }
             __syncthreads();
         }
-        if (t == 0) {
-            fj[j] = red[0];
-            nj[j] = redi[0];
-        }
-        __syncthreads();
     }
     if (t == 0) nfrozen = 0;
     for (int e = t; e < 2 * mm; e += nt) coef[e] = 0.0;  // Omega, Psi (the summed Gram is at 2mm)
@@ -1009,7 +1034,7 @@ hipError_t launch_stop_path(const Plan& pl, const double* fpart, const int* nnzp
                             PathState* ps, Ctrl* ctrl, hipStream_t st) {
     hipError_t e = launch_gram_sum(pl, pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stop_path, dim3(1), dim3(256), 0, st, pl.m, pl.nwave_part, fpart,
+    hipLaunchKernelGGL(k_stop_path, dim3(1), dim3(1024), 0, st, pl.m, pl.nwave_part, fpart,
                        nnzpart, trace, coef, fcomp, ps, ctrl);
     return hipGetLastError();
 }
