@@ -38,7 +38,6 @@ namespace {
 
 constexpr int kT = 4;          // column tiles of 16 per chunk
 constexpr int kQS = 8;         // row quads per stage (32 rows)
-constexpr int kAStageBytes = 16 * kT * kQS * 16;  // 8192: 64 columns x 8 quads x 16 B
 
 // LDS slot of (column c, quad q) within an A stage: quads are XOR-swizzled by
 // bits 1..3 of the column, so that the 16 columns read together by an MFMA
