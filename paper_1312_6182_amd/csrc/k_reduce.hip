@@ -589,19 +589,19 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
 __device__ void inv_sqrt_from_eig(const double* a, const double* v, double* out, int msz,
                                   double* lam, int* rankdef) {
     const int t = threadIdx.x, nt = blockDim.x;
-    if (t == 0) {
-        double lmax = 0.0;
-        for (int i = 0; i < msz; ++i) lmax = fmax(lmax, a[i * LDM + i]);
-        const double thr = lmax * ((double)msz * 2.220446049250313e-16) * ((double)msz * 2.220446049250313e-16);
-        int rd = !(lmax > 0.0);
-        for (int i = 0; i < msz; ++i) {
-            const double l = a[i * LDM + i];
-            if (l > thr && l > 0.0) lam[i] = 1.0 / sqrt(l);
-            else { lam[i] = 0.0; rd = 1; }
-        }
-        *rankdef = rd;
+    // every thread finds the largest eigenvalue; thread i inverts the root of
+    // eigenvalue i
+    double lmax = 0.0;
+    for (int i = 0; i < msz; ++i) lmax = fmax(lmax, a[i * LDM + i]);
+    const double thr = lmax * ((double)msz * 2.220446049250313e-16) * ((double)msz * 2.220446049250313e-16);
+    int rd = !(lmax > 0.0);
+    for (int i = t; i < msz; i += nt) {
+        const double l = a[i * LDM + i];
+        if (l > thr && l > 0.0) lam[i] = 1.0 / sqrt(l);
+        else { lam[i] = 0.0; rd = 1; }
     }
-    __syncthreads();
+    rd = __syncthreads_or(rd);
+    if (t == 0) *rankdef = rd;
     for (int e = t; e < msz * msz; e += nt) {
         const int i = e / msz, j = e % msz;
         double s = 0.0;
@@ -609,6 +609,13 @@ __device__ void inv_sqrt_from_eig(const double* a, const double* v, double* out,
         out[i * LDM + j] = s;
     }
     __syncthreads();
+}
+
+// Sum over the 64 lanes of a wave by a fixed butterfly (every lane gets it).
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 // s, c = sum of fp[w], cp[w] over w = sl, sl + step, ... < nwp, in that
@@ -651,6 +658,7 @@ struct StopShared {
     int live[kMaxM];
     int dead[kMaxM];
     double dsc[kMaxM];  // original-form block L1: 1/||s_j|| (0 for a dead component)
+    double fterm[kMaxM];  // component j's term of F
     int nlive, ndead, rankdef, stop;
 };
 
@@ -781,50 +789,54 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
     if (ctrl->done) return;
     __shared__ StopShared ss;
     __shared__ double red[1024];
-    __shared__ int redi[1024];
     extern __shared__ double dyn[];
     double* A0 = dyn;
     double* A1 = dyn + (size_t)m * LDM;
     double* A2 = dyn + (size_t)2 * m * LDM;
     const int t = threadIdx.x, nt = blockDim.x;
     const int k = ctrl->k;
+    // the control fields the stopping rule needs, loaded up front so their
+    // latency overlaps the sums
+    const double last_F = ctrl->last_F, tol = ctrl->tol;
+    const int max_iter = ctrl->max_iter, deg_seen = ctrl->degenerate_seen;
 
-    // per-component objective and support size: tpc threads per component,
-    // each summing a strided slice, slices added in order (fixed order)
+    // per-component objective and support size: tpc (a power of two <= 64)
+    // lanes of one wave per component, each summing a strided slice, the
+    // slices combined by a fixed butterfly (fixed order)
     {
-        const int tpc = nt / m >= 1 ? nt / m : 1;
+        int tpc = 64;
+        while (tpc > 1 && tpc * m > nt) tpc >>= 1;
         for (int j0 = 0; j0 < m; j0 += nt / tpc) {
             const int j = j0 + t / tpc, sl = t % tpc;
             double s = 0.0;
             int c = 0;
-            if (j < m && t / tpc < nt / tpc) slice_sum(fpart + (size_t)j * nwp,
-                                                       nnzpart + (size_t)j * nwp, nwp, sl, tpc,
-                                                       &s, &c);
-            red[t] = s;
-            redi[t] = c;
-            __syncthreads();
-            if (sl == 0 && j < m) {
-                double a = 0.0;
-                int b = 0;
-                for (int q = 0; q < tpc; ++q) {
-                    a += red[t + q];
-                    b += redi[t + q];
-                }
-                ss.fj[j] = a;
-                ss.nj[j] = b;
+            if (j < m) slice_sum(fpart + (size_t)j * nwp, nnzpart + (size_t)j * nwp, nwp, sl, tpc,
+                                 &s, &c);
+            for (int o = tpc / 2; o >= 1; o >>= 1) {
+                s += __shfl_xor(s, o, 64);
+                c += __shfl_xor(c, o, 64);
             }
-            __syncthreads();
+            if (sl == 0 && j < m) {
+                ss.fj[j] = s;
+                ss.nj[j] = c;
+            }
         }
     }
+    __syncthreads();
+    // per-component terms in parallel (original form of block L1: ||s_j||)
+    for (int j = t; j < m; j += nt) {
+        const double fj = ss.fj[j];
+        ss.fterm[j] = exact ? sqrt(fj) : fj;
+        ss.dsc[j] = (exact && fj > 0.0) ? 1.0 / sqrt(fj) : 0.0;
+        fcomp[j] = fj;
+        reinterpret_cast<int64_t*>(fcomp + m)[j] = ss.nj[j];
+    }
+    __syncthreads();
     if (t == 0) {
         double F = 0.0;
         int nl = 0, nd = 0;
         for (int j = 0; j < m; ++j) {
-            // original form of block L1: F = sum_j ||s_j||
-            F += exact ? sqrt(ss.fj[j]) : ss.fj[j];
-            ss.dsc[j] = (ss.fj[j] > 0.0) ? 1.0 / sqrt(ss.fj[j]) : 0.0;
-            fcomp[j] = ss.fj[j];
-            reinterpret_cast<int64_t*>(fcomp + m)[j] = ss.nj[j];
+            F += ss.fterm[j];
             if (ss.nj[j] > 0) ss.live[nl++] = j;
             else ss.dead[nd++] = j;
         }
@@ -832,20 +844,22 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
         ss.ndead = nd;
         trace[k] = F;
         int stop = 0, status = GPSPCA_OK;
+        int degenerate = deg_seen;
         if (!isfinite(F)) {
             stop = 1;
             status = GPSPCA_ENONFINITE;
         } else if (F == 0.0) {
             stop = 1;
+            degenerate = 1;
             ctrl->degenerate_seen = 1;
-        } else if (k >= 1 && fabs(F - ctrl->last_F) < ctrl->tol * fabs(ctrl->last_F)) {
+        } else if (k >= 1 && fabs(F - last_F) < tol * fabs(last_F)) {
             stop = 1;
-        } else if (k + 1 >= ctrl->max_iter) {
+        } else if (k + 1 >= max_iter) {
             stop = 1;
             status = GPSPCA_MAXITER;
         }
         if (stop) {
-            if (status >= 0 && ctrl->degenerate_seen) status = GPSPCA_DEGENERATE;
+            if (status >= 0 && degenerate) status = GPSPCA_DEGENERATE;
             ctrl->status = status;
             ctrl->done = 1;
             ctrl->n_iter = k + 1;
@@ -862,11 +876,13 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
         // per-thread sums, added in thread order
         double sg = 0.0;
         for (int g = t; g < ngram; g += nt) sg += gram[(size_t)3 * g];
-        red[t] = sg;
+        // a fixed butterfly within each wave, then the waves in order
+        sg = wave_sum_d(sg);
+        if ((t & 63) == 0) red[t >> 6] = sg;
         __syncthreads();
         if (t == 0) {
             double g2 = 0.0;
-            for (int u = 0; u < nt; ++u) g2 += red[u];
+            for (int u = 0; u < (nt + 63) / 64; ++u) g2 += red[u];
             coef[2] = g2;
             const double om = 1.0 / sqrt(g2);
             coef[0] = om;
@@ -1195,11 +1211,6 @@ hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, cons
 // products per barrier.  P x = 0 gives 0 (the next pass then has F = 0 and
 // stops).  In place (out == xf, or scratch == xd) is allowed: each thread
 // reads and writes only its own rows.
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __restrict__ Q,
                                                   const float* xf, const double* xd, float* out,
