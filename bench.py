@@ -251,6 +251,28 @@ def time_gpu(G, torch, Ad, form, m, gamma, steps, warmup):
     return r, ms, kms, launches, kname
 
 
+def deflated_leg(G, torch, Ad, gamma, passes, m=5):
+    """m single-unit L1 components by deflation, each run for exactly
+    `passes` passes (tol = 0): passes per second over the whole call, which
+    includes each component's start (deflated column norms, top column) and
+    the deflation projection after every pass."""
+    G.solve_deflated(Ad, 0, m, gamma, tol=0.0, max_iter=2)
+    torch.cuda.synchronize()
+    G.profile_read()
+    G.profile_enable(True)
+    t0 = time.perf_counter()
+    r = G.solve_deflated(Ad, 0, m, gamma, tol=0.0, max_iter=passes)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    G.profile_enable(False)
+    kms, launches, kname = G.profile_read()
+    pp, nn = Ad.shape
+    total = sum(r.n_iter)
+    return {"components": m, "passes": total, "passes_per_s": total / el,
+            "ms_per_component": 1e3 * el / m, "kernel": kname,
+            "kernel_gbps": algorithmic_bytes(kname, pp, nn, 1) / (kms / max(1, launches) * 1e-3) / 1e9}
+
+
 def cpu_baseline(A32, form_id, m, gamma, budget_s):
     import oracle as O
     p, n = A32.shape
@@ -485,6 +507,10 @@ def main():
             rec("c3_BL0_m8", Ad, 3, 8, 0.01 * cmax * cmax)
             rec("c3_BL1_m64", Ad, 2, 64, 0.05 * cmax)
             rec("c3_SL1_m1", Ad, 0, 1, 0.05 * cmax)
+            rec("c3_BL1X_m8", Ad, 4, 8, 0.05 * cmax)
+            extra["c3_SL1_deflated_5"] = deflated_leg(G, torch, Ad, 0.05 * cmax, xs)
+            print(f"[bench] extra c3_SL1_deflated_5: {extra['c3_SL1_deflated_5']}", file=sys.stderr,
+                  flush=True)
         A2, _, _, _ = W.planted_single(5000, 50000, args.seed, k=500)
         c2max = column_norm_max(A2)
         A2d = torch.from_numpy(np.ascontiguousarray(A2.T)).cuda().t()
