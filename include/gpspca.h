@@ -205,7 +205,9 @@ int gpspca_solve_multistart(const gpspca_matrix* A, int form, int m, double gamm
  * obj_trace[k * max_iter ...], n_iter[k] entries valid); n_iter and status
  * (host, m ints).  Returns GPSPCA_OK when every component converged, the
  * largest per-component status otherwise, or a negative error (EDTYPE for
- * 16/8-bit storage).  Synchronizes `stream`.
+ * 16/8-bit storage; EINVAL when A_k is zero, i.e. the rank of A is below
+ * k + 1: components 0 .. k-1 are then already written).  Synchronizes
+ * `stream`.
  */
 size_t gpspca_deflated_workspace_bytes(const gpspca_matrix* A, int m, int max_iter);
 int gpspca_solve_deflated(const gpspca_matrix* A, int form, int m, double gamma, double tol,

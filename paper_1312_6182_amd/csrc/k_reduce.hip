@@ -314,9 +314,20 @@ __global__ __launch_bounds__(256) void k_gram_sum(int nent, int mm, int ngram, i
     const int e = blockIdx.x * epb + el;
     double s = 0.0;
     if (e < nent) {
+        // in order of g; the loads of 8 terms are issued together (indices past
+        // the end re-read the last term and are not added)
         const double* gp = gram + e;
-#pragma unroll 4
-        for (int g = sl; g < ngram; g += S) s += gp[(size_t)g * 3 * mm];
+        for (int g0 = sl; g0 < ngram; g0 += 8 * S) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int g = g0 + u * S;
+                v[u] = gp[(size_t)(g < ngram ? g : ngram - 1) * 3 * mm];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (g0 + u * S < ngram) s += v[u];
+        }
     }
     red[t] = s;
     __syncthreads();
