@@ -506,7 +506,8 @@ hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* tou
 __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                            bool warm = false) {
     const int t = threadIdx.x, nt = blockDim.x;
-    constexpr double kTol = 9.094947017729282e-13;   // 2^-40
+    // |a_pq| > 2^-40 sqrt(|a_pp a_qq|), tested squared (no square root)
+    constexpr double kTol2 = 8.271806125530277e-25;  // 2^-80
     if (!warm) {
         for (int e = t; e < msz * msz; e += nt) {
             const int i = e / msz, j = e % msz;
@@ -527,7 +528,7 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
             const int i = e / msz, j = e % msz;
             if (i < j) {
                 const double apq = a[i * LDM + j];
-                need |= (fabs(apq) > kTol * sqrt(fabs(a[i * LDM + i] * a[j * LDM + j])) &&
+                need |= (apq * apq > kTol2 * fabs(a[i * LDM + i] * a[j * LDM + j]) &&
                          fabs(apq) > 1e-300) ? 1 : 0;
             }
         }
@@ -542,10 +543,10 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                 if (qq < msz) {
                     const double apq = a[pp * LDM + qq];
                     const double app = a[pp * LDM + pp], aqq = a[qq * LDM + qq];
-                    if (fabs(apq) > kTol * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+                    if (apq * apq > kTol2 * fabs(app * aqq) && fabs(apq) > 1e-300) {
                         const double tau = (aqq - app) / (2.0 * apq);
                         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        c = rsqrt(1.0 + tt * tt);
                         s = tt * c;
                     }
                 }
@@ -630,13 +631,13 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 // s, c = sum of fp[w], cp[w] over w = sl, sl + step, ... < nwp, in that
-// order.  The loads of 16 terms are issued together (indices past the end
+// order.  The loads of B terms are issued together (indices past the end
 // re-read the last term and add 0, which leaves the non-negative sums as they
 // were), instead of one dependent load at a time.
+template <int B>
 __device__ __forceinline__ void slice_sum(const double* __restrict__ fp,
                                           const int* __restrict__ cp, int nwp, int sl, int step,
                                           double* s_out, int* c_out) {
-    constexpr int B = 16;
     double s = 0.0;
     int c = 0;
     for (int w0 = sl; w0 < nwp; w0 += B * step) {
@@ -821,7 +822,7 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
             const int j = j0 + t / tpc, sl = t % tpc;
             double s = 0.0;
             int c = 0;
-            if (j < m) slice_sum(fpart + (size_t)j * nwp, nnzpart + (size_t)j * nwp, nwp, sl, tpc,
+            if (j < m) slice_sum<32>(fpart + (size_t)j * nwp, nnzpart + (size_t)j * nwp, nwp, sl, tpc,
                                  &s, &c);
             for (int o = tpc / 2; o >= 1; o >>= 1) {
                 s += __shfl_xor(s, o, 64);
@@ -986,7 +987,7 @@ __global__ __launch_bounds__(1024) void k_stop_path(int m, int nwp, const double
             double s = 0.0;
             int c = 0;
             if (j < m && t / tpc < nt / tpc)
-                slice_sum(fpart + (size_t)j * nwp, nnzpart + (size_t)j * nwp, nwp, sl, tpc, &s, &c);
+                slice_sum<16>(fpart + (size_t)j * nwp, nnzpart + (size_t)j * nwp, nwp, sl, tpc, &s, &c);
             red[t] = s;
             redi[t] = c;
             __syncthreads();
