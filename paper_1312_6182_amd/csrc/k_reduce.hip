@@ -1303,23 +1303,48 @@ hipError_t launch_deflate(int p, int k, const double* Q, const float* xf, const 
 // k_defl_norms: ||P a_i|| = sqrt(||a_i||^2 - sum_j (q_j^T a_i)^2) in FP64 for
 // every column of the FP32 matrix (one wave per column at a time; the column
 // is read k + 1 times, from cache after the first): the default start of a
-// deflated component.
+// deflated component.  Each lane sums its rows lane, lane + 64, ... in order;
+// the loads of 8 such rows are issued together (rows past p re-read row p - 1
+// and add 0), instead of one dependent load per row.
 __global__ __launch_bounds__(256) void k_defl_norms(const float* __restrict__ A, int64_t lda,
                                                     int p, int64_t n, int k,
                                                     const double* __restrict__ Q,
                                                     double* __restrict__ norms) {
+    constexpr int U = 8;
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
     for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += nw) {
         const float* a = A + i * lda;
         double ss = 0.0;
-        for (int r = lane; r < p; r += 64) ss += (double)a[r] * a[r];
+        for (int r0 = lane; r0 < p; r0 += 64 * U) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = r0 + 64 * u;
+                v[u] = a[r < p ? r : p - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) ss += (r0 + 64 * u < p) ? (double)v[u] * v[u] : 0.0;
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
         double dd = 0.0;
         for (int j = 0; j < k; ++j) {
+            const double* q = Q + (size_t)j * p;
             double d = 0.0;
-            for (int r = lane; r < p; r += 64) d += Q[(size_t)j * p + r] * a[r];
+            for (int r0 = lane; r0 < p; r0 += 64 * U) {
+                float v[U];
+                double qv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int r = r0 + 64 * u;
+                    const int rc = r < p ? r : p - 1;
+                    v[u] = a[rc];
+                    qv[u] = q[rc];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) d += (r0 + 64 * u < p) ? qv[u] * v[u] : 0.0;
+            }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
             dd += d * d;
