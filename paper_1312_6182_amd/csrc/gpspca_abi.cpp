@@ -595,7 +595,7 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
     if (pl.defl_k > 0) {
         // deflated component (m = 1): x_{k+1} = P g / ||P g|| straight from the
         // FP64 g, which the normalization of the plain retraction would only scale
-        GPSPCA_HIP(launch_deflate((int)pl.p, pl.defl_k, pl.defl_q, nullptr, P.g64, Xn, P.g64,
+        GPSPCA_HIP(launch_deflate((int)pl.p, pl.defl_k, pl.defl_q, P.g64, Xn, P.g64,
                                   P.ctrl, st));
         if (pl.use_mfma || pl.use_q) GPSPCA_HIP(launch_x_interleave(pl, Xn, P.xil[(k + 1) & 1], st));
     } else {
@@ -1098,7 +1098,7 @@ int gpspca_solve_deflated(const gpspca_matrix* A, int form, int m, double gamma,
                                          A->n, k, Q, W.norms, grid, st));
             GPSPCA_HIP(launch_topm(p1, W.norms, W.cand_v, W.cand_i, W.idx, st));
             GPSPCA_HIP(launch_gather(p1, pp1, W.idx, W.g64, st));
-            GPSPCA_HIP(launch_deflate((int)A->p, k, Q, nullptr, W.g64, x0, scratch, nullptr, st));
+            GPSPCA_HIP(launch_deflate((int)A->p, k, Q, W.g64, x0, scratch, nullptr, st));
             start = x0;
         }
         rc = solve_core(A, form, 1, gamma, nullptr, nullptr, 0, nullptr, start, tol, max_iter,

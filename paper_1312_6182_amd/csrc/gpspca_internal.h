@@ -211,12 +211,15 @@ hipError_t launch_copy_x(const Plan& pl, const float* Xint, float* Xout, hipStre
 inline size_t coef_omega(int m) { return 0; }
 inline size_t coef_psi(int m) { return (size_t)m * m; }
 
-// ---- host driver (gpspca_abi.cpp), shared with the server (serve.cpp) ----
-hipError_t launch_deflate(int p, int k, const double* Q, const float* xf, const double* xd,
-                          float* out, double* scratch, const Ctrl* ctrl, hipStream_t st);
+// Deflated single-unit components: x <- P x / ||P x|| with P = I - Q Q^T,
+// the column norms of P A, and Q[:, k] <- x.
+hipError_t launch_deflate(int p, int k, const double* Q, const double* x, float* out,
+                          double* scratch, const Ctrl* ctrl, hipStream_t st);
 hipError_t launch_defl_norms(const float* A, int64_t lda, int p, int64_t n, int k,
                              const double* Q, double* norms, int grid, hipStream_t st);
 hipError_t launch_append_basis(int p, const float* x, double* q, hipStream_t st);
+
+// ---- host driver (gpspca_abi.cpp), shared with the server (serve.cpp) ----
 
 int fail(int code, const std::string& msg);
 int check_problem(const gpspca_matrix* A, int form, int m, double gamma, const double* mu);

@@ -1217,15 +1217,15 @@ hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, cons
 // Deflated single-unit components.  P = I - Q Q^T with Q (p x k, leading dim
 // p, FP64) the earlier components.
 //
-// k_deflate: out = P x / ||P x|| in FP64 from FP32 x (xf) or FP64 x (xd), to
-// FP32; one workgroup of 1024 threads.  Every sum is a fixed-order butterfly
+// k_deflate: out = P x / ||P x|| in FP64 from FP64 x, to FP32; one workgroup
+// of 1024 threads.  Every sum is a fixed-order butterfly
 // within each wave followed by the 16 wave sums added in wave order, eight dot
 // products per barrier.  P x = 0 gives 0 (the next pass then has F = 0 and
-// stops).  In place (out == xf, or scratch == xd) is allowed: each thread
-// reads and writes only its own rows.
+// stops).  scratch == x is allowed: each thread reads and writes only its
+// own rows.
 
 __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __restrict__ Q,
-                                                  const float* xf, const double* xd, float* out,
+                                                  const double* x, float* __restrict__ out,
                                                   double* scratch,
                                                   const Ctrl* __restrict__ ctrl) {
     if (ctrl && ctrl->done) return;
@@ -1233,7 +1233,6 @@ __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __
     __shared__ double wpart[8][NW];
     __shared__ double c[kMaxM + 1];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    auto xin = [&](int r) { return xd ? xd[r] : (double)xf[r]; };
     for (int j0 = 0; j0 < k; j0 += 8) {
         const int nj = (k - j0 < 8) ? k - j0 : 8;
         double d[8];
@@ -1245,7 +1244,7 @@ __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __
 #pragma unroll
         for (int u = 0; u < 8; ++u) qo[u] = (size_t)(j0 + (u < nj ? u : nj - 1)) * p;
         for (int r = t; r < p; r += 1024) {
-            const double xr = xin(r);
+            const double xr = x[r];
             double q[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) q[u] = Q[qo[u] + r];
@@ -1267,7 +1266,7 @@ __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __
     }
     double s2 = 0.0;
     for (int r = t; r < p; r += 1024) {
-        double y = xin(r);
+        double y = x[r];
         int j = 0;
         for (; j + 4 <= k; j += 4) {
             double q[4];
@@ -1294,9 +1293,9 @@ __global__ __launch_bounds__(1024) void k_deflate(int p, int k, const double* __
     for (int r = t; r < p; r += 1024) out[r] = (float)(scratch[r] * inv);
 }
 
-hipError_t launch_deflate(int p, int k, const double* Q, const float* xf, const double* xd,
-                          float* out, double* scratch, const Ctrl* ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(k_deflate, dim3(1), dim3(1024), 0, st, p, k, Q, xf, xd, out, scratch, ctrl);
+hipError_t launch_deflate(int p, int k, const double* Q, const double* x, float* out,
+                          double* scratch, const Ctrl* ctrl, hipStream_t st) {
+    hipLaunchKernelGGL(k_deflate, dim3(1), dim3(1024), 0, st, p, k, Q, x, out, scratch, ctrl);
     return hipGetLastError();
 }
 
