@@ -78,30 +78,44 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
     if (ctrl->done) return;
     const int y = blockIdx.y;
     const int c0 = (int)((int64_t)npart * y / nsplit), c1 = (int)((int64_t)npart * (y + 1) / nsplit);
-    // this split's flags, staged in LDS once instead of loaded per step
-    __shared__ int tf[1024];
+    // this split's touched partials as an ascending list in LDS, built once
+    // (a partial that no workgroup wrote is neither read nor added)
+    __shared__ int plist[1024];
+    __shared__ int wcnt[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const bool staged = touched && (c1 - c0) <= 1024;
+    int nlist = 0;
     if (staged) {
-        for (int i = threadIdx.x; i < c1 - c0; i += 256) tf[i] = touched[c0 + i];
-        __syncthreads();
+        for (int b = 0; b < c1 - c0; b += 256) {
+            const int i = b + t;
+            const bool on = i < c1 - c0 && touched[c0 + i] != 0;
+            const uint64_t bal = __ballot(on);
+            if (lane == 0) wcnt[wv] = __popcll(bal);
+            __syncthreads();
+            int before = nlist;
+            for (int w = 0; w < wv; ++w) before += wcnt[w];
+            if (on) plist[before + __popcll(bal & ((1ull << lane) - 1ull))] = c0 + i;
+            nlist += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+            __syncthreads();
+        }
     }
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * 256 + t;
     if (e >= ne) return;
     double s = 0.0;
     int c = c0;
     if (staged) {
-        // in order of c, skipping untouched partials; the loads of 4 partials
-        // are issued together (an untouched one is read but not added)
-        for (; c + 4 <= c1; c += 4) {
-            float v[4];
+        // in list order (ascending c); the loads of 8 partials are issued
+        // together (past the end the last one is re-read and not added)
+        for (int q = 0; q < nlist; q += 8) {
+            float v[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = gpart[(size_t)(c + u) * ne + e];
+            for (int u = 0; u < 8; ++u)
+                v[u] = gpart[(size_t)plist[q + u < nlist ? q + u : nlist - 1] * ne + e];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (tf[c + u - c0]) s += (double)v[u];
+            for (int u = 0; u < 8; ++u)
+                if (q + u < nlist) s += (double)v[u];
         }
-        for (; c < c1; ++c)
-            if (tf[c - c0]) s += (double)gpart[(size_t)c * ne + e];
+        c = c1;
     } else if (!touched) {
         for (; c + 4 <= c1; c += 4) {
             const float v0 = gpart[(size_t)c * ne + e];
@@ -1174,7 +1188,7 @@ __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
                                                const float* __restrict__ Xk,
                                                const double* __restrict__ coef,
                                                float* __restrict__ Xn,
-                                               float* __restrict__ Xil,
+                                               float* __restrict__ Xil, int diag,
                                                const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ double om[kMaxM];
@@ -1189,7 +1203,11 @@ __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
     const int r = blockIdx.x * 256 + t;
     if (r >= p) return;
     double acc = 0.0;
-    int l = 0;
+    int l = diag ? m : 0;  // gamma path: Omega and Psi are diagonal
+    if (diag) {
+        acc = g64[(size_t)j * p + r] * om[j];
+        if (dead) acc += (double)Xk[(size_t)j * ldx + r] * ps[j];
+    }
     for (; l + 4 <= m; l += 4) {  // in order of l, 4 loads issued together
         double gv[4];
 #pragma unroll
@@ -1198,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
         for (int u = 0; u < 4; ++u) acc += gv[u] * om[l + u];
     }
     for (; l < m; ++l) acc += g64[(size_t)l * p + r] * om[l];
-    if (dead)
+    if (dead && !diag)
         for (int l = 0; l < m; ++l) acc += (double)Xk[(size_t)l * ldx + r] * ps[l];
     Xn[(size_t)j * ldx + r] = (float)acc;
     if (Xil)
@@ -1209,7 +1227,7 @@ hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, cons
                         float* Xn, float* Xil_n, const Ctrl* ctrl, hipStream_t st) {
     const int p = (int)pl.p;
     hipLaunchKernelGGL(k_apply, dim3((p + 255) / 256, pl.m), dim3(256), 0, st, pl.m, p, pl.ldx,
-                       g64, Xk, coef, Xn, Xil_n, ctrl);
+                       g64, Xk, coef, Xn, Xil_n, pl.path, ctrl);
     return hipGetLastError();
 }
 
