@@ -33,14 +33,26 @@ def x_to_device(X: np.ndarray):
     return torch.from_numpy(np.ascontiguousarray(X.T)).cuda().t()
 
 
-def chain_depth(p: int) -> int:
-    """Upper bound on the length of the longest FP32 summation chain of one
-    correlation on the GPU (per-lane sequential part + tree levels)."""
-    return 4 * math.ceil(p / 256) + 48
+def chain_depth(p: int) -> float:
+    """lambda sqrt(L) with lambda = 4 and L = ceil(p/4) + 64, an upper bound on
+    the longest chain of FP32 additions in one correlation on the GPU (the
+    matrix-core kernels carry one accumulator through p/4 steps of four
+    products; the other kernels use shorter per-lane chains and a tree).
+
+    This is a probabilistic bound, not a worst-case one: for rounding errors
+    modelled as independent and mean-zero, a sum along a chain of L additions
+    errs by at most lambda sqrt(L) u sum|terms| (u = 2^-24) except with
+    probability about 2 exp(-lambda^2 / 2) (Higham and Mary, SIAM J. Sci.
+    Comput. 41(5), 2019).  The deterministic bound L u sum|terms| is sqrt(L)/4
+    times wider (about 12x at p = 10^4) and would mark far more elements as
+    ties.  Every use multiplies the band by a safety factor of 4 or 8, so the
+    effective lambda is 16 or more."""
+    return 4.0 * math.sqrt(math.ceil(p / 4) + 64)
 
 
 def corr_band(A64: np.ndarray, X64: np.ndarray) -> np.ndarray:
-    """Forward-error bound of the FP32 correlation a_i^T x_j (n x m)."""
+    """Probabilistic error bound of the FP32 correlation a_i^T x_j (n x m):
+    chain_depth(p) u sum_r |A_ri X_rj|."""
     p = A64.shape[0]
     return chain_depth(p) * 2.0 ** -24 * (np.abs(A64).T @ np.abs(X64)) + 1e-30
 
@@ -56,6 +68,25 @@ def margin_band(Y: np.ndarray, eb: np.ndarray, form: int, mu: np.ndarray):
     if is_l0(form):
         return mu[None, :] ** 2 * (2 * np.abs(Y) * eb + eb * eb)
     return mu[None, :] * eb
+
+
+def term_band(A64, X64, S64, form, mu):
+    """FP32 band of each component's objective term f_j (length m): f_j sums
+    t^2 (l1, t = mu|y| - gamma) or q = (mu y)^2 - gamma (l0) over the support,
+    and each summand moves by its margin's band when y does (2 t mu e + (mu e)^2
+    for l1, the margin band itself for l0).  A small f_j that is a difference of
+    large numbers keeps only this absolute accuracy."""
+    m = X64.shape[1]
+    mu = np.ones(m) if mu is None else np.asarray(mu, dtype=np.float64)
+    Y = A64.T @ X64
+    eb = corr_band(A64, X64)
+    on = S64 != 0
+    if is_l0(form):
+        per = margin_band(Y, eb, form, mu)
+    else:
+        t = np.abs(S64)
+        per = 2.0 * t * mu[None, :] * eb + (mu[None, :] * eb) ** 2
+    return (per * on).sum(axis=0)
 
 
 def trajectory(A64, form, m, gamma, mu, X0, iters):

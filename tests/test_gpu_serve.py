@@ -69,6 +69,10 @@ def test_mixed_requests_equal_solo_solves(gpu):
     overlapped = sum(1 for a in res for b in res
                      if a is not b and a.t_admit < b.t_done and b.t_admit < a.t_done)
     print(f"\n[serve] {len(reqs)} requests, {overlapped} overlapping pairs, stats {st}", flush=True)
+    # continuous batching: requests admitted while others were on the device
+    assert overlapped > 0
+    assert sum(1 for r in res[1:] if r.t_admit > min(x.t_admit for x in res)
+               and any(o.t_admit < r.t_admit < o.t_done for o in res if o is not r)) > 0
     assert any(form < 2 and m > 1 for (_, form, m, _, _) in reqs)
     for (i, form, m, g, mu), r in zip(reqs, res):
         solo = _alone(gpu, mats[i], shapes[i][2], form, m, g, mu, 1e-4, 200)
