@@ -24,13 +24,18 @@ EINVAL, ENOMEM, ENONFINITE = -1, -3, -5
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gpspca_oracle.c")
-_LIB = os.path.join(_HERE, "libgpspca_oracle.so")
+# GPSPCA_ORACLE_LIB names a separately built copy (the sanitizer test's
+# instrumented build); it is used as given and never rebuilt here.
+_LIB_ENV = os.environ.get("GPSPCA_ORACLE_LIB")
+_LIB = _LIB_ENV or os.path.join(_HERE, "libgpspca_oracle.so")
 _lock = threading.Lock()
 _lib = None
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (IEEE double, no fast-math, OpenMP)."""
+    if _LIB_ENV:
+        return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",

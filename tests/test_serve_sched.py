@@ -9,7 +9,9 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LIB = os.path.join(ROOT, "paper_1312_6182_amd", "libgpspca_sched.so")
+# GPSPCA_SCHED_LIB: a separately built copy (the sanitizer test's instrumented build)
+LIB = os.environ.get("GPSPCA_SCHED_LIB") or os.path.join(ROOT, "paper_1312_6182_amd",
+                                                         "libgpspca_sched.so")
 
 U64, SZ, I, P = ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p
 MAXU = (1 << 64) - 1
