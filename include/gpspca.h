@@ -129,6 +129,32 @@ int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const do
                  void* workspace, size_t ws_bytes, void* stream,
                  float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter);
 
+/* Size of the library's own device scratch for gpspca_solve_noalloc (bytes). */
+#define GPSPCA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * gpspca_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, and harnesses that forbid hipMalloc.  The
+ * iteration, arguments, outputs and statuses are gpspca_solve's; in place of a
+ * caller workspace the call uses a scratch array that the library holds in
+ * device memory, GPSPCA_NOALLOC_SCRATCH_BYTES per GPU (each GPU the library
+ * runs on keeps its own copy until the process ends).  The call allocates
+ * nothing: no hipMalloc, hipFree, pinned host memory, events or graphs (its
+ * passes are enqueued one by one).
+ *  - A problem whose scratch (its gpspca_workspace_bytes for the default
+ *    kernel configuration) exceeds GPSPCA_NOALLOC_SCRATCH_BYTES is rejected with
+ *    GPSPCA_ENOMEM before any device work.
+ *  - Every call on one GPU uses that GPU's one scratch array, and each call
+ *    initializes what it reads: calls that overlap on one GPU (other host
+ *    threads, or other streams of this call's device) race and must be
+ *    serialized by the caller.
+ * Synchronizes `stream` before returning.
+ */
+int gpspca_solve_noalloc(const gpspca_matrix* A, int form, int m, double gamma,
+                         const double* mu, const float* X0, double tol, int max_iter,
+                         void* stream, float* X, float* Z, uint32_t* support,
+                         double* obj_trace, int* n_iter);
+
 /*
  * One pass of the iteration at a given feasible point X (device p x m, leading
  * dim p, used as given: it is not re-projected).  For step-level checks.

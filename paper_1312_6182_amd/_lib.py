@@ -18,6 +18,7 @@ F32, BF16, F8E4M3 = 0, 1, 2
 OK, MAXITER, DEGENERATE = 0, 1, 2
 EINVAL, EDTYPE, ENOMEM, EDEVICE, ENONFINITE = -1, -2, -3, -4, -5
 MAX_M = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Matrix(ctypes.Structure):
@@ -47,6 +48,7 @@ _MP = ctypes.POINTER(Matrix)
 SIGNATURES = {
     "gpspca_workspace_bytes": (_SZ, [_MP, _I, _I, _I]),
     "gpspca_solve": (_I, [_MP, _I, _I, _D, _P, _P, _D, _I, _P, _SZ, _P, _P, _P, _P, _P, _P]),
+    "gpspca_solve_noalloc": (_I, [_MP, _I, _I, _D, _P, _P, _D, _I, _P, _P, _P, _P, _P, _P]),
     "gpspca_step": (_I, [_MP, _I, _I, _D, _P, _P, _P, _SZ, _P, _P, _P, _P, _P]),
     "gpspca_column_norms": (_I, [_MP, _P, _P]),
     "gpspca_path_workspace_bytes": (_SZ, [_MP, _I, _I]),

@@ -126,6 +126,44 @@ def solve(A: torch.Tensor, form: int, m: int = 1, gamma: float = 0.0,
                        status=rc)
 
 
+def solve_noalloc(A: torch.Tensor, form: int, m: int = 1, gamma: float = 0.0,
+                  mu: Optional[Sequence[float]] = None, X0: Optional[torch.Tensor] = None,
+                  tol: float = 1e-4, max_iter: int = 1000,
+                  col_scale: Optional[torch.Tensor] = None,
+                  stream: Optional[torch.cuda.Stream] = None,
+                  out: Optional[tuple] = None) -> SolveResult:
+    """gpspca_solve_noalloc: the solve with the library's own device scratch (no
+    workspace).  `out` = (X (m, p), Z (m, n), support (m, ceil(n/32)) int32)
+    preallocated output tensors, else they are allocated here."""
+    lib = L.load()
+    M = matrix(A, col_scale)
+    p, n = A.shape
+    dev = A.device
+    nw = (n + 31) // 32
+    if out is None:
+        out = (torch.empty((m, p), dtype=torch.float32, device=dev),
+               torch.empty((m, n), dtype=torch.float32, device=dev),
+               torch.empty((m, nw), dtype=torch.int32, device=dev))
+    Xt, Zt, sup = out
+    if Xt.shape != (m, p) or Zt.shape != (m, n) or sup.shape != (m, nw):
+        raise ValueError("output tensors have the wrong shapes")
+    trace = (ctypes.c_double * max_iter)()
+    nit = ctypes.c_int(0)
+    x0p = None
+    if X0 is not None:
+        X0c = X0.t().contiguous() if X0.dim() == 2 else X0.reshape(1, -1).contiguous()
+        if X0c.shape != (m, p) or X0c.dtype != torch.float32:
+            raise ValueError("X0 must be a float32 (p, m) tensor")
+        x0p = X0c.data_ptr()
+    rc = lib.gpspca_solve_noalloc(ctypes.byref(M), form, m, float(gamma), _mu_array(mu, m), x0p,
+                                  float(tol), int(max_iter), _stream_ptr(stream), Xt.data_ptr(),
+                                  Zt.data_ptr(), sup.data_ptr(), trace, ctypes.byref(nit))
+    L.check(rc, "gpspca_solve_noalloc")
+    k = nit.value
+    return SolveResult(X=Xt.t(), Z=Zt.t(), support=sup, trace=list(trace[:k]), n_iter=k,
+                       status=rc)
+
+
 @dataclass
 class StepResult:
     S: torch.Tensor   # (n, m) thresholded correlations

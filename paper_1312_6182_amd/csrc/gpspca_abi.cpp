@@ -669,18 +669,21 @@ static int capture_pair(const Plan& pl, const PassParams& pp, const Ptrs& P, Pas
 // enqueued at once).  Pairs of passes go through a captured graph when the
 // solve is long enough to repay the capture (and kernel timing is off).
 // Returns the final control block in *fin.
+// noalloc: no graph (instantiation allocates), no launch timing (events), and
+// the control block is read into the caller's stack instead of pinned memory.
 static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int max_iter,
-                      double tol, hipStream_t st, Ctrl* fin) {
+                      double tol, hipStream_t st, Ctrl* fin, bool noalloc = false) {
     TimedLaunches tl;
-    {
+    if (!noalloc) {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         tl.on = g_prof.on;
     }
-    Ctrl* snap = nullptr;
-    int rc = pinned_ctrl(&snap);
+    Ctrl stack_snap;
+    Ctrl* snap = &stack_snap;
+    int rc = noalloc ? GPSPCA_OK : pinned_ctrl(&snap);
     if (rc) return rc;
     PassGraph pg;
-    const bool use_graph = !tl.on && max_iter >= 8 && graphs_enabled();
+    const bool use_graph = !noalloc && !tl.on && max_iter >= 8 && graphs_enabled();
     if (use_graph) {
         rc = capture_pair(pl, pp, P, &pg);
         if (rc) return rc;
@@ -739,7 +742,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
                double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
                float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
                int* status_out, const double* norms_in, int multistart, const double* defl_q,
-               int defl_k, int exact) {
+               int defl_k, int exact, int noalloc) {
     int ncu = 0;
     int rc = device_cus(&ncu);
     if (rc) return rc;
@@ -826,7 +829,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
     }
 
     Ctrl fin;
-    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin);
+    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin, noalloc != 0);
     if (rc) return rc;
     if (fin.status < 0) return fail(fin.status, status_text(fin.status));
     if (fin.n_iter < 1) return fail(GPSPCA_EDEVICE, "solve ended without a pass");
@@ -884,6 +887,32 @@ static int check_path(const gpspca_matrix* A, int form, int K, const double* gam
     return GPSPCA_OK;
 }
 
+// ------------------------------------------------------- allocation-free solve
+// Scratch of gpspca_solve_noalloc, in place of the caller's workspace: one copy
+// per GPU (each device holds its own at its own address until the process
+// ends).  On the host the array's name is only a stand-in for the device
+// symbol; host code uses the device address that hipGetSymbolAddress returns,
+// resolved once per device with that device current, and never the name.
+static __device__ __align__(256) unsigned char scratch[GPSPCA_NOALLOC_SCRATCH_BYTES];
+
+static int scratch_address(void** out) {
+    static std::mutex mu;
+    static void* addr[64] = {nullptr};
+    int dev = 0;
+    GPSPCA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(GPSPCA_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        GPSPCA_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0)
+            return fail(GPSPCA_EDEVICE, "scratch symbol has no aligned device address");
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return GPSPCA_OK;
+}
+
 }  // namespace gpspca
 
 using namespace gpspca;
@@ -921,6 +950,35 @@ int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const do
     return solve_core(A, form, m, gamma, mu, nullptr, 0, nullptr, X0, tol, max_iter, workspace,
                       ws_bytes, static_cast<hipStream_t>(stream), X, Z, support, obj_trace,
                       n_iter, nullptr, nullptr, 0, nullptr, 0, exact);
+}
+
+int gpspca_solve_noalloc(const gpspca_matrix* A, int form, int m, double gamma,
+                         const double* mu, const float* X0, double tol, int max_iter,
+                         void* stream, float* X, float* Z, uint32_t* support,
+                         double* obj_trace, int* n_iter) {
+    const int exact = form == GPSPCA_BL1X ? 1 : 0;
+    if (exact) form = GPSPCA_BL1;
+    int rc = check_problem(A, form, m, gamma, mu);
+    if (rc) return rc;
+    if (!std::isfinite(tol) || tol < 0.0) return fail(GPSPCA_EINVAL, "tol must be finite and >= 0");
+    if (max_iter < 1) return fail(GPSPCA_EINVAL, "max_iter must be >= 1");
+    if (!X) return fail(GPSPCA_EINVAL, "X is NULL");
+    if (!X0 && m > A->n) return fail(GPSPCA_EINVAL, "default start needs m <= n");
+    int ncu = 0;
+    rc = device_cus(&ncu);
+    if (rc) return rc;
+    Plan pl;  // the plan solve_core will make
+    make_plan(A, form, m, max_iter, ncu, &pl);
+    if (pl.total > GPSPCA_NOALLOC_SCRATCH_BYTES)
+        return fail(GPSPCA_ENOMEM, "problem needs " + std::to_string(pl.total) +
+                                       " bytes of scratch, more than GPSPCA_NOALLOC_SCRATCH_BYTES (" +
+                                       std::to_string((size_t)GPSPCA_NOALLOC_SCRATCH_BYTES) + ")");
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    return solve_core(A, form, m, gamma, mu, nullptr, 0, nullptr, X0, tol, max_iter, ws,
+                      GPSPCA_NOALLOC_SCRATCH_BYTES, static_cast<hipStream_t>(stream), X, Z,
+                      support, obj_trace, n_iter, nullptr, nullptr, 0, nullptr, 0, exact, 1);
 }
 
 int gpspca_refine(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,

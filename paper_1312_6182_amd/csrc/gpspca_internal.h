@@ -228,6 +228,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
                double tol, int max_iter, void* workspace, size_t ws_bytes, hipStream_t st,
                float* X, float* Z, uint32_t* support, double* obj_trace, int* n_iter,
                int* status_out, const double* norms_in, int multistart = 0,
-               const double* defl_q = nullptr, int defl_k = 0, int exact = 0);
+               const double* defl_q = nullptr, int defl_k = 0, int exact = 0,
+               int noalloc = 0);
 
 }  // namespace gpspca
