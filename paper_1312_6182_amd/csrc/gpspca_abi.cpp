@@ -520,10 +520,12 @@ struct TimedLaunches {
     }
     hipError_t begin(hipStream_t st) {
         if (!on) return hipSuccess;
+        // timing only: no system-scope fence at the event (the two events of a
+        // pass cost about 12 us with the default flags on 10000 x 100000, m = 8)
         hipEvent_t a, b;
-        hipError_t e = hipEventCreate(&a);
+        hipError_t e = hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
         if (e != hipSuccess) return e;
-        e = hipEventCreate(&b);
+        e = hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
         if (e != hipSuccess) return e;
         ev.emplace_back(a, b);
         return hipEventRecord(a, st);
@@ -585,13 +587,18 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
         GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, touched, P.l1, P.ctrl, st));
         GPSPCA_HIP(launch_gram(pl, P.l1, pl.red_split, Xk, with_x, P.g64, P.gram, P.ctrl, st));
     }
+    // single-unit passes whose x needs no interleaved copy: the stop kernel
+    // writes x_{k+1} = g / ||g|| itself (one launch less per pass)
+    const bool x_in_stop = !pl.path && pl.m == 1 && pl.defl_k == 0 && !(pl.use_mfma || pl.use_q);
     if (pl.path) {
         GPSPCA_HIP(launch_stop_path(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp,
                                     P.pstate, P.ctrl, st));
     } else {
         GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp,
-                               P.coef + 5 * (size_t)pl.m * pl.m, P.ctrl, st));
+                               P.coef + 5 * (size_t)pl.m * pl.m, P.g64, x_in_stop ? Xn : nullptr,
+                               P.ctrl, st));
     }
+    if (x_in_stop) return GPSPCA_OK;
     if (pl.defl_k > 0) {
         // deflated component (m = 1): x_{k+1} = P g / ||P g|| straight from the
         // FP64 g, which the normalization of the plain retraction would only scale
@@ -640,9 +647,17 @@ struct PassGraph {
     }
 };
 
-static bool graphs_enabled() {
+// Graphs are used for small matrices only (at most 256 MB of A), where launch
+// latency is a large share of a pass; GPSPCA_GRAPH=0 / 1 forces them off / on.
+// On large matrices the replayed pair measured slower than the same passes
+// enqueued one by one (10000 x 100000, m = 8: 844 against 760 us per pass;
+// 5000 x 50000, m = 1: 173 against 167 us).
+static bool graphs_enabled(const Plan& pl) {
     const char* e = std::getenv("GPSPCA_GRAPH");
-    return !(e && e[0] == '0');
+    if (e && e[0] == '0') return false;
+    if (e && e[0] == '1') return true;
+    const double elem = pl.dtype == GPSPCA_BF16 ? 2.0 : pl.dtype == GPSPCA_F8E4M3 ? 1.0 : 4.0;
+    return (double)pl.p * (double)pl.n * elem <= 256.0 * (1 << 20);
 }
 
 static int capture_pair(const Plan& pl, const PassParams& pp, const Ptrs& P, PassGraph* pg) {
@@ -683,7 +698,7 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
     int rc = noalloc ? GPSPCA_OK : pinned_ctrl(&snap);
     if (rc) return rc;
     PassGraph pg;
-    const bool use_graph = !noalloc && !tl.on && max_iter >= 8 && graphs_enabled();
+    const bool use_graph = !noalloc && !tl.on && max_iter >= 8 && graphs_enabled(pl);
     if (use_graph) {
         rc = capture_pair(pl, pp, P, &pg);
         if (rc) return rc;

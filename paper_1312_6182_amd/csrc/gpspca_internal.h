@@ -163,9 +163,11 @@ hipError_t launch_reduce_partials(const Plan& pl, const float* gpart, const int*
 hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float* X,
                        int with_x, double* g64, double* gram, const Ctrl* ctrl,
                        hipStream_t st);
+// Xn (m = 1 only, may be NULL): write x_{k+1} = g / ||g|| from g64 as well.
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
-                       double* vprev, Ctrl* ctrl, hipStream_t st);
+                       double* vprev, const double* g64, float* Xn, Ctrl* ctrl,
+                       hipStream_t st);
 hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* touched,
                               const float* X, int with_x, double* g64, double* gram,
                               const Ctrl* ctrl, hipStream_t st);

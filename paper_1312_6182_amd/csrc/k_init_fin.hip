@@ -19,42 +19,72 @@ __device__ __forceinline__ bool better(double va, int64_t ia, double vb, int64_t
     return va > vb || (va == vb && ia < ib);
 }
 
-// m rounds of a workgroup argmax over [b, e) of (val, idx) pairs; pairs whose
-// index is already chosen are skipped.  Results in chosen_v / chosen_i.
+// m rounds of a workgroup argmax over [b, e) of (val, idx) pairs.  The order
+// "larger value, then lower index" is strict and total, so round r's winner
+// is the best pair that comes after round r-1's winner in it: one comparison
+// per pair and round, and any reduction order finds the same (unique) pair.
+// Results in chosen_v / chosen_i (index -1 once the pairs run out).
+__device__ __forceinline__ void wave_best(double& v, int64_t& i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int64_t oi = __shfl_xor(i, o, 64);
+        if (better(ov, oi, v, i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+}
+
 __device__ void topm_block(int m, int64_t b, int64_t e, const double* __restrict__ val,
                            const int64_t* __restrict__ idx, double* chosen_v, int64_t* chosen_i,
                            double* rv, int64_t* ri) {
-    const int t = threadIdx.x, nt = blockDim.x;
+    const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6, nw = (nt + 63) >> 6;
+    double lv = INFINITY;   // the previous round's winner (none yet: every pair qualifies)
+    int64_t li = -1;
     for (int r = 0; r < m; ++r) {
         double bv = -INFINITY;
         int64_t bi = -1;
         for (int64_t i = b + t; i < e; i += nt) {
             const int64_t ci = idx ? idx[i] : i;
             if (ci < 0) continue;
-            bool taken = false;
-            for (int q = 0; q < r; ++q) taken |= (chosen_i[q] == ci);
-            if (taken) continue;
             const double cv = val[i];
-            if (better(cv, ci, bv, bi)) {
+            // after the previous winner in the order, and better than the best so far
+            const bool after = (r == 0) || better(lv, li, cv, ci);
+            if (after && better(cv, ci, bv, bi)) {
                 bv = cv;
                 bi = ci;
             }
         }
-        rv[t] = bv;
-        ri[t] = bi;
+        wave_best(bv, bi);
+        if (lane == 0) {
+            rv[wv] = bv;
+            ri[wv] = bi;
+        }
         __syncthreads();
-        for (int h = nt / 2; h > 0; h >>= 1) {
-            if (t < h && better(rv[t + h], ri[t + h], rv[t], ri[t])) {
-                rv[t] = rv[t + h];
-                ri[t] = ri[t + h];
+        bv = rv[0];
+        bi = ri[0];
+        for (int w = 1; w < nw; ++w)
+            if (better(rv[w], ri[w], bv, bi)) {
+                bv = rv[w];
+                bi = ri[w];
+            }
+        if (t == 0) {
+            chosen_v[r] = bv;
+            chosen_i[r] = bi;
+        }
+        lv = bv;
+        li = bi;
+        __syncthreads();
+        if (bi < 0) {
+            // pairs exhausted: the remaining rounds choose nothing
+            for (int q = r + 1 + t; q < m; q += nt) {
+                chosen_v[q] = -INFINITY;
+                chosen_i[q] = -1;
             }
             __syncthreads();
+            return;
         }
-        if (t == 0) {
-            chosen_v[r] = rv[0];
-            chosen_i[r] = ri[0];
-        }
-        __syncthreads();
     }
 }
 

@@ -512,16 +512,39 @@ hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* tou
 // A step computes its rotations (one thread per pair), then applies
 // A <- R A R^T as independent 2 x 2 blocks (rows of pair k1, columns of pair
 // k2: rows first, then columns, each block by one thread) and V <- V R^T, so
-// every entry is read and written once per step.
-// A pair is rotated while |a_pq| > 2^-40 sqrt(|a_pp a_qq|): the off-diagonal
-// then bounds the relative error of the inverse square root built from the
-// result far below the FP32 of the retracted X.
+// every entry is read and written once per step.  The pairs of a step follow
+// from the step index alone, so each thread computes its indices in
+// registers and issues its rotation and matrix loads together (one LDS round
+// trip per item).
+// A pair is rotated while |a_pq| > 2^-30 sqrt(|a_pp a_qq|) (the relative test,
+// which keeps the small eigenvalues of a graded matrix accurate).  An
+// off-diagonal of relative size e moves the inverse square root built from
+// the diagonal by at most about e relative (first-order perturbation), far
+// below the FP32 of the retracted X.  The rotated pair's off-diagonal entry is
+// set to zero exactly, as the rotation makes it: computed, it would keep a
+// rounding residue of about 2^-52 max(a_pp, a_qq), which the relative test
+// would chase without end when a_pp / a_qq is large.
 // Executed by the whole workgroup.
+__device__ __forceinline__ int rr_pos(int i, int r, int mm) {
+    // slot i of the round-robin schedule at step r (slot 0 stays in place)
+    if (i == 0) return 0;
+    int x = i - 1 + r;
+    x = (x >= mm - 1) ? x - (mm - 1) : x;
+    return 1 + x;
+}
+
+__device__ __forceinline__ void rr_pair(int k, int r, int mm, int& pp, int& qq) {
+    const int a = rr_pos(k, r, mm), b = rr_pos(mm - 1 - k, r, mm);
+    pp = a < b ? a : b;
+    qq = a < b ? b : a;
+}
+
 __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                            bool warm = false) {
+    (void)prs;
     const int t = threadIdx.x, nt = blockDim.x;
-    // |a_pq| > 2^-40 sqrt(|a_pp a_qq|), tested squared (no square root)
-    constexpr double kTol2 = 8.271806125530277e-25;  // 2^-80
+    // |a_pq| > 2^-30 sqrt(|a_pp a_qq|), tested squared (no square root)
+    constexpr double kTol2 = 8.673617379884035e-19;  // 2^-60
     if (!warm) {
         for (int e = t; e < msz * msz; e += nt) {
             const int i = e / msz, j = e % msz;
@@ -549,10 +572,8 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
         if (!__syncthreads_or(need)) break;
         for (int r = 0; r < mm - 1; ++r) {
             if (t < half) {
-                // round-robin schedule: position 0 fixed, the others rotate
-                auto pos = [&](int i) { return i == 0 ? 0 : 1 + ((i - 1 + r) % (mm - 1)); };
-                int pp = pos(t), qq = pos(mm - 1 - t);
-                if (pp > qq) { const int tmp = pp; pp = qq; qq = tmp; }
+                int pp, qq;
+                rr_pair(t, r, mm, pp, qq);
                 double c = 1.0, s = 0.0;
                 if (qq < msz) {
                     const double apq = a[pp * LDM + qq];
@@ -566,8 +587,6 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                 }
                 rot[2 * t] = c;
                 rot[2 * t + 1] = s;
-                prs[2 * t] = pp;
-                prs[2 * t + 1] = qq;
             }
             __syncthreads();
             // items: 2 x 2 blocks of A (e < nblk) and row pairs of V; a pair
@@ -576,30 +595,41 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
             for (int e = t; e < nitem; e += nt) {
                 if (e < nblk) {
                     const int k1 = e / half, k2 = e % half;
-                    const int p1 = prs[2 * k1], q1 = prs[2 * k1 + 1];
-                    const int p2 = prs[2 * k2], q2 = prs[2 * k2 + 1];
+                    int p1, q1, p2, q2;
+                    rr_pair(k1, r, mm, p1, q1);
+                    rr_pair(k2, r, mm, p2, q2);
+                    const bool h1 = q1 < msz, h2 = q2 < msz;
+                    const int q1c = h1 ? q1 : p1, q2c = h2 ? q2 : p2;
                     const double c1 = rot[2 * k1], s1 = rot[2 * k1 + 1];
                     const double c2 = rot[2 * k2], s2 = rot[2 * k2 + 1];
-                    const bool h1 = q1 < msz, h2 = q2 < msz;
-                    const double x00 = a[p1 * LDM + p2];
-                    const double x01 = h2 ? a[p1 * LDM + q2] : 0.0;
-                    const double x10 = h1 ? a[q1 * LDM + p2] : 0.0;
-                    const double x11 = (h1 && h2) ? a[q1 * LDM + q2] : 0.0;
+                    const double y00 = a[p1 * LDM + p2];
+                    const double y01 = a[p1 * LDM + q2c];
+                    const double y10 = a[q1c * LDM + p2];
+                    const double y11 = a[q1c * LDM + q2c];
+                    if (s1 == 0.0 && s2 == 0.0) continue;   // both identity (c = 1)
+                    const double x00 = y00;
+                    const double x01 = h2 ? y01 : 0.0;
+                    const double x10 = h1 ? y10 : 0.0;
+                    const double x11 = (h1 && h2) ? y11 : 0.0;
                     // rows
                     const double r00 = c1 * x00 - s1 * x10, r01 = c1 * x01 - s1 * x11;
                     const double r10 = s1 * x00 + c1 * x10, r11 = s1 * x01 + c1 * x11;
-                    // columns
+                    // columns; the diagonal block of a rotated pair has a zero
+                    // off-diagonal by construction
+                    const bool zq = (k1 == k2);
                     a[p1 * LDM + p2] = c2 * r00 - s2 * r01;
-                    if (h2) a[p1 * LDM + q2] = s2 * r00 + c2 * r01;
-                    if (h1) a[q1 * LDM + p2] = c2 * r10 - s2 * r11;
+                    if (h2) a[p1 * LDM + q2] = zq ? 0.0 : s2 * r00 + c2 * r01;
+                    if (h1) a[q1 * LDM + p2] = zq ? 0.0 : c2 * r10 - s2 * r11;
                     if (h1 && h2) a[q1 * LDM + q2] = s2 * r10 + c2 * r11;
                 } else {
                     const int f = e - nblk;
                     const int k = f / msz, row = f % msz;
-                    const int pp = prs[2 * k], qq = prs[2 * k + 1];
+                    int pp, qq;
+                    rr_pair(k, r, mm, pp, qq);
                     if (qq >= msz) continue;
                     const double c = rot[2 * k], s = rot[2 * k + 1];
                     const double vp = v[row * LDM + pp], vq = v[row * LDM + qq];
+                    if (s == 0.0) continue;
                     v[row * LDM + pp] = c * vp - s * vq;
                     v[row * LDM + qq] = s * vp + c * vq;
                 }
@@ -805,20 +835,15 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
     __syncthreads();
 }
 
-// One workgroup: objective, trace, stopping rule, retraction coefficients.
-// m = 1: ||g||^2 is summed here from the ngram Gram partials (no k_gram_sum).
-__global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __restrict__ fpart,
-                       const int* __restrict__ nnzpart, double* __restrict__ vprev,
-                       double* __restrict__ trace, double* __restrict__ coef,
-                       double* __restrict__ fcomp, const double* __restrict__ gram, int ngram,
-                       int exact, Ctrl* __restrict__ ctrl) {
-    if (ctrl->done) return;
-    __shared__ StopShared ss;
-    __shared__ double red[1024];
-    extern __shared__ double dyn[];
-    double* A0 = dyn;
-    double* A1 = dyn + (size_t)m * LDM;
-    double* A2 = dyn + (size_t)2 * m * LDM;
+// Objective of a pass, its trace entry and the stopping rule, by the whole
+// workgroup: per-component terms f_j and support sizes from the fixed-order
+// sums of the wave partials, F, and the rule (F = 0, the relative change
+// below tol, or the last allowed pass).  Fills ss (terms, live and dead
+// components, stop) and the control block; returns the stop flag.
+__device__ int stop_rule(int m, int nwp, const double* __restrict__ fpart,
+                         const int* __restrict__ nnzpart, double* __restrict__ trace,
+                         double* __restrict__ fcomp, int exact, Ctrl* __restrict__ ctrl,
+                         StopShared& ss) {
     const int t = threadIdx.x, nt = blockDim.x;
     const int k = ctrl->k;
     // the control fields the stopping rule needs, loaded up front so their
@@ -894,7 +919,29 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
         ss.stop = stop;
     }
     __syncthreads();
-    if (ss.stop) return;
+    return ss.stop;
+}
+
+// One workgroup: objective, trace, stopping rule, retraction coefficients.
+// m = 1: ||g||^2 is summed here from the ngram Gram partials (no k_gram_sum),
+// and with Xn given the retraction x_{k+1} = g / ||g|| is written here too
+// (rows < p, FP32), in place of a separate apply launch.
+__global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __restrict__ fpart,
+                       const int* __restrict__ nnzpart, double* __restrict__ vprev,
+                       double* __restrict__ trace, double* __restrict__ coef,
+                       double* __restrict__ fcomp, const double* __restrict__ gram, int ngram,
+                       int exact, const double* __restrict__ g64, float* __restrict__ Xn, int p,
+                       Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ StopShared ss;
+    __shared__ double red[1024];
+    extern __shared__ double dyn[];
+    double* A0 = dyn;
+    double* A1 = dyn + (size_t)m * LDM;
+    double* A2 = dyn + (size_t)2 * m * LDM;
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int k = ctrl->k;
+    if (stop_rule(m, nwp, fpart, nnzpart, trace, fcomp, exact, ctrl, ss)) return;
 
     const int mm = m * m;
     if (m == 1) {
@@ -914,13 +961,18 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
             coef[0] = om;
             coef[1] = 0.0;
             ctrl->ndead = 0;
-            if (!(g2 > 0.0) || !isfinite(om)) {
+            const int bad = (!(g2 > 0.0) || !isfinite(om)) ? 1 : 0;
+            if (bad) {
                 ctrl->status = GPSPCA_ENONFINITE;
                 ctrl->done = 1;
                 ctrl->n_iter = k + 1;
             }
+            red[0] = bad ? 0.0 : om;
         }
         __syncthreads();
+        const double om = red[0];
+        if (Xn && om != 0.0)
+            for (int r = t; r < p; r += nt) Xn[r] = (float)(g64[r] * om);
     } else {
         if (exact) {
             // direction G D, D = Diag(1/||s_j||): G^T G <- D G^T G D, G^T X <- D G^T X
@@ -957,19 +1009,21 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
 
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
-                       double* vprev, Ctrl* ctrl, hipStream_t st) {
+                       double* vprev, const double* g64, float* Xn, Ctrl* ctrl,
+                       hipStream_t st) {
     if (pl.m > 1) {
         hipError_t e = launch_gram_sum(pl, 3 * pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st);
         if (e != hipSuccess) return e;
     }
     // threads: the Jacobi steps of m = 64 have 32 x 32 blocks plus 64 x 32 rotated pairs of V;
-    // m = 1 needs no eigen-solver, and one wave makes every barrier free
-    const int threads = pl.m > 32 ? 1024 : pl.m > 16 ? 512 : pl.m > 1 ? 256 : 64;
+    // m = 1 needs no eigen-solver: one wave makes every barrier free, four write x
+    const int threads = pl.m > 32 ? 1024 : pl.m > 16 ? 512 : (pl.m > 1 || Xn) ? 256 : 64;
     const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
-                       nnzpart, vprev, trace, coef, fcomp, gram, pl.gram_blocks, pl.exact, ctrl);
+                       nnzpart, vprev, trace, coef, fcomp, gram, pl.gram_blocks, pl.exact,
+                       g64, pl.m == 1 ? Xn : nullptr, (int)pl.p, ctrl);
     return hipGetLastError();
 }
 
