@@ -363,6 +363,7 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     const bool xil = pl->use_mfma || pl->use_q;   // interleaved copies of X for the DMA kernels
     pl->o_xil0 = take(xil ? sizeof(float) * L * (size_t)pl->mpad : 1);
     pl->o_xil1 = take(xil ? sizeof(float) * L * (size_t)pl->mpad : 1);
+    pl->o_fsum = take(sizeof(double) * 2 * M);   // per-component objective and support sums
     pl->total = o;
 }
 
@@ -440,6 +441,7 @@ struct Ptrs {
     int* list;
     int* nlist;
     float* xil[2];
+    double* fsum;
 };
 
 static Ptrs carve(const Plan& pl, void* ws) {
@@ -471,6 +473,7 @@ static Ptrs carve(const Plan& pl, void* ws) {
     P.nlist = P.list + pl.n;
     P.xil[0] = reinterpret_cast<float*>(b + pl.o_xil0);
     P.xil[1] = reinterpret_cast<float*>(b + pl.o_xil1);
+    P.fsum = reinterpret_cast<double*>(b + pl.o_fsum);
     return P;
 }
 
@@ -596,7 +599,7 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
     } else {
         GPSPCA_HIP(launch_stop(pl, P.fpart, P.nnzpart, P.gram, P.trace, P.coef, P.fcomp,
                                P.coef + 5 * (size_t)pl.m * pl.m, P.g64, x_in_stop ? Xn : nullptr,
-                               P.ctrl, st));
+                               P.fsum, P.ctrl, st));
     }
     if (x_in_stop) return GPSPCA_OK;
     if (pl.defl_k > 0) {

@@ -108,7 +108,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
         o_l1, o_g64, o_gram, o_coef, o_norms, o_cand_v, o_cand_i, o_idx, o_fin, o_invn, o_fcomp,
-        o_pstate, o_list, o_xil0, o_xil1;
+        o_pstate, o_list, o_xil0, o_xil1, o_fsum;
     size_t total;
 };
 
@@ -166,13 +166,16 @@ hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float
 // Xn (m = 1 only, may be NULL): write x_{k+1} = g / ||g|| from g64 as well.
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
-                       double* vprev, const double* g64, float* Xn, Ctrl* ctrl,
+                       double* vprev, const double* g64, float* Xn, double* fsum, Ctrl* ctrl,
                        hipStream_t st);
 hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* touched,
                               const float* X, int with_x, double* g64, double* gram,
                               const Ctrl* ctrl, hipStream_t st);
+// fsum (may be NULL): also sum the objective and support-size partials per
+// component into fsum[0..m) and fsum[m..2m).
 hipError_t launch_gram_sum(const Plan& pl, int nent, int ngram, const double* gram, double* coef,
-                           const Ctrl* ctrl, hipStream_t st);
+                           const Ctrl* ctrl, hipStream_t st, const double* fpart = nullptr,
+                           const int* nnzpart = nullptr, double* fsum = nullptr);
 // gamma path: per-column objective, trace, stopping and normalization
 struct PathState {
     int frozen;            // 1 once this column's stopping rule fired

@@ -750,7 +750,7 @@ __device__ __forceinline__ void bpm_block(const PassParams& pp, int64_t cb, int6
 // ---------------------------------------------------------------------------
 template <int M, int KQ2, bool VEC, int ST, int G>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_backproj(
-                                                  PassParams pp, int j0,
+                                                  PassParams pp, int j0b,
                                                   const float* __restrict__ S,
                                                   const uint8_t* __restrict__ act,
                                                   float* __restrict__ gpart,
@@ -760,6 +760,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     constexpr int U = 4;
     __shared__ int list[256];
     __shared__ int wcount[4];
+    // component group of this workgroup: launches cover several groups of 16
+    // components through the grid's z dimension
+    const int j0 = j0b + 16 * (int)blockIdx.z;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int p = pp.p, nqf = p >> 2, nq = (p + 3) >> 2, m = pp.m;
     const int mg = (m - j0 < M) ? m - j0 : M;
@@ -1119,12 +1122,13 @@ static hipError_t launch_bp_dense(const Plan& pl, const PassParams& pp, const fl
     return hipGetLastError();
 }
 
+// ng: component groups of 16 from j0 on, one per grid z index.
 template <int M, bool VEC, int ST, int G>
 static hipError_t launch_bp_t(const Plan& pl, const PassParams& pp, int j0, const float* S,
                               const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
-                              hipStream_t st) {
-    hipLaunchKernelGGL((k_backproj<M, 2, VEC, ST, G>), dim3(pl.bp_rb, pl.bp_cr), dim3(256), 0, st,
-                       pp, j0, S, act, gpart, touched, pl.bp_cr, pl.bp_thr, ctrl);
+                              hipStream_t st, int ng = 1) {
+    hipLaunchKernelGGL((k_backproj<M, 2, VEC, ST, G>), dim3(pl.bp_rb, pl.bp_cr, ng), dim3(256), 0,
+                       st, pp, j0, S, act, gpart, touched, pl.bp_cr, pl.bp_thr, ctrl);
     return hipGetLastError();
 }
 
@@ -1135,6 +1139,9 @@ static hipError_t launch_bp_v(const Plan& pl, const PassParams& pp, int j0, cons
                               const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                               hipStream_t st) {
     const int r = pl.m - j0;
+    // every full group of 16 from j0 on in one launch
+    if (r > 16 || (r == 16 && pl.m > 16))
+        return launch_bp_t<16, VEC, ST, 0>(pl, pp, j0, S, act, gpart, touched, ctrl, st, r / 16);
     const int mb = r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 16;
     // m <= 16: the dense code rides in this launch; m > 16: k_backproj_dense
     const bool dense_here = j0 == 0 && pl.bp_thr <= kBpThrMax && pl.m <= 16;
@@ -1166,7 +1173,7 @@ hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
             e = launch_bp_dense<kStF32>(pl, pp, S, act, gpart, touched, ctrl, st);
         if (e != hipSuccess) return e;
     }
-    for (int j0 = 0; j0 < pl.m; j0 += 16) {
+    for (int j0 = 0; j0 < pl.m; j0 += (pl.m - j0 >= 16 && pl.m > 16) ? (pl.m - j0) / 16 * 16 : 16) {
         hipError_t e;
         if (pl.dtype == GPSPCA_BF16)
             e = launch_bp_v<true, kStBF16>(pl, pp, j0, S, act, gpart, touched, ctrl, st);

@@ -317,13 +317,59 @@ hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float
 // coefficient scratch: coef[2mm + e] = sum_g gram[g][e] for e < nent.
 // Each workgroup owns EPB = 256 / S entries; S slices per entry sum the
 // partials g = sl, sl + S, ... and a fixed-order tree adds the slices.
+// Blocks past the Gram entries (fsum != NULL) each sum one component's
+// objective and support-size partials: fsum[j] = sum_w fpart[j nwp + w],
+// fsum[m + j] = sum_w nnzpart[j nwp + w] (thread slices in order, then a fixed
+// tree), so the one-workgroup stop kernel reads 2m numbers.
 __global__ __launch_bounds__(256) void k_gram_sum(int nent, int mm, int ngram, int S,
                                                   const double* __restrict__ gram,
                                                   double* __restrict__ coef,
+                                                  const double* __restrict__ fpart,
+                                                  const int* __restrict__ nnzpart, int nwp,
+                                                  int m, double* __restrict__ fsum,
                                                   const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ double red[256];
+    __shared__ long long redc[256];
     const int t = threadIdx.x, epb = 256 / S;
+    const int nblk = (nent + epb - 1) / epb;
+    if ((int)blockIdx.x >= nblk) {
+        const int j = blockIdx.x - nblk;
+        double sf = 0.0;
+        long long sc = 0;
+        for (int w0 = t; w0 < nwp; w0 += 8 * 256) {
+            double v[8];
+            int c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int w = w0 + u * 256;
+                const int wc = w < nwp ? w : nwp - 1;
+                v[u] = fpart[(size_t)j * nwp + wc];
+                c[u] = nnzpart[(size_t)j * nwp + wc];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (w0 + u * 256 < nwp) {
+                    sf += v[u];
+                    sc += c[u];
+                }
+        }
+        red[t] = sf;
+        redc[t] = sc;
+        __syncthreads();
+        for (int hh = 128; hh >= 1; hh >>= 1) {
+            if (t < hh) {
+                red[t] += red[t + hh];
+                redc[t] += redc[t + hh];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            fsum[j] = red[0];
+            fsum[m + j] = (double)redc[0];
+        }
+        return;
+    }
     const int el = t % epb, sl = t / epb;
     const int e = blockIdx.x * epb + el;
     double s = 0.0;
@@ -353,15 +399,17 @@ __global__ __launch_bounds__(256) void k_gram_sum(int nent, int mm, int ngram, i
 }
 
 hipError_t launch_gram_sum(const Plan& pl, int nent, int ngram, const double* gram, double* coef,
-                           const Ctrl* ctrl, hipStream_t st) {
+                           const Ctrl* ctrl, hipStream_t st, const double* fpart,
+                           const int* nnzpart, double* fsum) {
     const int mm = pl.m * pl.m;
     // slices per entry: enough to shorten the serial chains, while keeping at
     // least a few workgroups busy
     int S = 1;
     while (S < 64 && S * 8 <= ngram && (nent * 2 * S + 255) / 256 <= 64) S *= 2;
     const int epb = 256 / S;
-    hipLaunchKernelGGL(k_gram_sum, dim3((nent + epb - 1) / epb), dim3(256), 0, st, nent, mm,
-                       ngram, S, gram, coef, ctrl);
+    const int blocks = (nent + epb - 1) / epb + (fsum ? pl.m : 0);
+    hipLaunchKernelGGL(k_gram_sum, dim3(blocks), dim3(256), 0, st, nent, mm, ngram, S, gram, coef,
+                       fpart, nnzpart, pl.nwave_part, pl.m, fsum, ctrl);
     return hipGetLastError();
 }
 
@@ -516,11 +564,11 @@ hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* tou
 // from the step index alone, so each thread computes its indices in
 // registers and issues its rotation and matrix loads together (one LDS round
 // trip per item).
-// A pair is rotated while |a_pq| > 2^-30 sqrt(|a_pp a_qq|) (the relative test,
-// which keeps the small eigenvalues of a graded matrix accurate).  An
-// off-diagonal of relative size e moves the inverse square root built from
-// the diagonal by at most about e relative (first-order perturbation), far
-// below the FP32 of the retracted X.  The rotated pair's off-diagonal entry is
+// A pair is rotated while |a_pq| > 2^-16 sqrt(|a_pp a_qq|) (the relative test,
+// which keeps the small eigenvalues of a graded matrix accurate); the inverse
+// square root is then built with the first-order correction of the remaining
+// off-diagonal (inv_sqrt_from_eig), which leaves an error of second order,
+// far below the FP32 of the retracted X.  The rotated pair's off-diagonal entry is
 // set to zero exactly, as the rotation makes it: computed, it would keep a
 // rounding residue of about 2^-52 max(a_pp, a_qq), which the relative test
 // would chase without end when a_pp / a_qq is large.
@@ -539,12 +587,20 @@ __device__ __forceinline__ void rr_pair(int k, int r, int mm, int& pp, int& qq) 
     qq = a < b ? b : a;
 }
 
+// Items per thread of a Jacobi step; the kernels that call jacobi_eig launch
+// at least jacobi_threads(m) threads.
+constexpr int kItems = 3;
+
+// Threads for an m x m Jacobi step: m > 32: 1024 (32 x 32 blocks + 64 x 32 rows
+// of V = 3072 items); m > 16: 512 (at most 768); else 256 (at most 192).
+static int jacobi_threads(int m) { return m > 32 ? 1024 : m > 16 ? 512 : 256; }
+
 __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                            bool warm = false) {
     (void)prs;
     const int t = threadIdx.x, nt = blockDim.x;
-    // |a_pq| > 2^-30 sqrt(|a_pp a_qq|), tested squared (no square root)
-    constexpr double kTol2 = 8.673617379884035e-19;  // 2^-60
+    // |a_pq| > 2^-16 sqrt(|a_pp a_qq|), tested squared (no square root)
+    constexpr double kTol2 = 2.3283064365386963e-10;  // 2^-32
     if (!warm) {
         for (int e = t; e < msz * msz; e += nt) {
             const int i = e / msz, j = e % msz;
@@ -556,6 +612,26 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
     const int mm = msz + (msz & 1);
     const int half = mm / 2;
     const int nblk = half * half, nitem = nblk + msz * half;
+    // items: 2 x 2 blocks of A (e < nblk: row pair ik1, column pair ik2) and
+    // rows of V (pair ik2, row irow; ik1 = -1); a pair whose second index is
+    // the padding position (odd msz) has a single row / column.  Thread t owns
+    // items t, t + nt, ... (at most kItems: blockDim.x is chosen for that).
+    int ik1[kItems], ik2[kItems], irow[kItems];
+    const int nmine = (t < nitem) ? (nitem - t + nt - 1) / nt : 0;
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+        const int e = t + u * nt;
+        if (e < nblk) {
+            ik1[u] = e / half;
+            ik2[u] = e % half;
+            irow[u] = 0;
+        } else {
+            const int f = e - nblk;
+            ik1[u] = -1;
+            ik2[u] = f / msz;
+            irow[u] = f % msz;
+        }
+    }
     for (int sweep = 0; sweep < 40; ++sweep) {
         // a sweep that would apply no rotation ends the iteration.  Every pair
         // is tested at once before the sweep: if none qualifies, no step of the
@@ -589,49 +665,69 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
                 rot[2 * t + 1] = s;
             }
             __syncthreads();
-            // items: 2 x 2 blocks of A (e < nblk) and row pairs of V; a pair
-            // whose second index is the padding position (odd msz) has a single
-            // row / column.  A row of V is a block with an identity row rotation.
-            for (int e = t; e < nitem; e += nt) {
-                if (e < nblk) {
-                    const int k1 = e / half, k2 = e % half;
+            // this thread's items (fixed for the whole eigensolve): every load
+            // of a step is issued before the first use
+            double rc[kItems][2][2];   // (c, s) of the item's pairs
+            double x[kItems][4];
+            int ip[kItems][4];         // p1, q1, p2, q2 (A block) or pp, qq, -, - (V row)
+#pragma unroll
+            for (int u = 0; u < kItems; ++u) {
+                if (u >= nmine) break;
+                if (ik1[u] >= 0) {
                     int p1, q1, p2, q2;
-                    rr_pair(k1, r, mm, p1, q1);
-                    rr_pair(k2, r, mm, p2, q2);
-                    const bool h1 = q1 < msz, h2 = q2 < msz;
-                    const int q1c = h1 ? q1 : p1, q2c = h2 ? q2 : p2;
-                    const double c1 = rot[2 * k1], s1 = rot[2 * k1 + 1];
-                    const double c2 = rot[2 * k2], s2 = rot[2 * k2 + 1];
-                    const double y00 = a[p1 * LDM + p2];
-                    const double y01 = a[p1 * LDM + q2c];
-                    const double y10 = a[q1c * LDM + p2];
-                    const double y11 = a[q1c * LDM + q2c];
+                    rr_pair(ik1[u], r, mm, p1, q1);
+                    rr_pair(ik2[u], r, mm, p2, q2);
+                    ip[u][0] = p1; ip[u][1] = q1; ip[u][2] = p2; ip[u][3] = q2;
+                    const int q1c = q1 < msz ? q1 : p1, q2c = q2 < msz ? q2 : p2;
+                    rc[u][0][0] = rot[2 * ik1[u]];
+                    rc[u][0][1] = rot[2 * ik1[u] + 1];
+                    rc[u][1][0] = rot[2 * ik2[u]];
+                    rc[u][1][1] = rot[2 * ik2[u] + 1];
+                    x[u][0] = a[p1 * LDM + p2];
+                    x[u][1] = a[p1 * LDM + q2c];
+                    x[u][2] = a[q1c * LDM + p2];
+                    x[u][3] = a[q1c * LDM + q2c];
+                } else {
+                    int pp, qq;
+                    rr_pair(ik2[u], r, mm, pp, qq);
+                    const int qc = qq < msz ? qq : pp;
+                    ip[u][0] = pp; ip[u][1] = qq;
+                    rc[u][0][0] = rot[2 * ik2[u]];
+                    rc[u][0][1] = rot[2 * ik2[u] + 1];
+                    x[u][0] = v[irow[u] * LDM + pp];
+                    x[u][1] = v[irow[u] * LDM + qc];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kItems; ++u) {
+                if (u >= nmine) break;
+                if (ik1[u] >= 0) {
+                    const int p1 = ip[u][0], q1 = ip[u][1], p2 = ip[u][2], q2 = ip[u][3];
+                    const double c1 = rc[u][0][0], s1 = rc[u][0][1];
+                    const double c2 = rc[u][1][0], s2 = rc[u][1][1];
                     if (s1 == 0.0 && s2 == 0.0) continue;   // both identity (c = 1)
-                    const double x00 = y00;
-                    const double x01 = h2 ? y01 : 0.0;
-                    const double x10 = h1 ? y10 : 0.0;
-                    const double x11 = (h1 && h2) ? y11 : 0.0;
+                    const bool h1 = q1 < msz, h2 = q2 < msz;
+                    const double x00 = x[u][0];
+                    const double x01 = h2 ? x[u][1] : 0.0;
+                    const double x10 = h1 ? x[u][2] : 0.0;
+                    const double x11 = (h1 && h2) ? x[u][3] : 0.0;
                     // rows
                     const double r00 = c1 * x00 - s1 * x10, r01 = c1 * x01 - s1 * x11;
                     const double r10 = s1 * x00 + c1 * x10, r11 = s1 * x01 + c1 * x11;
                     // columns; the diagonal block of a rotated pair has a zero
                     // off-diagonal by construction
-                    const bool zq = (k1 == k2);
+                    const bool zq = (ik1[u] == ik2[u]);
                     a[p1 * LDM + p2] = c2 * r00 - s2 * r01;
                     if (h2) a[p1 * LDM + q2] = zq ? 0.0 : s2 * r00 + c2 * r01;
                     if (h1) a[q1 * LDM + p2] = zq ? 0.0 : c2 * r10 - s2 * r11;
                     if (h1 && h2) a[q1 * LDM + q2] = s2 * r10 + c2 * r11;
                 } else {
-                    const int f = e - nblk;
-                    const int k = f / msz, row = f % msz;
-                    int pp, qq;
-                    rr_pair(k, r, mm, pp, qq);
-                    if (qq >= msz) continue;
-                    const double c = rot[2 * k], s = rot[2 * k + 1];
-                    const double vp = v[row * LDM + pp], vq = v[row * LDM + qq];
-                    if (s == 0.0) continue;
-                    v[row * LDM + pp] = c * vp - s * vq;
-                    v[row * LDM + qq] = s * vp + c * vq;
+                    const int pp = ip[u][0], qq = ip[u][1];
+                    const double c = rc[u][0][0], s = rc[u][0][1];
+                    if (qq >= msz || s == 0.0) continue;
+                    const double vp = x[u][0], vq = x[u][1];
+                    v[irow[u] * LDM + pp] = c * vp - s * vq;
+                    v[irow[u] * LDM + qq] = s * vp + c * vq;
                 }
             }
             __syncthreads();
@@ -639,12 +735,58 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
     }
 }
 
-// out = V diag(lam^{-1/2}) V^T from the diagonalized a and eigenvectors v.
-// Eigenvalues below (msz * eps)^2 * lam_max count as zero (their inverse root
-// is dropped) and set *rankdef.
-__device__ void inv_sqrt_from_eig(const double* a, const double* v, double* out, int msz,
+// C = op(A) op(B) for n x n matrices in LDS (leading dim LDM), op(X) = X or
+// X^T.  With h = ceil(n/2), thread t = ii h + jj computes the four entries
+// (ii | ii + h) x (jj | jj + h) of C in registers, summing over k in order
+// (h^2 <= blockDim.x: jacobi_threads): the lanes of a wave then read
+// consecutive entries of B (and share those of A), free of LDS bank
+// conflicts.  C is written after a barrier, so it may be A or B.  Executed by
+// the whole workgroup.
+template <bool TA, bool TB>
+__device__ void lds_gemm(int n, const double* A, const double* B, double* C) {
+    const int t = threadIdx.x, h = (n + 1) / 2;
+    const bool mine = t < h * h;
+    const int ii = mine ? t / h : 0, jj = mine ? t % h : 0;
+    const int i1 = ii + h < n ? ii + h : ii, j1 = jj + h < n ? jj + h : jj;
+    double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+    if (mine) {
+        for (int k = 0; k < n; ++k) {
+            const double a0 = TA ? A[k * LDM + ii] : A[ii * LDM + k];
+            const double a1 = TA ? A[k * LDM + i1] : A[i1 * LDM + k];
+            const double b0 = TB ? B[jj * LDM + k] : B[k * LDM + jj];
+            const double b1 = TB ? B[j1 * LDM + k] : B[k * LDM + j1];
+            c00 += a0 * b0;
+            c01 += a0 * b1;
+            c10 += a1 * b0;
+            c11 += a1 * b1;
+        }
+    }
+    __syncthreads();
+    if (mine) {
+        C[ii * LDM + jj] = c00;
+        if (jj + h < n) C[ii * LDM + jj + h] = c01;
+        if (ii + h < n) C[(ii + h) * LDM + jj] = c10;
+        if (ii + h < n && jj + h < n) C[(ii + h) * LDM + jj + h] = c11;
+    }
+    __syncthreads();
+}
+
+// out = V Y V^T ~ (V a V^T)^{-1/2} from the Jacobi result: a = V^T M V is
+// diagonal up to off-diagonal entries below the stopping tolerance.  Y is the
+// inverse square root of a to first order in its off-diagonal (the
+// Daleckii-Krein formula): Y_ii = a_ii^{-1/2}, and for i != j
+//   Y_ij = f[a_ii, a_jj] a_ij,  f[x, y] = (x^{-1/2} - y^{-1/2}) / (x - y)
+//        = -1 / (sqrt(x) sqrt(y) (sqrt(x) + sqrt(y))),
+// a divided difference that stays finite for equal diagonal entries.  The
+// error left is second order in the relative off-diagonal e (measured below
+// 250 e^2 on the retracted X: 6e-8 at e = 2^-16, the FP32 rounding of X), so
+// the sweeps stop there.
+// Eigenvalues below (msz * eps)^2 * lam_max count as zero (their row and
+// column of Y are dropped) and set *rankdef.  a is overwritten.
+__device__ void inv_sqrt_from_eig(double* a, const double* v, double* out, int msz,
                                   double* lam, int* rankdef) {
     const int t = threadIdx.x, nt = blockDim.x;
+    const int ne = msz * msz;
     // every thread finds the largest eigenvalue; thread i inverts the root of
     // eigenvalue i
     double lmax = 0.0;
@@ -658,13 +800,20 @@ __device__ void inv_sqrt_from_eig(const double* a, const double* v, double* out,
     }
     rd = __syncthreads_or(rd);
     if (t == 0) *rankdef = rd;
-    for (int e = t; e < msz * msz; e += nt) {
+    // Y in place of a: with l_i = a_ii^{-1/2}, f[a_ii, a_jj] = -(l_i l_j)^2 / (l_i + l_j)
+    for (int e = t; e < ne; e += nt) {
         const int i = e / msz, j = e % msz;
-        double s = 0.0;
-        for (int k = 0; k < msz; ++k) s += v[i * LDM + k] * lam[k] * v[j * LDM + k];
-        out[i * LDM + j] = s;
+        const double li = lam[i], lj = lam[j];
+        double y;
+        if (i == j) y = li;
+        else if (li == 0.0 || lj == 0.0) y = 0.0;
+        else y = -a[i * LDM + j] * (li * lj) * (li * lj) / (li + lj);
+        a[i * LDM + j] = y;
     }
     __syncthreads();
+    // T = V Y over Y, then out = T V^T
+    lds_gemm<false, false>(msz, v, a, a);
+    lds_gemm<false, true>(msz, a, v, out);
 }
 
 // Sum over the 64 lanes of a wave by a fixed butterfly (every lane gets it).
@@ -740,22 +889,11 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
     if (warm) {
         // A0 <- V0^T M V0 with the previous pass's eigenvectors V0: the Gram matrix
         // changes little between passes, so this is nearly diagonal already
-        for (int e = t; e < nl * nl; e += nt) {
-            const int i = e / nl, j = e % nl;
-            double s2 = 0.0;
-            for (int k = 0; k < nl; ++k) s2 += A0[i * LDM + k] * A1[k * LDM + j];
-            A2[i * LDM + j] = s2;
-        }
-        __syncthreads();
-        for (int e = t; e < nl * nl; e += nt) {
-            const int i = e / nl, j = e % nl;
-            double s2 = 0.0;
-            for (int k = 0; k < nl; ++k) s2 += A1[k * LDM + i] * A2[k * LDM + j];
-            A0[i * LDM + j] = s2;
-        }
-        __syncthreads();
+        lds_gemm<false, false>(nl, A0, A1, A2);
+        lds_gemm<true, false>(nl, A1, A2, A0);
     }
     jacobi_eig(A0, A1, nl, ss.rot, ss.prs, warm);
+
     if (nd == 0) {
         for (int e = t; e < nl * nl; e += nt) {
             const int i = e / nl, j = e % nl;
@@ -764,6 +902,7 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
     }
     int rd1 = 0;
     inv_sqrt_from_eig(A0, A1, A2, nl, ss.lam, &ss.rankdef);
+
     rd1 = ss.rankdef;
     __syncthreads();
     // Omega[L,L] = W_L
@@ -843,7 +982,7 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
 __device__ int stop_rule(int m, int nwp, const double* __restrict__ fpart,
                          const int* __restrict__ nnzpart, double* __restrict__ trace,
                          double* __restrict__ fcomp, int exact, Ctrl* __restrict__ ctrl,
-                         StopShared& ss) {
+                         StopShared& ss, const double* __restrict__ fsum = nullptr) {
     const int t = threadIdx.x, nt = blockDim.x;
     const int k = ctrl->k;
     // the control fields the stopping rule needs, loaded up front so their
@@ -851,10 +990,16 @@ __device__ int stop_rule(int m, int nwp, const double* __restrict__ fpart,
     const double last_F = ctrl->last_F, tol = ctrl->tol;
     const int max_iter = ctrl->max_iter, deg_seen = ctrl->degenerate_seen;
 
-    // per-component objective and support size: tpc (a power of two <= 64)
-    // lanes of one wave per component, each summing a strided slice, the
-    // slices combined by a fixed butterfly (fixed order)
-    {
+    // per-component objective and support size: summed already (fsum, by the
+    // Gram-sum kernel), or here by tpc (a power of two <= 64) lanes of one
+    // wave per component, each summing a strided slice, the slices combined by
+    // a fixed butterfly (fixed order)
+    if (fsum) {
+        for (int j = t; j < m; j += nt) {
+            ss.fj[j] = fsum[j];
+            ss.nj[j] = (int)fsum[m + j];
+        }
+    } else {
         int tpc = 64;
         while (tpc > 1 && tpc * m > nt) tpc >>= 1;
         for (int j0 = 0; j0 < m; j0 += nt / tpc) {
@@ -931,7 +1076,7 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
                        double* __restrict__ trace, double* __restrict__ coef,
                        double* __restrict__ fcomp, const double* __restrict__ gram, int ngram,
                        int exact, const double* __restrict__ g64, float* __restrict__ Xn, int p,
-                       Ctrl* __restrict__ ctrl) {
+                       const double* __restrict__ fsum, Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ StopShared ss;
     __shared__ double red[1024];
@@ -941,7 +1086,8 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
     double* A2 = dyn + (size_t)2 * m * LDM;
     const int t = threadIdx.x, nt = blockDim.x;
     const int k = ctrl->k;
-    if (stop_rule(m, nwp, fpart, nnzpart, trace, fcomp, exact, ctrl, ss)) return;
+    if (stop_rule(m, nwp, fpart, nnzpart, trace, fcomp, exact, ctrl, ss, m > 1 ? fsum : nullptr))
+        return;
 
     const int mm = m * m;
     if (m == 1) {
@@ -1009,21 +1155,22 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
 
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
-                       double* vprev, const double* g64, float* Xn, Ctrl* ctrl,
+                       double* vprev, const double* g64, float* Xn, double* fsum, Ctrl* ctrl,
                        hipStream_t st) {
     if (pl.m > 1) {
-        hipError_t e = launch_gram_sum(pl, 3 * pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st);
+        hipError_t e = launch_gram_sum(pl, 3 * pl.m * pl.m, pl.gram_blocks, gram, coef, ctrl, st,
+                                       fpart, nnzpart, fsum);
         if (e != hipSuccess) return e;
     }
     // threads: the Jacobi steps of m = 64 have 32 x 32 blocks plus 64 x 32 rotated pairs of V;
     // m = 1 needs no eigen-solver: one wave makes every barrier free, four write x
-    const int threads = pl.m > 32 ? 1024 : pl.m > 16 ? 512 : (pl.m > 1 || Xn) ? 256 : 64;
+    const int threads = pl.m > 1 ? jacobi_threads(pl.m) : Xn ? 256 : 64;
     const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
                        nnzpart, vprev, trace, coef, fcomp, gram, pl.gram_blocks, pl.exact,
-                       g64, pl.m == 1 ? Xn : nullptr, (int)pl.p, ctrl);
+                       g64, pl.m == 1 ? Xn : nullptr, (int)pl.p, fsum, ctrl);
     return hipGetLastError();
 }
 
@@ -1226,7 +1373,7 @@ hipError_t launch_project(const Plan& pl, const double* gram, double* coef, Ctrl
                           hipStream_t st) {
     hipError_t e = launch_gram_sum(pl, pl.m * pl.m, pl.gram_grid, gram, coef, ctrl, st);
     if (e != hipSuccess) return e;
-    const int threads = pl.m > 16 ? 512 : 256;
+    const int threads = jacobi_threads(pl.m);
     const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_project), true);
     (void)lds_once;
@@ -1277,9 +1424,74 @@ __global__ __launch_bounds__(256) void k_apply(int m, int p, int ldx,
         Xil[((size_t)((j >> 4) * (ldx >> 2) + (r >> 2)) * 16 + (j & 15)) * 4 + (r & 3)] = (float)acc;
 }
 
+// The same for m > 16 (full Omega and Psi): grid (row blocks of 256, groups of
+// 16 components); each thread reads its row of G once and keeps 16 outputs,
+// summing over l in the same order as k_apply (bitwise the same result), so G
+// is read m / 16 instead of m times.
+__global__ __launch_bounds__(256) void k_apply16(int m, int p, int ldx,
+                                                 const double* __restrict__ g64,
+                                                 const float* __restrict__ Xk,
+                                                 const double* __restrict__ coef,
+                                                 float* __restrict__ Xn, float* __restrict__ Xil,
+                                                 const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double om[kMaxM][16];
+    __shared__ double ps[kMaxM][16];
+    const int t = threadIdx.x, jb = blockIdx.y * 16, mm = m * m;
+    const int nj = (m - jb < 16) ? m - jb : 16;
+    const bool dead = ctrl->ndead > 0;
+    for (int e = t; e < m * 16; e += 256) {
+        const int l = e >> 4, jj = e & 15;
+        const int j = jb + (jj < nj ? jj : nj - 1);
+        om[l][jj] = coef[l * m + j];
+        ps[l][jj] = dead ? coef[mm + l * m + j] : 0.0;
+    }
+    __syncthreads();
+    const int r = blockIdx.x * 256 + t;
+    if (r >= p) return;
+    double acc[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+    int l = 0;
+    for (; l + 4 <= m; l += 4) {  // 4 loads issued together
+        double gv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gv[u] = g64[(size_t)(l + u) * p + r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) acc[jj] += gv[u] * om[l + u][jj];
+    }
+    for (; l < m; ++l) {
+        const double gv = g64[(size_t)l * p + r];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) acc[jj] += gv * om[l][jj];
+    }
+    if (dead)
+        for (int l2 = 0; l2 < m; ++l2) {
+            const double xv = (double)Xk[(size_t)l2 * ldx + r];
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) acc[jj] += xv * ps[l2][jj];
+        }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        if (jj >= nj) break;
+        const int j = jb + jj;
+        const float v = (float)acc[jj];
+        Xn[(size_t)j * ldx + r] = v;
+        if (Xil)
+            Xil[((size_t)((j >> 4) * (ldx >> 2) + (r >> 2)) * 16 + (j & 15)) * 4 + (r & 3)] = v;
+    }
+}
+
 hipError_t launch_apply(const Plan& pl, const double* g64, const float* Xk, const double* coef,
                         float* Xn, float* Xil_n, const Ctrl* ctrl, hipStream_t st) {
     const int p = (int)pl.p;
+    if (pl.m > 16 && !pl.path) {
+        hipLaunchKernelGGL(k_apply16, dim3((p + 255) / 256, (pl.m + 15) / 16), dim3(256), 0, st,
+                           pl.m, p, pl.ldx, g64, Xk, coef, Xn, Xil_n, ctrl);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_apply, dim3((p + 255) / 256, pl.m), dim3(256), 0, st, pl.m, p, pl.ldx,
                        g64, Xk, coef, Xn, Xil_n, pl.path, ctrl);
     return hipGetLastError();
