@@ -138,19 +138,21 @@ def random_orthonormal(p: int, m: int, seed: int) -> np.ndarray:
     return np.asfortranarray(Q * np.sign(np.diag(R))[None, :])
 
 
-def serving_requests(count: int, seed: int = 1000, p_max: int = 20000, n_max: int = 200000):
+def serving_requests(count: int, seed: int = 1000, p_max: int = 20000, n_max: int = 200000,
+                     repeat: float = 0.5):
     """Request descriptors of the mixed serving workload.
 
     p log-uniform in [200, p_max], n log-uniform in [2000, n_max] (20000 and
     200000 in the full setting), a formulation uniform over the four, m in
     {1, 4, 16} (for a single-unit form, m > 1 means m starts from the m columns
     of largest norm), gamma fraction uniform in
-    [0.01, 0.5], storage FP32 or bfloat16 (even odds), and with probability 1/2
-    a repeat of an earlier request's matrix."""
+    [0.01, 0.5], storage FP32 or bfloat16 (even odds), and with probability
+    `repeat` a repeat of an earlier request's matrix (a new gamma, form and m
+    on a matrix that may still be resident)."""
     rng = np.random.default_rng(seed)
     out = []
     for r in range(count):
-        if out and rng.random() < 0.5:
+        if out and rng.random() < repeat:
             prev = out[int(rng.integers(len(out)))]
             p, n, mseed, dt = prev["p"], prev["n"], prev["matrix_seed"], prev["dtype"]
         else:
