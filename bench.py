@@ -546,7 +546,8 @@ def sweep(args):
     5.  A is resident on the device; the time covers the whole solve call
     (start, passes, finalize, copy of the traces to the host).  The FP64 oracle
     runs the same solves on the host on the first instances, within a budget,
-    and its final objective per component is compared with the GPU's."""
+    and the first instance of each cell is compared with it at a fixed pass
+    count (sweep_parity)."""
     import torch
     import paper_1312_6182_amd as G
     from workloads import generators as W
