@@ -209,8 +209,10 @@ def column_norms(A: torch.Tensor, stream: Optional[torch.cuda.Stream] = None,
     return out
 
 
-def profile_enable(on: bool = True) -> None:
-    L.load().gpspca_profile_enable(1 if on else 0)
+def profile_enable(on: bool = True, every: int = 1) -> None:
+    """Time the dominant kernel's launches with HIP events: the first of each
+    solve and every `every`-th after it (False: off)."""
+    L.load().gpspca_profile_enable(max(1, int(every)) if on else 0)
 
 
 def profile_read():

@@ -140,6 +140,7 @@ static Tune env_tune() {
         const std::string fk = f;
         t.kernel = fk == "mfma" ? kTuneMfma : fk == "vx" ? kTuneVx : fk == "valu" ? kTuneValu
                  : fk == "rd" ? kTuneRd : fk == "rd128" ? kTuneRd128 : fk == "wg" ? kTuneWg
+                 : fk == "x3" ? kTuneX3
                  : fk == "mv" ? -1 : kTuneDefault;
     }
     if (const char* e = std::getenv("GPSPCA_MFMA_STAGES")) t.stages = std::atoi(e);
@@ -212,7 +213,9 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         // correlation kernel.  Choice: an explicit configuration (the autotuner
         // trying candidates), else the environment (tests, benchmarks), else the
         // autotuner's table, else the measured default -- register-resident X
-        // for m <= 4, matrix cores otherwise.
+        // for m <= 4, the FP32 matrix cores up to m = 32, and the FP32 values
+        // split into bfloat16 parts on the bfloat16 matrix cores beyond (m = 64
+        // on 10000 x 100000: 1243 us against 1301 for the best FP32 kernel).
         Tune tn{kTuneDefault, 0, 0};
         if (force) {
             tn = *force;
@@ -232,9 +235,11 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         else if (tn.kernel == kTuneMfma && pl->vec4) pl->use_mfma = 1;
         else if (tn.kernel == kTuneRd && pl->vec4) pl->use_mfma = pl->use_rd = 1;
         else if (tn.kernel == kTuneRd128 && pl->vec4) pl->use_mfma = pl->use_rd = pl->rd128 = 1;
+        else if (tn.kernel == kTuneX3 && pl->vec4) pl->use_mfma = pl->use_x3 = 1;
         else if (tn.kernel == kTuneWg && pl->vec4) pl->use_mfma = pl->use_wg = 1;
         else if (tn.kernel == kTuneValu) {}
         else if (vx_ok && m <= 4) pl->use_vx = 1;
+        else if (m > 32 && pl->vec4) pl->use_mfma = pl->use_x3 = 1;   // FP32 matrix cores are the bound
         else pl->use_mfma = pl->vec4;
         if (pl->use_q) {
             // 16/8-bit storage: bfloat16 matrix cores, one wavefront per workgroup
@@ -269,7 +274,8 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
                                         : 2;
             pl->rd_depth = (tn.stages == 2 || tn.stages == 3 || tn.stages == 6) ? tn.stages : 4;
             int per_cu = tn.waves > 0 ? tn.waves : 4;
-            if (!pl->use_rd && !pl->use_mv)
+            if (pl->use_x3) pl->rd_depth = tn.stages == 3 ? 3 : 2;
+            if (!pl->use_rd && !pl->use_mv && !pl->use_x3)
                 per_cu = std::min(per_cu, corr_mfma_blocks_per_cu(m, pl->mfma_stages));
             if (pl->use_mv) per_cu = 4;
             pl->waves_per_cu = per_cu;
@@ -327,7 +333,8 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     // summed faster by the split reduction, whose grid also spans the partials
     pl->fused_gram = (m <= 16 && !pl->fused_m1 && pl->npart <= 128) ? 1 : 0;
     pl->gram_blocks = pl->fused_gram ? (int)cdiv(A->p, 64) : pl->gram_grid;
-    pl->fin_grid = (int)std::max<int64_t>(1, cdiv(cdiv(A->n, 32), 256));
+    // 256 / m support words (32 columns each) per finalize workgroup
+    pl->fin_grid = (int)std::max<int64_t>(1, cdiv(cdiv(A->n, 32), 256 / std::max(1, m)));
     pl->topm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(A->n, 1024)));
 
     size_t o = 0;
@@ -390,6 +397,10 @@ static std::vector<Tune> tune_candidates(const gpspca_matrix* A, int m, int path
         c.push_back(Tune{kTuneMfma, 0, 4});
         if (m <= 32) c.push_back(Tune{kTuneMfma, 3, 4});
         c.push_back(Tune{kTuneWg, 8, 4});
+    }
+    if (m > 16) {
+        c.push_back(Tune{kTuneX3, 2, 4});
+        c.push_back(Tune{kTuneX3, 3, 4});
     }
     c.push_back(Tune{kTuneRd, 4, 4});
     c.push_back(Tune{kTuneRd128, 4, 4});
@@ -506,6 +517,7 @@ static PassParams make_params(const gpspca_matrix* A, const Plan& pl, double gam
 struct Prof {
     std::mutex mu;
     bool on = false;
+    int every = 1;   // time one launch in `every`
     double total_ms = 0.0;
     int64_t launches = 0;
     std::string name;
@@ -515,6 +527,9 @@ static Prof g_prof;
 struct TimedLaunches {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     bool on = false;
+    int every = 1;
+    int64_t seen = 0;
+    bool cur = false;   // the current launch is timed
     ~TimedLaunches() {
         for (auto& e : ev) {
             (void)hipEventDestroy(e.first);
@@ -522,7 +537,8 @@ struct TimedLaunches {
         }
     }
     hipError_t begin(hipStream_t st) {
-        if (!on) return hipSuccess;
+        cur = on && (seen++ % every) == 0;
+        if (!cur) return hipSuccess;
         // timing only: no system-scope fence at the event (the two events of a
         // pass cost about 12 us with the default flags on 10000 x 100000, m = 8)
         hipEvent_t a, b;
@@ -534,7 +550,7 @@ struct TimedLaunches {
         return hipEventRecord(a, st);
     }
     hipError_t end(hipStream_t st) {
-        if (!on) return hipSuccess;
+        if (!cur) return hipSuccess;
         return hipEventRecord(ev.back().second, st);
     }
     void collect(const char* name) {
@@ -569,6 +585,9 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
         else if (pl.use_q)
             GPSPCA_HIP(launch_corr_q(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
                                      P.ctrl, st));
+        else if (pl.use_x3)
+            GPSPCA_HIP(launch_corr_x3(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
+                                      P.ctrl, st));
         else if (pl.use_rd)
             GPSPCA_HIP(launch_corr_rd(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
                                       P.ctrl, st));
@@ -695,6 +714,7 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
     if (!noalloc) {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         tl.on = g_prof.on;
+        tl.every = g_prof.every;
     }
     Ctrl stack_snap;
     Ctrl* snap = &stack_snap;
@@ -730,6 +750,7 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
                            : pl.use_vx ? "k_corr_vx"
                            : pl.use_mv ? "k_corr_mv"
                            : pl.use_q ? "k_corr_q"
+                           : pl.use_x3 ? "k_corr_x3"
                            : pl.use_rd ? "k_corr_rd"
                            : pl.use_wg ? "k_corr_wg"
                            : pl.use_mfma ? "k_corr_mfma" : "k_corr");
@@ -1283,12 +1304,14 @@ static int time_config(const gpspca_matrix* A, int pform, int m, double gamma, i
 static std::string tune_text(const Plan& pl) {
     char b[96];
     const char* k = pl.fused_m1 ? "k_pass_m1" : pl.use_vx ? "k_corr_vx"
+                  : pl.use_x3 ? "k_corr_x3"
                   : pl.use_rd ? (pl.rd128 ? "k_corr_rd(128-byte lines)" : "k_corr_rd")
                   : pl.use_wg ? "k_corr_wg"
                   : pl.use_q ? "k_corr_q" : pl.use_mfma ? "k_corr_mfma" : pl.use_mv ? "k_corr_mv"
                   : "k_corr";
     std::snprintf(b, sizeof(b), "%s stages=%d waves_per_cu=%d grid=%d", k,
-                  pl.use_rd ? pl.rd_depth : pl.mfma_stages, pl.waves_per_cu, pl.corr_grid);
+                  (pl.use_rd || pl.use_x3) ? pl.rd_depth : pl.mfma_stages, pl.waves_per_cu,
+                  pl.corr_grid);
     return b;
 }
 
@@ -1361,7 +1384,8 @@ int gpspca_column_norms(const gpspca_matrix* A, double* norms, void* stream) {
 
 int gpspca_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    g_prof.on = on != 0;
+    g_prof.on = on > 0;
+    g_prof.every = on > 0 ? on : 1;
     return GPSPCA_OK;
 }
 

@@ -58,7 +58,7 @@ struct PassParams {
 
 // A configuration of the correlation kernel: the autotuner's unit of choice.
 enum TuneKernel { kTuneDefault = 0, kTuneMfma = 1, kTuneVx = 2, kTuneValu = 3, kTuneRd = 4,
-                  kTuneWg = 5, kTuneRd128 = 6 };
+                  kTuneWg = 5, kTuneRd128 = 6, kTuneX3 = 7 };
 struct Tune {
     int kernel;            // TuneKernel
     int stages;            // LDS stages (matrix-core kernels), 0 = default
@@ -95,6 +95,7 @@ struct Plan {
     int mfma_stages;       // stages in flight of the matrix-core kernels (FP32 and 16/8-bit)
     int waves_per_cu;      // resident matrix-core workgroups per CU
     int use_rd;            // matrix-core correlation with register-direct operand loads
+    int use_x3;            // FP32 correlation on the bfloat16 matrix cores (three-part split)
     int use_wg;            // matrix-core correlation, four waves sharing X per workgroup
     int rd_depth;          // its software-pipeline depth (stages of 32 rows)
     int rd128;             // register-direct loads of whole 128-byte lines (8 columns each)
@@ -127,6 +128,9 @@ hipError_t launch_corr_wg(const Plan& pl, const PassParams& pp, const float* X, 
                           float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st);
 hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                          float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st);
+hipError_t launch_corr_x3(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
                           float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st);
 int corr_mfma_blocks_per_cu(int m, int stages);

@@ -881,6 +881,242 @@ hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, 
 }
 
 // ---------------------------------------------------------------------------
+// k_corr_x3: the correlation of FP32 A and X on the bfloat16 matrix cores.
+// Every FP32 value v splits exactly into three bfloat16 parts, v = v1 + v2 +
+// v3 (v1 = bf16(v), v2 = bf16(v - v1), v3 = v - v1 - v2: 8 + 8 + 8 bits of
+// the 24-bit significand, each residual exact in FP32), and y_ij = a_i^T x_j
+// is accumulated in FP32 from the six part products a_k x_l with k + l <= 4.
+// The three dropped ones (k + l >= 5) add up to less than 2^-23 |a_ri x_rj|
+// per row, the size of FP32's own rounding of the product.  A 16x16x32
+// bfloat16 MFMA does 8 times the work of a 16x16x4 FP32 one at twice its
+// rate, so the six cost 3/8 of the FP32 matrix-core time: at 64 components,
+// where the FP32 kernels are bound by the matrix cores, this one is bound by
+// HBM and the splitting (VALU) instead.
+// Loads as in k_corr_rd (registers only, software-pipelined D stages of 32
+// rows): lane (lj, lk) holds quads lk and 4 + lk of a stage of column 16 t +
+// lj, which are the 8 k-values of its bfloat16 operand, and the same quads of
+// component lj of X from the interleaved copy.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8m __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split3_bf16(const f4m& q0, const f4m& q1, bf8m& v1, bf8m& v2,
+                                            bf8m& v3) {
+    float r[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        r[e] = q0[e];
+        r[4 + e] = q1[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        v1[e] = (__bf16)r[e];
+        r[e] -= (float)v1[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        v2[e] = (__bf16)r[e];
+        r[e] -= (float)v2[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v3[e] = (__bf16)r[e];
+}
+
+template <int NT, int J, int D>
+__device__ __forceinline__ void x3_chunk(const PassParams& pp, int64_t c0, int64_t cend,
+                                         const float* const* xcol,
+                                         const float* __restrict__ Xil, double* f_acc,
+                                         int* nnz_acc, float* __restrict__ S,
+                                         uint8_t* __restrict__ act) {
+    int nact_l = 0;   // active columns written by this lane
+    const int lane = threadIdx.x;
+    const int lj = lane & 15, lk = lane >> 4;
+    const int p = pp.p, m = pp.m;
+    const int nqf = p >> 2;
+    const int nqx = pp.ldx >> 2;
+    const int nst = (nqf + kQS - 1) / kQS;
+    const bool l0 = pp.l0 != 0;
+
+    const float* colp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        int64_t col = c0 + 16 * t + lj;
+        col = (col < cend) ? col : cend - 1;
+        colp[t] = pp.A + col * pp.lda;
+    }
+    f4m abuf[D][NT][2], xbuf[D][J][2];
+    auto load = [&](int st, f4m(&ab)[NT][2], f4m(&xb)[J][2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = kQS * st + 4 * h + lk;
+            const int qa = (q < nqf) ? q : nqf - 1;
+            const int qx = (q < nqf) ? q : nqx - 1;   // the last quad of X is zero
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                ab[t][h] = __builtin_nontemporal_load(reinterpret_cast<const f4m*>(colp[t] + 4 * qa));
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+                xb[jb][h] = *reinterpret_cast<const f4m*>(
+                    Xil + ((size_t)(jb * nqx + qx) * 16 + lj) * 4);
+        }
+    };
+    f4m acc[NT][J];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4m{0.f, 0.f, 0.f, 0.f};
+
+    if (nst > 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) load(d, abuf[d], xbuf[d]);
+        __builtin_amdgcn_sched_barrier(0);
+        for (int s0 = 0; s0 < nst; s0 += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                bf8m x1[J], x2[J], x3[J];
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    split3_bf16(xbuf[d][jb][0], xbuf[d][jb][1], x1[jb], x2[jb], x3[jb]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    bf8m a1, a2, a3;
+                    split3_bf16(abuf[d][t][0], abuf[d][t][1], a1, a2, a3);
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb) {
+                        // smallest terms first
+                        f4m c = acc[t][jb];
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, x1[jb], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, x2[jb], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x3[jb], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, x1[jb], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x2[jb], c, 0, 0, 0);
+                        acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x1[jb], c, 0, 0, 0);
+                    }
+                }
+                // stages past the last one re-read it (clamped) and meet zero X
+                int nxt = s0 + d + D;
+                nxt = (nxt < nst) ? nxt : nst;
+                __builtin_amdgcn_sched_barrier(0);
+                load(nxt, abuf[d], xbuf[d]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    if (p & 3) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int64_t col = c0 + 16 * t + 4 * lk + v;
+                col = (col < cend) ? col : cend - 1;
+                const float* ac = pp.A + col * pp.lda;
+                for (int r = 4 * nqf; r < p; ++r) {
+                    const float a = ac[r];
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb)
+                        acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
+                }
+            }
+    }
+
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t col = c0 + 16 * t + 4 * lk + v;
+            const bool cvalid = col < cend;
+            bool any = false;
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb) {
+                const int comp = 16 * jb + lj;
+                if (cvalid && comp < m) {
+                    float s;
+                    double fv;
+                    const bool a = threshold_m(l0, pp.mu[comp], pp.gam[comp], acc[t][jb][v], s, fv);
+                    S[col * m + comp] = s;
+                    if (a) {
+                        f_acc[jb] += fv;
+                        nnz_acc[jb] += 1;
+                        any = true;
+                    }
+                }
+            }
+            const uint64_t bal = __ballot(any);
+            if (cvalid && lj == 0) {
+                const int fl = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                act[col] = fl;
+                nact_l += fl;
+            }
+        }
+    add_active_count(nact_l, pp.nact);
+}
+
+template <int J, int D>
+__global__ __launch_bounds__(64) void k_corr_x3(PassParams pp, const float* __restrict__ X,
+                                                const float* __restrict__ Xil,
+                                                float* __restrict__ S, uint8_t* __restrict__ act,
+                                                double* __restrict__ fpart,
+                                                int* __restrict__ nnzpart,
+                                                const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int lane = threadIdx.x;
+    const int m = pp.m, ldx = pp.ldx;
+    const int64_t n = pp.n;
+    const int64_t W = gridDim.x, w = blockIdx.x;
+    const int64_t ntile = (n + 15) / 16;
+    const int64_t cbeg = 16 * (ntile * w / W);
+    const int64_t cend = std::min<int64_t>(n, 16 * (ntile * (w + 1) / W));
+    const int lj = lane & 15;
+    double f_acc[J];
+    int nnz_acc[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) { f_acc[jb] = 0.0; nnz_acc[jb] = 0; }
+    const float* xcol[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * kT) {
+        const int64_t left = cend - c0;
+        if (left > 48) x3_chunk<4, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 32) x3_chunk<3, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else if (left > 16) x3_chunk<2, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+        else x3_chunk<1, J, D>(pp, c0, cend, xcol, Xil, f_acc, nnz_acc, S, act);
+    }
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) {
+        double f = f_acc[jb];
+        int c = nnz_acc[jb];
+        f += __shfl_xor(f, 16, 64);
+        c += __shfl_xor(c, 16, 64);
+        f += __shfl_xor(f, 32, 64);
+        c += __shfl_xor(c, 32, 64);
+        const int comp = 16 * jb + lj;
+        if (lane < 16 && comp < m) {
+            fpart[(int64_t)comp * W + w] = f;
+            nnzpart[(int64_t)comp * W + w] = c;
+        }
+    }
+}
+
+hipError_t launch_corr_x3(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                          float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st) {
+    const dim3 grid(pl.corr_grid), block(64);
+#define GPSPCA_X3(JJ, DD) \
+    hipLaunchKernelGGL((k_corr_x3<JJ, DD>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
+                       nnzpart, ctrl)
+    const bool d3 = pl.rd_depth == 3;
+    if (pl.m <= 16) {
+        if (d3) GPSPCA_X3(1, 3); else GPSPCA_X3(1, 2);
+    } else if (pl.m <= 32) {
+        if (d3) GPSPCA_X3(2, 3); else GPSPCA_X3(2, 2);
+    } else {
+        if (d3) GPSPCA_X3(4, 3); else GPSPCA_X3(4, 2);
+    }
+#undef GPSPCA_X3
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // k_corr_mv: the same matrix-core correlation for m <= 16, but A is staged
 // through registers instead of LDS DMA: one wave per SIMD can hold three
 // 16 KB stages in flight (A streamed as contiguous 512-byte column segments,

@@ -36,24 +36,60 @@ __device__ __forceinline__ void wave_best(double& v, int64_t& i) {
     }
 }
 
+// Ranges of at most CAP pairs per thread are read once into registers (all
+// loads issued together); longer ones are re-read every round.
+template <int CAP>
 __device__ void topm_block(int m, int64_t b, int64_t e, const double* __restrict__ val,
                            const int64_t* __restrict__ idx, double* chosen_v, int64_t* chosen_i,
                            double* rv, int64_t* ri) {
     const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6, nw = (nt + 63) >> 6;
+    const bool in_regs = (e - b) <= (int64_t)CAP * nt;
+    double pv[CAP];
+    int64_t pi[CAP];
+    if (in_regs) {
+#pragma unroll
+        for (int u = 0; u < CAP; ++u) {
+            pv[u] = -INFINITY;
+            pi[u] = -1;
+        }
+        if (e > b) {
+#pragma unroll
+            for (int u = 0; u < CAP; ++u) {
+                const int64_t i = b + t + (int64_t)u * nt;
+                const int64_t ic = i < e ? i : e - 1;   // in range; dropped below when i >= e
+                const int64_t ci = idx ? idx[ic] : ic;
+                const double cv = val[ic];
+                pv[u] = (i < e && ci >= 0) ? cv : -INFINITY;
+                pi[u] = (i < e) ? ci : -1;
+            }
+        }
+    }
     double lv = INFINITY;   // the previous round's winner (none yet: every pair qualifies)
     int64_t li = -1;
     for (int r = 0; r < m; ++r) {
         double bv = -INFINITY;
         int64_t bi = -1;
-        for (int64_t i = b + t; i < e; i += nt) {
-            const int64_t ci = idx ? idx[i] : i;
-            if (ci < 0) continue;
-            const double cv = val[i];
-            // after the previous winner in the order, and better than the best so far
-            const bool after = (r == 0) || better(lv, li, cv, ci);
-            if (after && better(cv, ci, bv, bi)) {
-                bv = cv;
-                bi = ci;
+        if (in_regs) {
+#pragma unroll
+            for (int u = 0; u < CAP; ++u) {
+                if (pi[u] < 0) continue;
+                const bool after = (r == 0) || better(lv, li, pv[u], pi[u]);
+                if (after && better(pv[u], pi[u], bv, bi)) {
+                    bv = pv[u];
+                    bi = pi[u];
+                }
+            }
+        } else {
+            for (int64_t i = b + t; i < e; i += nt) {
+                const int64_t ci = idx ? idx[i] : i;
+                if (ci < 0) continue;
+                const double cv = val[i];
+                // after the previous winner in the order, and better than the best so far
+                const bool after = (r == 0) || better(lv, li, cv, ci);
+                if (after && better(cv, ci, bv, bi)) {
+                    bv = cv;
+                    bi = ci;
+                }
             }
         }
         wave_best(bv, bi);
@@ -95,21 +131,22 @@ __global__ __launch_bounds__(256) void k_topm_local(int64_t n, int m, const doub
     __shared__ double chv[kMaxM];
     __shared__ int64_t chi[kMaxM];
     const int64_t b = n * blockIdx.x / gridDim.x, e = n * (blockIdx.x + 1) / gridDim.x;
-    topm_block(m, b, e, norms, nullptr, chv, chi, rv, ri);
+    topm_block<8>(m, b, e, norms, nullptr, chv, chi, rv, ri);
     for (int r = threadIdx.x; r < m; r += blockDim.x) {
         cv[(size_t)blockIdx.x * m + r] = chv[r];
         ci[(size_t)blockIdx.x * m + r] = chi[r];
     }
 }
 
-__global__ __launch_bounds__(256) void k_topm_final(int ncand, int m, const double* __restrict__ cv,
-                                                    const int64_t* __restrict__ ci,
-                                                    int64_t* __restrict__ idx) {
-    __shared__ double rv[256];
-    __shared__ int64_t ri[256];
+// 1024 threads: the candidates (at most 256 workgroups x 64) fit 16 per thread.
+__global__ __launch_bounds__(1024) void k_topm_final(int ncand, int m, const double* __restrict__ cv,
+                                                     const int64_t* __restrict__ ci,
+                                                     int64_t* __restrict__ idx) {
+    __shared__ double rv[16];
+    __shared__ int64_t ri[16];
     __shared__ double chv[kMaxM];
     __shared__ int64_t chi[kMaxM];
-    topm_block(m, 0, ncand, cv, ci, chv, chi, rv, ri);
+    topm_block<16>(m, 0, ncand, cv, ci, chv, chi, rv, ri);
     for (int r = threadIdx.x; r < m; r += blockDim.x) idx[r] = chi[r];
 }
 
@@ -117,7 +154,7 @@ hipError_t launch_topm(const Plan& pl, const double* norms, double* cand_v, int6
                        int64_t* idx, hipStream_t st) {
     hipLaunchKernelGGL(k_topm_local, dim3(pl.topm_grid), dim3(256), 0, st, pl.n, pl.m, norms,
                        cand_v, cand_i);
-    hipLaunchKernelGGL(k_topm_final, dim3(1), dim3(256), 0, st, pl.topm_grid * pl.m, pl.m,
+    hipLaunchKernelGGL(k_topm_final, dim3(1), dim3(1024), 0, st, pl.topm_grid * pl.m, pl.m,
                        cand_v, cand_i, idx);
     return hipGetLastError();
 }
@@ -147,69 +184,88 @@ hipError_t launch_gather(const Plan& pl, const PassParams& pp, const int64_t* id
     return hipGetLastError();
 }
 
-// Support words and per-block sums of s^2 per component.
+// Support words and per-block sums of s^2 per component.  S is row-major
+// (n x m): thread t takes component t % m of word blockIdx.x * (256 / m) + t / m,
+// so each load instruction of a wave reads consecutive components of a row.
 __global__ __launch_bounds__(256) void k_fin_support(int64_t n, int m, const float* __restrict__ S,
                                                      uint32_t* __restrict__ support,
                                                      double* __restrict__ fin) {
     __shared__ double red[256];
     const int t = threadIdx.x;
+    const int wpb = 256 / m, j = t % m, k = t / m;
     const int64_t nw = (n + 31) / 32;
-    const int64_t w = (int64_t)blockIdx.x * 256 + t;
-    for (int j = 0; j < m; ++j) {
-        double ss = 0.0;
-        if (w < nw) {
-            uint32_t bits = 0;
-            for (int b = 0; b < 32; ++b) {
-                const int64_t i = w * 32 + b;
-                if (i < n) {
-                    const float s = S[i * m + j];
-                    bits |= (s != 0.f ? 1u : 0u) << b;
-                    ss += (double)s * (double)s;
-                }
-            }
-            if (support) support[(size_t)j * nw + w] = bits;
+    const int64_t w = (int64_t)blockIdx.x * wpb + k;
+    double ss = 0.0;
+    if (k < wpb && w < nw) {
+        uint32_t bits = 0;
+        const int64_t i0 = w * 32;
+        const int cnt = (int)((n - i0) < 32 ? (n - i0) : 32);
+        for (int b = 0; b < cnt; ++b) {
+            const float s = S[(i0 + b) * m + j];
+            bits |= (s != 0.f ? 1u : 0u) << b;
+            ss += (double)s * (double)s;
         }
-        red[t] = ss;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (t < h) red[t] += red[t + h];
-            __syncthreads();
-        }
-        if (t == 0) fin[(size_t)blockIdx.x * m + j] = red[0];
+        if (support) support[(size_t)j * nw + w] = bits;
+    }
+    red[t] = ss;
+    __syncthreads();
+    // per component, a fixed pairwise tree over the block's words
+    for (int h = 1; h < wpb; h <<= 1) {
+        if (k < wpb && (k & (2 * h - 1)) == 0 && k + h < wpb) red[t] += red[t + h * m];
         __syncthreads();
     }
+    if (k == 0) fin[(size_t)blockIdx.x * m + j] = red[t];
 }
 
-__global__ void k_fin_norm(int m, int nblk, const double* __restrict__ fin,
-                           double* __restrict__ invn) {
-    const int j = threadIdx.x;
-    if (j >= m) return;
+// 1 / ||s_j|| from the per-block sums; grid (components), 256 threads: strided
+// per-thread sums in block order, then a fixed tree.
+__global__ __launch_bounds__(256) void k_fin_norm(int m, int nblk, const double* __restrict__ fin,
+                                                  double* __restrict__ invn) {
+    __shared__ double red[256];
+    const int j = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += fin[(size_t)b * m + j];
-    invn[j] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int b = t; b < nblk; b += 256) s += fin[(size_t)b * m + j];
+    red[t] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) invn[j] = red[0] > 0.0 ? 1.0 / sqrt(red[0]) : 0.0;
 }
 
-// Z[i + j*n] = S[i*m + j] * invn[j]  (invn == nullptr: plain transpose)
-__global__ void k_fin_z(int64_t n, int m, const float* __restrict__ S,
-                        const double* __restrict__ invn, float* __restrict__ Z) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n * m) return;
-    const int j = (int)(e / n);
-    const int64_t i = e % n;
-    const float s = S[i * m + j];
-    Z[e] = invn ? (float)((double)s * invn[j]) : s;
+// Z[i + j*n] = S[i*m + j] * invn[j]  (invn == nullptr: plain transpose).  A
+// workgroup transposes 64 rows of S through LDS: rows are read as one
+// contiguous block, and each column j of Z is written as 64 consecutive
+// values.
+__global__ __launch_bounds__(256) void k_fin_z(int64_t n, int m, const float* __restrict__ S,
+                                               const double* __restrict__ invn,
+                                               float* __restrict__ Z) {
+    __shared__ float tile[64 * (kMaxM + 1)];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int rows = (int)((n - i0) < 64 ? (n - i0) : 64);
+    const int ld = m + 1;
+    for (int e = t; e < rows * m; e += 256) tile[(e / m) * ld + e % m] = S[i0 * m + e];
+    __syncthreads();
+    for (int e = t; e < 64 * m; e += 256) {
+        const int j = e >> 6, ii = e & 63;
+        if (ii < rows) {
+            const float s = tile[ii * ld + j];
+            Z[(size_t)j * n + i0 + ii] = invn ? (float)((double)s * invn[j]) : s;
+        }
+    }
 }
 
 hipError_t launch_finalize(const Plan& pl, const float* S, double* fin, double* invn, float* Z,
                            uint32_t* support, hipStream_t st) {
-    const int64_t ne = pl.n * pl.m;
     if (invn) {
         hipLaunchKernelGGL(k_fin_support, dim3(pl.fin_grid), dim3(256), 0, st, pl.n, pl.m, S,
                            support, fin);
-        hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(64), 0, st, pl.m, pl.fin_grid, fin, invn);
+        hipLaunchKernelGGL(k_fin_norm, dim3(pl.m), dim3(256), 0, st, pl.m, pl.fin_grid, fin, invn);
     }
     if (Z)
-        hipLaunchKernelGGL(k_fin_z, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pl.n,
+        hipLaunchKernelGGL(k_fin_z, dim3((unsigned)((pl.n + 63) / 64)), dim3(256), 0, st, pl.n,
                            pl.m, S, invn, Z);
     return hipGetLastError();
 }

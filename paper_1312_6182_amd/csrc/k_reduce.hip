@@ -557,13 +557,25 @@ hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* tou
 // a (msz x msz, leading dim LDM, LDS) is diagonalized in place; v receives the
 // eigenvectors (columns).  With `warm`, v already holds an orthogonal V0 and a
 // holds V0^T M V0: the rotations continue from there (V <- V0 J ...).
-// A step computes its rotations (one thread per pair), then applies
-// A <- R A R^T as independent 2 x 2 blocks (rows of pair k1, columns of pair
-// k2: rows first, then columns, each block by one thread) and V <- V R^T, so
-// every entry is read and written once per step.  The pairs of a step follow
-// from the step index alone, so each thread computes its indices in
-// registers and issues its rotation and matrix loads together (one LDS round
-// trip per item).
+//
+// Layout: during a sweep the matrix is kept in slot coordinates.  With mm =
+// msz rounded up to even (an odd size gets a zero padding row and column that
+// never rotates), step r of the round-robin schedule pairs slot k with slot
+// mm - 1 - k, and slot s holds index 0 (s = 0) or 1 + (s - 1 + r) mod (mm - 1).
+// Moving to step r + 1 then shifts the contents of every slot s >= 2 to s - 1
+// and slot 1 to mm - 1, the same permutation at every step, so each step reads
+// its pairs at fixed addresses and writes the rotated entries straight to
+// their places for the next step: every thread's LDS offsets are computed once
+// for the whole eigensolve.  A sweep is mm - 1 steps, after which the slots
+// are back in index order.  Only one entry of each symmetric pair is kept
+// during the sweeps (the one whose row slot belongs to the pair of lower
+// number, or the upper one within a pair); the other is filled in at the end.
+//
+// A step: threads k < mm/2 compute the rotation of pair k while every thread
+// loads its items (2 x 2 blocks of A over a pair of pairs, upper half only,
+// and rows of V over one pair); then each item applies its rotations
+// (A <- R A R^T, V <- V R^T) and stores the results at the next step's slots.
+//
 // A pair is rotated while |a_pq| > 2^-16 sqrt(|a_pp a_qq|) (the relative test,
 // which keeps the small eigenvalues of a graded matrix accurate); the inverse
 // square root is then built with the first-order correction of the remaining
@@ -572,32 +584,32 @@ hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* tou
 // set to zero exactly, as the rotation makes it: computed, it would keep a
 // rounding residue of about 2^-52 max(a_pp, a_qq), which the relative test
 // would chase without end when a_pp / a_qq is large.
-// Executed by the whole workgroup.
-__device__ __forceinline__ int rr_pos(int i, int r, int mm) {
-    // slot i of the round-robin schedule at step r (slot 0 stays in place)
-    if (i == 0) return 0;
-    int x = i - 1 + r;
-    x = (x >= mm - 1) ? x - (mm - 1) : x;
-    return 1 + x;
-}
-
-__device__ __forceinline__ void rr_pair(int k, int r, int mm, int& pp, int& qq) {
-    const int a = rr_pos(k, r, mm), b = rr_pos(mm - 1 - k, r, mm);
-    pp = a < b ? a : b;
-    qq = a < b ? b : a;
-}
+// a and v need mm rows.  Executed by the whole workgroup.
 
 // Items per thread of a Jacobi step; the kernels that call jacobi_eig launch
 // at least jacobi_threads(m) threads.
 constexpr int kItems = 3;
 
-// Threads for an m x m Jacobi step: m > 32: 1024 (32 x 32 blocks + 64 x 32 rows
-// of V = 3072 items); m > 16: 512 (at most 768); else 256 (at most 192).
+// Threads for an m x m Jacobi step: m > 32: 1024 (at most 32 x 33 / 2 blocks
+// of A + 64 x 32 rows of V = 2576 items); m > 16: 512 (at most 648); else 256
+// (at most 164).
 static int jacobi_threads(int m) { return m > 32 ? 1024 : m > 16 ? 512 : 256; }
 
-__device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
-                           bool warm = false) {
-    (void)prs;
+__device__ __forceinline__ int jac_pidx(int s, int mm) { return s < mm / 2 ? s : mm - 1 - s; }
+
+// slot that receives slot s's contents at the next step
+__device__ __forceinline__ int jac_next(int s, int mm) {
+    return s == 0 ? 0 : (s == 1 ? mm - 1 : s - 1);
+}
+
+// offset of the kept entry of the symmetric pair (u, w)
+__device__ __forceinline__ int jac_kept(int u, int w, int mm) {
+    const int pu = jac_pidx(u, mm), pw = jac_pidx(w, mm);
+    const bool swap = pu > pw || (pu == pw && u > w);
+    return swap ? w * LDM + u : u * LDM + w;
+}
+
+__device__ void jacobi_eig(double* a, double* v, int msz, double* rot, bool warm = false) {
     const int t = threadIdx.x, nt = blockDim.x;
     // |a_pq| > 2^-16 sqrt(|a_pp a_qq|), tested squared (no square root)
     constexpr double kTol2 = 2.3283064365386963e-10;  // 2^-32
@@ -607,39 +619,83 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
             v[i * LDM + j] = (i == j) ? 1.0 : 0.0;
         }
     }
-    __syncthreads();
-    if (msz < 2) return;
-    const int mm = msz + (msz & 1);
-    const int half = mm / 2;
-    const int nblk = half * half, nitem = nblk + msz * half;
-    // items: 2 x 2 blocks of A (e < nblk: row pair ik1, column pair ik2) and
-    // rows of V (pair ik2, row irow; ik1 = -1); a pair whose second index is
-    // the padding position (odd msz) has a single row / column.  Thread t owns
-    // items t, t + nt, ... (at most kItems: blockDim.x is chosen for that).
-    int ik1[kItems], ik2[kItems], irow[kItems];
-    const int nmine = (t < nitem) ? (nitem - t + nt - 1) / nt : 0;
+    if (msz < 2) {
+        __syncthreads();
+        return;
+    }
+    const int mm = msz + (msz & 1), half = mm / 2;
+    if (msz & 1) {
+        for (int e = t; e < mm; e += nt) {
+            a[msz * LDM + e] = 0.0;
+            a[e * LDM + msz] = 0.0;
+        }
+        for (int e = t; e < msz; e += nt) v[e * LDM + msz] = 0.0;
+    }
+    // items: upper blocks (k1 <= k2) of A, then rows of V; thread t owns
+    // items t, t + nt, ... (at most kItems: blockDim.x is chosen for that)
+    const int nA = half * (half + 1) / 2, nitem = nA + msz * half;
+    int kind[kItems];     // 0 none, 1 block of A, 2 diagonal block of A, 3 row of V
+    int rk1[kItems], rk2[kItems];
+    int ld[kItems][4], sto[kItems][4];
 #pragma unroll
     for (int u = 0; u < kItems; ++u) {
         const int e = t + u * nt;
-        if (e < nblk) {
-            ik1[u] = e / half;
-            ik2[u] = e % half;
-            irow[u] = 0;
+        kind[u] = 0;
+        rk1[u] = rk2[u] = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ld[u][q] = sto[u][q] = 0;
+        if (e >= nitem) continue;
+        if (e < nA) {
+            int k1 = 0, rem = e;
+            while (rem >= half - k1) {
+                rem -= half - k1;
+                ++k1;
+            }
+            const int k2 = k1 + rem;
+            const int P1 = k1, Q1 = mm - 1 - k1, P2 = k2, Q2 = mm - 1 - k2;
+            const int nP1 = jac_next(P1, mm), nQ1 = jac_next(Q1, mm);
+            const int nP2 = jac_next(P2, mm), nQ2 = jac_next(Q2, mm);
+            rk1[u] = k1;
+            rk2[u] = k2;
+            if (k1 < k2) {
+                kind[u] = 1;
+                ld[u][0] = P1 * LDM + P2;
+                ld[u][1] = P1 * LDM + Q2;
+                ld[u][2] = Q1 * LDM + P2;
+                ld[u][3] = Q1 * LDM + Q2;
+                sto[u][0] = jac_kept(nP1, nP2, mm);
+                sto[u][1] = jac_kept(nP1, nQ2, mm);
+                sto[u][2] = jac_kept(nQ1, nP2, mm);
+                sto[u][3] = jac_kept(nQ1, nQ2, mm);
+            } else {
+                kind[u] = 2;
+                ld[u][0] = P1 * LDM + P1;
+                ld[u][1] = P1 * LDM + Q1;
+                ld[u][3] = Q1 * LDM + Q1;
+                sto[u][0] = jac_kept(nP1, nP1, mm);
+                sto[u][1] = jac_kept(nP1, nQ1, mm);
+                sto[u][3] = jac_kept(nQ1, nQ1, mm);
+            }
         } else {
-            const int f = e - nblk;
-            ik1[u] = -1;
-            ik2[u] = f / msz;
-            irow[u] = f % msz;
+            const int f = e - nA, row = f % msz, k = f / msz;
+            const int P = k, Q = mm - 1 - k;
+            kind[u] = 3;
+            rk1[u] = k;
+            ld[u][0] = row * LDM + P;
+            ld[u][1] = row * LDM + Q;
+            sto[u][0] = row * LDM + jac_next(P, mm);
+            sto[u][1] = row * LDM + jac_next(Q, mm);
         }
     }
+    __syncthreads();
     for (int sweep = 0; sweep < 40; ++sweep) {
         // a sweep that would apply no rotation ends the iteration.  Every pair
-        // is tested at once before the sweep: if none qualifies, no step of the
-        // sweep would rotate (nothing changes), so the sweep is skipped.
+        // is tested at once before the sweep (the slots are in index order
+        // here): if none qualifies, no step of the sweep would rotate.
         int need = 0;
         for (int e = t; e < msz * msz; e += nt) {
             const int i = e / msz, j = e % msz;
-            if (i < j) {
+            if (i != j && jac_kept(i, j, mm) == i * LDM + j) {
                 const double apq = a[i * LDM + j];
                 need |= (apq * apq > kTol2 * fabs(a[i * LDM + i] * a[j * LDM + j]) &&
                          fabs(apq) > 1e-300) ? 1 : 0;
@@ -647,92 +703,78 @@ __device__ void jacobi_eig(double* a, double* v, int msz, double* rot, int* prs,
         }
         if (!__syncthreads_or(need)) break;
         for (int r = 0; r < mm - 1; ++r) {
+            // phase 1: the rotations of this step, and every item's loads
             if (t < half) {
-                int pp, qq;
-                rr_pair(t, r, mm, pp, qq);
-                double c = 1.0, s = 0.0;
-                if (qq < msz) {
-                    const double apq = a[pp * LDM + qq];
-                    const double app = a[pp * LDM + pp], aqq = a[qq * LDM + qq];
-                    if (apq * apq > kTol2 * fabs(app * aqq) && fabs(apq) > 1e-300) {
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = rsqrt(1.0 + tt * tt);
-                        s = tt * c;
-                    }
+                const int P = t, Q = mm - 1 - t;
+                const double apq = a[P * LDM + Q];
+                const double app = a[P * LDM + P], aqq = a[Q * LDM + Q];
+                double c = 1.0, sn = 0.0;
+                if (apq * apq > kTol2 * fabs(app * aqq) && fabs(apq) > 1e-300) {
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = rsqrt(1.0 + tt * tt);
+                    sn = tt * c;
                 }
                 rot[2 * t] = c;
-                rot[2 * t + 1] = s;
+                rot[2 * t + 1] = sn;
+            }
+            double x[kItems][4];
+#pragma unroll
+            for (int u = 0; u < kItems; ++u) {
+                x[u][0] = x[u][1] = x[u][2] = x[u][3] = 0.0;
+                if (kind[u] == 1) {
+                    x[u][0] = a[ld[u][0]];
+                    x[u][1] = a[ld[u][1]];
+                    x[u][2] = a[ld[u][2]];
+                    x[u][3] = a[ld[u][3]];
+                } else if (kind[u] == 2) {
+                    x[u][0] = a[ld[u][0]];
+                    x[u][1] = a[ld[u][1]];
+                    x[u][3] = a[ld[u][3]];
+                } else if (kind[u] == 3) {
+                    x[u][0] = v[ld[u][0]];
+                    x[u][1] = v[ld[u][1]];
+                }
             }
             __syncthreads();
-            // this thread's items (fixed for the whole eigensolve): every load
-            // of a step is issued before the first use
-            double rc[kItems][2][2];   // (c, s) of the item's pairs
-            double x[kItems][4];
-            int ip[kItems][4];         // p1, q1, p2, q2 (A block) or pp, qq, -, - (V row)
+            // phase 2: rotate and store at the next step's slots
 #pragma unroll
             for (int u = 0; u < kItems; ++u) {
-                if (u >= nmine) break;
-                if (ik1[u] >= 0) {
-                    int p1, q1, p2, q2;
-                    rr_pair(ik1[u], r, mm, p1, q1);
-                    rr_pair(ik2[u], r, mm, p2, q2);
-                    ip[u][0] = p1; ip[u][1] = q1; ip[u][2] = p2; ip[u][3] = q2;
-                    const int q1c = q1 < msz ? q1 : p1, q2c = q2 < msz ? q2 : p2;
-                    rc[u][0][0] = rot[2 * ik1[u]];
-                    rc[u][0][1] = rot[2 * ik1[u] + 1];
-                    rc[u][1][0] = rot[2 * ik2[u]];
-                    rc[u][1][1] = rot[2 * ik2[u] + 1];
-                    x[u][0] = a[p1 * LDM + p2];
-                    x[u][1] = a[p1 * LDM + q2c];
-                    x[u][2] = a[q1c * LDM + p2];
-                    x[u][3] = a[q1c * LDM + q2c];
-                } else {
-                    int pp, qq;
-                    rr_pair(ik2[u], r, mm, pp, qq);
-                    const int qc = qq < msz ? qq : pp;
-                    ip[u][0] = pp; ip[u][1] = qq;
-                    rc[u][0][0] = rot[2 * ik2[u]];
-                    rc[u][0][1] = rot[2 * ik2[u] + 1];
-                    x[u][0] = v[irow[u] * LDM + pp];
-                    x[u][1] = v[irow[u] * LDM + qc];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kItems; ++u) {
-                if (u >= nmine) break;
-                if (ik1[u] >= 0) {
-                    const int p1 = ip[u][0], q1 = ip[u][1], p2 = ip[u][2], q2 = ip[u][3];
-                    const double c1 = rc[u][0][0], s1 = rc[u][0][1];
-                    const double c2 = rc[u][1][0], s2 = rc[u][1][1];
-                    if (s1 == 0.0 && s2 == 0.0) continue;   // both identity (c = 1)
-                    const bool h1 = q1 < msz, h2 = q2 < msz;
-                    const double x00 = x[u][0];
-                    const double x01 = h2 ? x[u][1] : 0.0;
-                    const double x10 = h1 ? x[u][2] : 0.0;
-                    const double x11 = (h1 && h2) ? x[u][3] : 0.0;
-                    // rows
-                    const double r00 = c1 * x00 - s1 * x10, r01 = c1 * x01 - s1 * x11;
-                    const double r10 = s1 * x00 + c1 * x10, r11 = s1 * x01 + c1 * x11;
-                    // columns; the diagonal block of a rotated pair has a zero
-                    // off-diagonal by construction
-                    const bool zq = (ik1[u] == ik2[u]);
-                    a[p1 * LDM + p2] = c2 * r00 - s2 * r01;
-                    if (h2) a[p1 * LDM + q2] = zq ? 0.0 : s2 * r00 + c2 * r01;
-                    if (h1) a[q1 * LDM + p2] = zq ? 0.0 : c2 * r10 - s2 * r11;
-                    if (h1 && h2) a[q1 * LDM + q2] = s2 * r10 + c2 * r11;
-                } else {
-                    const int pp = ip[u][0], qq = ip[u][1];
-                    const double c = rc[u][0][0], s = rc[u][0][1];
-                    if (qq >= msz || s == 0.0) continue;
+                if (kind[u] == 0) continue;
+                const double c1 = rot[2 * rk1[u]], s1 = rot[2 * rk1[u] + 1];
+                if (kind[u] == 3) {
                     const double vp = x[u][0], vq = x[u][1];
-                    v[irow[u] * LDM + pp] = c * vp - s * vq;
-                    v[irow[u] * LDM + qq] = s * vp + c * vq;
+                    v[sto[u][0]] = c1 * vp - s1 * vq;
+                    v[sto[u][1]] = s1 * vp + c1 * vq;
+                    continue;
                 }
+                const double c2 = rot[2 * rk2[u]], s2 = rot[2 * rk2[u] + 1];
+                const double x00 = x[u][0], x01 = x[u][1], x11 = x[u][3];
+                const double x10 = (kind[u] == 2) ? x01 : x[u][2];
+                // rows
+                const double r00 = c1 * x00 - s1 * x10, r01 = c1 * x01 - s1 * x11;
+                const double r10 = s1 * x00 + c1 * x10, r11 = s1 * x01 + c1 * x11;
+                // columns
+                a[sto[u][0]] = c2 * r00 - s2 * r01;
+                if (kind[u] == 1) {
+                    a[sto[u][1]] = s2 * r00 + c2 * r01;
+                    a[sto[u][2]] = c2 * r10 - s2 * r11;
+                } else {
+                    // the rotated pair's off-diagonal is zero by construction
+                    a[sto[u][1]] = (s1 != 0.0) ? 0.0 : x01;
+                }
+                a[sto[u][3]] = s2 * r10 + c2 * r11;
             }
             __syncthreads();
         }
     }
+    // fill in the other entry of every symmetric pair
+    for (int e = t; e < msz * msz; e += nt) {
+        const int i = e / msz, j = e % msz;
+        const int kp = jac_kept(i, j, mm);
+        if (kp != i * LDM + j) a[i * LDM + j] = a[kp];
+    }
+    __syncthreads();
 }
 
 // C = op(A) op(B) for n x n matrices in LDS (leading dim LDM), op(X) = X or
@@ -856,7 +898,6 @@ __device__ __forceinline__ void slice_sum(const double* __restrict__ fp,
 
 struct StopShared {
     double rot[kMaxM];
-    int prs[kMaxM];
     double lam[kMaxM];
     double fj[kMaxM];
     int nj[kMaxM];
@@ -892,7 +933,7 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
         lds_gemm<false, false>(nl, A0, A1, A2);
         lds_gemm<true, false>(nl, A1, A2, A0);
     }
-    jacobi_eig(A0, A1, nl, ss.rot, ss.prs, warm);
+    jacobi_eig(A0, A1, nl, ss.rot, warm);
 
     if (nd == 0) {
         for (int e = t; e < nl * nl; e += nt) {
@@ -943,7 +984,7 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
             A0[i * LDM + j] = A1[i * LDM + j];
         }
         __syncthreads();
-        jacobi_eig(A0, A1, nd, ss.rot, ss.prs);
+        jacobi_eig(A0, A1, nd, ss.rot);
         inv_sqrt_from_eig(A0, A1, A2, nd, ss.lam, &ss.rankdef);
         // Omega[L,D] = -(W_L C) W_D ; Psi[D,D] = W_D
         double* tmp = A0;  // nl x nd product
@@ -1082,8 +1123,10 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
     __shared__ double red[1024];
     extern __shared__ double dyn[];
     double* A0 = dyn;
-    double* A1 = dyn + (size_t)m * LDM;
-    double* A2 = dyn + (size_t)2 * m * LDM;
+    // three matrices of m rows rounded up to even (jacobi_eig pads odd sizes)
+    const int mr = m + (m & 1);
+    double* A1 = dyn + (size_t)mr * LDM;
+    double* A2 = dyn + (size_t)2 * mr * LDM;
     const int t = threadIdx.x, nt = blockDim.x;
     const int k = ctrl->k;
     if (stop_rule(m, nwp, fpart, nnzpart, trace, fcomp, exact, ctrl, ss, m > 1 ? fsum : nullptr))
@@ -1165,7 +1208,7 @@ hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
     // threads: the Jacobi steps of m = 64 have 32 x 32 blocks plus 64 x 32 rotated pairs of V;
     // m = 1 needs no eigen-solver: one wave makes every barrier free, four write x
     const int threads = pl.m > 1 ? jacobi_threads(pl.m) : Xn ? 256 : 64;
-    const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
+    const size_t shm = (pl.m > 1) ? (size_t)3 * (pl.m + (pl.m & 1)) * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
@@ -1332,8 +1375,10 @@ __global__ void k_project(int m, double* __restrict__ coef, Ctrl* __restrict__ c
     __shared__ StopShared ss;
     extern __shared__ double dyn[];
     double* A0 = dyn;
-    double* A1 = dyn + (size_t)m * LDM;
-    double* A2 = dyn + (size_t)2 * m * LDM;
+    // three matrices of m rows rounded up to even (jacobi_eig pads odd sizes)
+    const int mr = m + (m & 1);
+    double* A1 = dyn + (size_t)mr * LDM;
+    double* A2 = dyn + (size_t)2 * mr * LDM;
     const int t = threadIdx.x, nt = blockDim.x, mm = m * m;
     if (m == 1) {
         if (t == 0) {
@@ -1352,7 +1397,7 @@ __global__ void k_project(int m, double* __restrict__ coef, Ctrl* __restrict__ c
         A0[i * LDM + j] = coef[2 * mm + e];
     }
     __syncthreads();
-    jacobi_eig(A0, A1, m, ss.rot, ss.prs);
+    jacobi_eig(A0, A1, m, ss.rot);
     inv_sqrt_from_eig(A0, A1, A2, m, ss.lam, &ss.rankdef);
     for (int e = t; e < mm; e += nt) {
         const int i = e / m, j = e % m;
@@ -1374,7 +1419,7 @@ hipError_t launch_project(const Plan& pl, const double* gram, double* coef, Ctrl
     hipError_t e = launch_gram_sum(pl, pl.m * pl.m, pl.gram_grid, gram, coef, ctrl, st);
     if (e != hipSuccess) return e;
     const int threads = jacobi_threads(pl.m);
-    const size_t shm = (pl.m > 1) ? (size_t)3 * pl.m * LDM * sizeof(double) : 0;
+    const size_t shm = (pl.m > 1) ? (size_t)3 * (pl.m + (pl.m & 1)) * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_project), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_project, dim3(1), dim3(threads), shm, st, pl.m, coef, ctrl);

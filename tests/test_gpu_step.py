@@ -98,12 +98,13 @@ def test_step_zero_gamma_dense_support(gpu, form):
     np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
 
 
-@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "rd", "rd128", "wg", "valu"])
+@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "rd", "rd128", "wg", "x3", "valu"])
 @pytest.mark.parametrize("form,m", [(O.BL1, 4), (O.BL0, 8)])
 def test_every_correlation_kernel(gpu, kernel, form, m, monkeypatch):
     """Force each block correlation kernel (registers-X, matrix cores through
-    registers, matrix cores through LDS DMA, plain vector ALU) on the same case:
-    one step and a 6-pass solve against the oracle."""
+    registers, matrix cores through LDS DMA, FP32 split into bfloat16 parts on
+    the bfloat16 matrix cores, plain vector ALU) on the same case: one step and
+    a 6-pass solve against the oracle."""
     monkeypatch.setenv("GPSPCA_CORR_KERNEL", kernel)
     p, n = 1003, 3001  # ragged row quad
     A32, _, _ = W.planted_block(p, n, 3, 23, k=40)
@@ -126,12 +127,17 @@ def test_every_correlation_kernel(gpu, kernel, form, m, monkeypatch):
     np.testing.assert_allclose(res.trace, rs["trace"], rtol=1e-5)
 
 
-@pytest.mark.parametrize("kernel", ["rd", "rd128"])
-@pytest.mark.parametrize("m,p,n", [(20, 1001, 2999), (40, 514, 1500), (16, 4097, 64)])
+@pytest.mark.parametrize("kernel", ["rd", "rd128", "x3", "x3-d3"])
+@pytest.mark.parametrize("m,p,n", [(20, 1001, 2999), (40, 514, 1500), (16, 4097, 64),
+                                   (64, 2003, 1203)])
 def test_register_direct_kernels_component_groups(gpu, kernel, m, p, n, monkeypatch):
-    """The register-direct matrix-core kernels with 2 and 4 component groups,
-    ragged rows and a matrix of only 4 tiles: one step against the oracle."""
-    monkeypatch.setenv("GPSPCA_CORR_KERNEL", kernel)
+    """The register-direct matrix-core kernels (FP32, and FP32 split into
+    bfloat16 parts with 2 or 3 stages in flight) with 1, 2 and 4 component
+    groups, ragged rows and a matrix of only 4 tiles: one step against the
+    oracle."""
+    monkeypatch.setenv("GPSPCA_CORR_KERNEL", kernel.split("-")[0])
+    if kernel.endswith("-d3"):
+        monkeypatch.setenv("GPSPCA_MFMA_STAGES", "3")
     print(f"\n[corr {kernel}] m={m} p={p} n={n}", flush=True)
     A32, _, _ = W.planted_block(p, n, 4, 90 + m, k=min(40, n // 4))
     A64 = A32.astype(np.float64)
@@ -144,6 +150,9 @@ def test_register_direct_kernels_component_groups(gpu, kernel, m, p, n, monkeypa
     ties = tie_mask(A64, X0, O.BL1, gamma, mu)
     S = out.S.cpu().numpy().astype(np.float64)
     np.testing.assert_array_equal((S != 0)[~ties], (ref["S"] != 0)[~ties])
+    # thresholded values within the FP32 band of the correlation
+    eb = corr_band(A64, X0) * mu[None, :]
+    assert np.all(np.abs(S - ref["S"]) <= eb + 1e-7 * np.abs(ref["S"]))
     assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
     np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
 
