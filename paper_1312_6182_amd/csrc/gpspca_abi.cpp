@@ -140,7 +140,7 @@ static Tune env_tune() {
         const std::string fk = f;
         t.kernel = fk == "mfma" ? kTuneMfma : fk == "vx" ? kTuneVx : fk == "valu" ? kTuneValu
                  : fk == "rd" ? kTuneRd : fk == "rd128" ? kTuneRd128 : fk == "wg" ? kTuneWg
-                 : fk == "x3" ? kTuneX3
+                 : fk == "x3" ? kTuneX3 : fk == "qw" ? kTuneQw
                  : fk == "mv" ? -1 : kTuneDefault;
     }
     if (const char* e = std::getenv("GPSPCA_MFMA_STAGES")) t.stages = std::atoi(e);
@@ -241,7 +241,18 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         else if (vx_ok && m <= 4) pl->use_vx = 1;
         else if (m > 32 && pl->vec4) pl->use_mfma = pl->use_x3 = 1;   // FP32 matrix cores are the bound
         else pl->use_mfma = pl->vec4;
-        if (pl->use_q) {
+        if (pl->use_q && tn.kernel != kTuneMfma) {
+            // 16/8-bit storage, four-wave workgroups sharing X (the default): one
+            // per CU.  Staging: 2 stages of up to 8 tiles per wave, 3 stages of
+            // 4 tiles (stages = 3), or for e4m3 2 stages of 4 tiles (stages = 2)
+            pl->use_qw = 1;
+            pl->corr_M = 16;
+            pl->mfma_stages = (tn.stages == 2 || tn.stages == 3) ? tn.stages : 8;
+            pl->waves_per_cu = 4;
+            const int64_t grid = std::min<int64_t>(ncu, cdiv(cdiv(A->n, 16), 4));
+            pl->corr_grid = (int)std::max<int64_t>(1, grid);
+            pl->nwave_part = pl->corr_grid * 4;
+        } else if (pl->use_q) {
             // 16/8-bit storage: bfloat16 matrix cores, one wavefront per workgroup
             pl->corr_M = 16;
             pl->mfma_stages = corr_q_stages(A->dtype, m, tn.stages);
@@ -380,6 +391,8 @@ static std::vector<Tune> tune_candidates(const gpspca_matrix* A, int m, int path
     c.push_back(Tune{kTuneDefault, 0, 0});
     const bool vec = ((A->lda & 3) == 0) && ((reinterpret_cast<uintptr_t>(A->data) & 15) == 0);
     if (A->dtype != GPSPCA_F32) {
+        c.push_back(Tune{kTuneQw, 3, 0});
+        if (A->dtype == GPSPCA_F8E4M3) c.push_back(Tune{kTuneQw, 2, 0});
         c.push_back(Tune{kTuneMfma, 2, 4});
         c.push_back(Tune{kTuneMfma, 3, 4});
         c.push_back(Tune{kTuneMfma, 8, 4});
@@ -582,6 +595,9 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
             GPSPCA_HIP(launch_corr_vx(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         else if (pl.use_mv)
             GPSPCA_HIP(launch_corr_mv(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
+        else if (pl.use_qw)
+            GPSPCA_HIP(launch_corr_qw(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
+                                      P.ctrl, st));
         else if (pl.use_q)
             GPSPCA_HIP(launch_corr_q(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
                                      P.ctrl, st));
@@ -749,6 +765,7 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
     tl.collect(pl.fused_m1 ? "k_pass_m1"
                            : pl.use_vx ? "k_corr_vx"
                            : pl.use_mv ? "k_corr_mv"
+                           : pl.use_qw ? "k_corr_qw"
                            : pl.use_q ? "k_corr_q"
                            : pl.use_x3 ? "k_corr_x3"
                            : pl.use_rd ? "k_corr_rd"
@@ -1307,6 +1324,7 @@ static std::string tune_text(const Plan& pl) {
                   : pl.use_x3 ? "k_corr_x3"
                   : pl.use_rd ? (pl.rd128 ? "k_corr_rd(128-byte lines)" : "k_corr_rd")
                   : pl.use_wg ? "k_corr_wg"
+                  : pl.use_qw ? "k_corr_qw"
                   : pl.use_q ? "k_corr_q" : pl.use_mfma ? "k_corr_mfma" : pl.use_mv ? "k_corr_mv"
                   : "k_corr";
     std::snprintf(b, sizeof(b), "%s stages=%d waves_per_cu=%d grid=%d", k,

@@ -58,7 +58,7 @@ struct PassParams {
 
 // A configuration of the correlation kernel: the autotuner's unit of choice.
 enum TuneKernel { kTuneDefault = 0, kTuneMfma = 1, kTuneVx = 2, kTuneValu = 3, kTuneRd = 4,
-                  kTuneWg = 5, kTuneRd128 = 6, kTuneX3 = 7 };
+                  kTuneWg = 5, kTuneRd128 = 6, kTuneX3 = 7, kTuneQw = 8 };
 struct Tune {
     int kernel;            // TuneKernel
     int stages;            // LDS stages (matrix-core kernels), 0 = default
@@ -90,6 +90,7 @@ struct Plan {
     int vec4;              // float4 loads of A are legal
     int dtype;             // storage of A (GPSPCA_F32 | BF16 | F8E4M3)
     int use_q;             // 16/8-bit storage: bfloat16 matrix-core correlation
+    int use_qw;            // ... by four-wave workgroups that share each X stage
     int restricted;        // frozen-support passes over a column list (VALU correlation)
     int use_mfma;          // block correlation on the matrix cores (LDS DMA staging)
     int mfma_stages;       // stages in flight of the matrix-core kernels (FP32 and 16/8-bit)
@@ -155,6 +156,10 @@ hipError_t launch_quantize(const float* A, int64_t lda, int p, int64_t n, int to
 int corr_q_stages(int dtype, int m, int want);
 int corr_q_blocks_per_cu(int dtype, int m, int stages);
 hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                         float* S,
+                         uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                         hipStream_t st);
+hipError_t launch_corr_qw(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
                          float* S,
                          uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                          hipStream_t st);

@@ -428,6 +428,287 @@ __global__ __launch_bounds__(64) void k_corr_q(PassParams pp, const float* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// k_corr_qw: k_corr_q with four waves per workgroup that stream the same row
+// stages in lockstep over their own columns and share each stage of X in
+// LDS.  X stays FP32 (its three bfloat16 parts are made at the operand), so
+// at 32 components a wave alone stages twice as many X bytes as e4m3 codes;
+// shared, each wave issues a quarter of the X instructions.  The workgroup
+// owns whole tiles of 16 columns; in each round every wave takes its share
+// (up to TMAX tiles) of the round's tiles, and every wave executes the same
+// barriers, including a wave with no tiles in a round (it still moves its
+// share of X).
+//   stage: per wave TMAX tiles x 8 slots of A (2 KB per tile), then X (XBlk
+//   per component block); per stage, wave w waits for its own DMAs, the
+//   barrier makes everyone's visible and frees the slot read in the last
+//   stage, then w issues its DMAs for the stage STAGES - 1 ahead.
+// ---------------------------------------------------------------------------
+template <int NT, int ST, int J, int STAGES, int TMAX>
+__device__ __forceinline__ void qw_round(const PassParams& pp, int64_t c0, int64_t cend,
+                                         uint32_t lbase, int wv, const float* const* xcol,
+                                         const float* __restrict__ Xil, double* f_acc,
+                                         int* nnz_acc, float* __restrict__ S,
+                                         uint8_t* __restrict__ act) {
+    int nact_l = 0;   // active columns written by this lane
+    constexpr int ES = (ST == kStBF16) ? 2 : 1;     // bytes per element
+    constexpr int EPS = 16 / ES;                     // rows per 16-byte slot
+    constexpr int XQ = 2 * EPS;                      // X row quads per stage (8 slots)
+    constexpr int XDMA = XQ / 4;                     // X DMA instructions per block
+    constexpr int XBlk = XQ * 16 * 16;               // X bytes per component block
+    constexpr int AW = TMAX * 2048;                  // A bytes per wave per stage
+    constexpr int StageBytes = 4 * AW + J * XBlk;
+    constexpr int ADMA = 2 * NT;                     // A DMA instructions (8 columns each)
+    constexpr int XW = J * XDMA / 4;                 // X DMA instructions per wave
+    static_assert((J * XDMA) % 4 == 0, "X instructions split over four waves");
+    constexpr int PER = ADMA + XW;
+    constexpr int G8 = EPS / 8;                      // 8-row operand groups per slot
+    const int lane = threadIdx.x & 63;
+    const int lj = lane & 15, lk = lane >> 4;
+    const int p = pp.p, m = pp.m;
+    const int nsf = p / EPS;                 // full slots per column
+    const int nst = (nsf + 7) / 8;           // stages
+    const int rows_main = nsf * EPS;
+    const int nxq = nsf * (EPS / 4);         // X row quads covered by full slots
+    const int nqx = pp.ldx >> 2;             // quads of the X buffers; the last is zero
+    const bool l0 = pp.l0 != 0;
+    const uint8_t* Ab = (ST == kStBF16) ? reinterpret_cast<const uint8_t*>(pp.Abf) : pp.Af8;
+    const int64_t colbytes = pp.lda * ES;
+
+    const uint8_t* acol[ADMA > 0 ? ADMA : 1];
+    int aslot[ADMA > 0 ? ADMA : 1];
+#pragma unroll
+    for (int i = 0; i < ADMA; ++i) {
+        const int L = 64 * i + lane;
+        const int cl = L >> 3;
+        aslot[i] = (L & 7) ^ ((cl >> 1) & 7);
+        int64_t col = c0 + cl;
+        col = (col < cend) ? col : cend - 1;
+        acol[i] = Ab + col * colbytes;
+    }
+    auto issue = [&](int st) {
+        const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+#pragma unroll
+        for (int i = 0; i < ADMA; ++i) {
+            int sl = 8 * st + aslot[i];
+            sl = (sl < nsf) ? sl : nsf - 1;
+            dma(acol[i] + 16 * sl, sb + wv * AW + 1024 * i);
+        }
+#pragma unroll
+        for (int u = 0; u < XW; ++u) {
+            const int idx = wv + 4 * u;          // instruction idx = XDMA jb + i
+            const int jb = idx / XDMA, i = idx % XDMA;
+            int q = XQ * st + 4 * i + lk;
+            q = (q < nxq) ? q : nqx - 1;
+            dma(Xil + ((size_t)(jb * nqx + q) * 16 + lj) * 4, sb + 4 * AW + XBlk * jb + 1024 * i);
+        }
+    };
+
+    f4q acc[NT > 0 ? NT : 1][J];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4q{0.f, 0.f, 0.f, 0.f};
+
+    // the previous round's last stage may still be read by other waves
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < STAGES - 1; ++s2)
+        if (s2 < nst) issue(s2);
+
+    for (int st = 0; st < nst; ++st) {
+        // own DMAs of stage st done: later stages issued so far are st+1 .. st+STAGES-2
+        const int later = (nst - 1 - st < STAGES - 2) ? nst - 1 - st : STAGES - 2;
+        if constexpr (STAGES >= 3) {
+            if (later >= 1) wait_vm<PER>();
+            else wait_vm<0>();
+        } else {
+            (void)later;
+            wait_vm<0>();
+        }
+        __syncthreads();
+        if (st + STAGES - 1 < nst) issue(st + STAGES - 1);
+        if constexpr (NT > 0) {
+            const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+            const uint32_t sa = sb + wv * AW, sx = sb + 4 * AW;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int slot = 4 * h + lk;
+                f4q araw[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) araw[t] = lds16(sa + q_slot(16 * t + lj, slot));
+                f4q xr[J][EPS / 4];
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+                    for (int u = 0; u < EPS / 4; ++u)
+                        xr[jb][u] = lds16(sx + XBlk * jb +
+                                          16u * (uint32_t)(((EPS / 4) * slot + u) * 16 + lj));
+                wait_lgkm();
+#pragma unroll
+                for (int t = 0; t < NT; ++t) tie(araw[t]);
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+#pragma unroll
+                    for (int u = 0; u < EPS / 4; ++u) tie(xr[jb][u]);
+#pragma unroll
+                for (int g = 0; g < G8; ++g) {
+                    bf8q xh[J], xm[J], xl[J];
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb) {
+                        float xv[8];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            xv[e] = xr[jb][2 * g][e];
+                            xv[4 + e] = xr[jb][2 * g + 1][e];
+                        }
+                        split3(xv, xh[jb], xm[jb], xl[jb]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        bf8q aop;
+                        if constexpr (ST == kStBF16) {
+                            aop = __builtin_bit_cast(bf8q, araw[t]);
+                        } else {
+                            const u4q wv4 = __builtin_bit_cast(u4q, araw[t]);
+                            aop = widen8(wv4[2 * g], wv4[2 * g + 1]);
+                        }
+#pragma unroll
+                        for (int jb = 0; jb < J; ++jb) {
+                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xh[jb], acc[t][jb], 0, 0, 0);
+                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xm[jb], acc[t][jb], 0, 0, 0);
+                            acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, xl[jb], acc[t][jb], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (NT > 0) {
+        // ragged tail rows rows_main .. p-1 (fewer than one slot), FP32 FMA
+        if (rows_main < p) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int64_t col = c0 + 16 * t + 4 * lk + v;
+                    col = (col < cend) ? col : cend - 1;
+                    const uint8_t* ac = Ab + col * colbytes;
+                    for (int r = rows_main; r < p; ++r) {
+                        const float a = (ST == kStBF16)
+                                            ? bf16_value(reinterpret_cast<const uint16_t*>(ac)[r])
+                                            : e4m3_value(ac[r]);
+#pragma unroll
+                        for (int jb = 0; jb < J; ++jb)
+                            acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
+                    }
+                }
+        }
+        // scale, threshold, S, activity flags
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t col = c0 + 16 * t + 4 * lk + v;
+                const bool cvalid = col < cend;
+                const float sc = cvalid ? column_scale(pp, col) : 1.0f;
+                bool any = false;
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb) {
+                    const int comp = 16 * jb + lj;
+                    if (cvalid && comp < m) {
+                        float s;
+                        double fv;
+                        const bool a = thresh_q(l0, pp.mu[comp], pp.gam[comp], sc * acc[t][jb][v],
+                                                s, fv);
+                        S[col * m + comp] = s;
+                        if (a) {
+                            f_acc[jb] += fv;
+                            nnz_acc[jb] += 1;
+                            any = true;
+                        }
+                    }
+                }
+                const uint64_t bal = __ballot(any);
+                if (cvalid && lj == 0) {
+                    const int fl = ((bal >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+                    act[col] = fl;
+                    nact_l += fl;
+                }
+            }
+    }
+    add_active_count(nact_l, pp.nact);
+}
+
+template <int ST, int J, int STAGES, int TMAX>
+__global__ __launch_bounds__(256) void k_corr_qw(PassParams pp, const float* __restrict__ X,
+                                                 const float* __restrict__ Xil,
+                                                 float* __restrict__ S, uint8_t* __restrict__ act,
+                                                 double* __restrict__ fpart,
+                                                 int* __restrict__ nnzpart,
+                                                 const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int EPS = (ST == kStBF16) ? 8 : 16;
+    constexpr int XBlk = 2 * EPS * 16 * 16;
+    constexpr int StageBytes = 4 * TMAX * 2048 + J * XBlk;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
+    const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = pp.m, ldx = pp.ldx;
+    const int64_t n = pp.n;
+    const int64_t G = gridDim.x, g = blockIdx.x;
+    const int64_t ntile = (n + 15) / 16;
+    const int64_t tb = ntile * g / G, te = ntile * (g + 1) / G;   // this workgroup's tiles
+    const int lj = lane & 15;
+
+    double f_acc[J];
+    int nnz_acc[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) { f_acc[jb] = 0.0; nnz_acc[jb] = 0; }
+    const float* xcol[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
+
+    for (int64_t r0 = tb; r0 < te; r0 += 4 * TMAX) {
+        // this round: tiles r0 .. r1-1, split evenly over the four waves
+        const int64_t r1 = (r0 + 4 * TMAX < te) ? r0 + 4 * TMAX : te;
+        const int64_t nt = r1 - r0;
+        const int64_t w0 = r0 + nt * wv / 4, w1 = r0 + nt * (wv + 1) / 4;
+        const int64_t c0 = 16 * w0;
+        const int64_t cend = std::min<int64_t>(n, 16 * w1);
+        const int k = (int)(w1 - w0);
+#define GPSPCA_QW(NT) qw_round<NT, ST, J, STAGES, TMAX>(pp, c0, cend, lbase, wv, xcol, Xil, f_acc, nnz_acc, S, act)
+        switch (k) {
+            case 0: GPSPCA_QW(0); break;
+            case 1: GPSPCA_QW(1); break;
+            case 2: GPSPCA_QW(2); break;
+            case 3: GPSPCA_QW(3); break;
+            case 4: GPSPCA_QW(4); break;
+            case 5: if constexpr (TMAX >= 5) GPSPCA_QW(5); break;
+            case 6: if constexpr (TMAX >= 6) GPSPCA_QW(6); break;
+            case 7: if constexpr (TMAX >= 7) GPSPCA_QW(7); break;
+            default: if constexpr (TMAX >= 8) GPSPCA_QW(8); break;
+        }
+#undef GPSPCA_QW
+    }
+
+    const int64_t W = G * 4, w = g * 4 + wv;
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) {
+        double f = f_acc[jb];
+        int c = nnz_acc[jb];
+        f += __shfl_xor(f, 16, 64);
+        c += __shfl_xor(c, 16, 64);
+        f += __shfl_xor(f, 32, 64);
+        c += __shfl_xor(c, 32, 64);
+        const int comp = 16 * jb + lj;
+        if (lane < 16 && comp < m) {
+            fpart[(int64_t)comp * W + w] = f;
+            nnzpart[(int64_t)comp * W + w] = c;
+        }
+    }
+}
+
 // ------------------------------------------------------------- launchers
 hipError_t launch_quantize(const float* A, int64_t lda, int p, int64_t n, int to, void* out,
                            int64_t ldq, float* scale, hipStream_t st) {
@@ -515,6 +796,45 @@ hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, c
     }
 #undef GPSPCA_CQW
 #undef GPSPCA_CQ
+    return hipGetLastError();
+}
+
+// Four-wave workgroups sharing X (one per CU: their stages take 96-160 KB of
+// LDS).  Shapes (chunk tiles per wave, stages): (8, 2) by default for J <= 2,
+// (4, 3) for pl.mfma_stages = 3, (4, 2) for e4m3 with pl.mfma_stages = 2,
+// and (4, 2) for J = 4.  On the 32-gamma path at 10000 x 100000: bfloat16
+// 433 us with (8, 2) against 508 with (4, 3); e4m3 349 / 407 / 417 us with
+// (8, 2) / (4, 2) / (4, 3); one wave per workgroup (k_corr_q) 529 and 516 us.
+hipError_t launch_corr_qw(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
+                          float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
+                          hipStream_t st) {
+    const int J = q_blocks(pl.m), Sg = pl.mfma_stages;
+    const dim3 grid(pl.corr_grid), block(256);
+#define GPSPCA_QWL(STT, JJ, SS, TT) \
+    hipLaunchKernelGGL((k_corr_qw<STT, JJ, SS, TT>), grid, block, 0, st, pp, X, Xil, S, act, \
+                       fpart, nnzpart, ctrl)
+    if (pl.dtype == GPSPCA_BF16) {
+        if (J == 1) {
+            if (Sg == 3) GPSPCA_QWL(kStBF16, 1, 3, 4); else GPSPCA_QWL(kStBF16, 1, 2, 8);
+        } else if (J == 2) {
+            if (Sg == 3) GPSPCA_QWL(kStBF16, 2, 3, 4); else GPSPCA_QWL(kStBF16, 2, 2, 8);
+        } else {
+            GPSPCA_QWL(kStBF16, 4, 2, 4);
+        }
+    } else {
+        if (J == 1) {
+            if (Sg == 3) GPSPCA_QWL(kStF8, 1, 3, 4);
+            else if (Sg == 2) GPSPCA_QWL(kStF8, 1, 2, 4);
+            else GPSPCA_QWL(kStF8, 1, 2, 8);
+        } else if (J == 2) {
+            if (Sg == 3) GPSPCA_QWL(kStF8, 2, 3, 4);
+            else if (Sg == 2) GPSPCA_QWL(kStF8, 2, 2, 4);
+            else GPSPCA_QWL(kStF8, 2, 2, 8);
+        } else {
+            GPSPCA_QWL(kStF8, 4, 2, 4);
+        }
+    }
+#undef GPSPCA_QWL
     return hipGetLastError();
 }
 

@@ -78,11 +78,30 @@ def _cid(c):
     return f"{FORM_NAMES[c[0]]}-m{c[1]}-p{c[2]}-n{c[3]}"
 
 
+# correlation kernel variants: one wave per workgroup (q), and four waves
+# sharing each X stage (qw: the default 2 stages of 8-tile chunks, 3 stages of
+# 4-tile chunks, 2 stages of 4-tile chunks)
+QVARIANTS = ["q", "qw", "qw-3", "qw-2"]
+
+
+def _set_variant(kernel, monkeypatch):
+    if kernel == "q":
+        monkeypatch.setenv("GPSPCA_CORR_KERNEL", "mfma")
+    else:
+        monkeypatch.setenv("GPSPCA_CORR_KERNEL", "qw")
+    if "-" in kernel:
+        monkeypatch.setenv("GPSPCA_MFMA_STAGES", kernel.split("-")[1])
+
+
+@pytest.mark.parametrize("kernel", QVARIANTS)
 @pytest.mark.parametrize("to", [O.BF16, O.E4M3], ids=["bf16", "e4m3"])
 @pytest.mark.parametrize("case", CASES, ids=_cid)
-def test_step_parity_quantized(gpu, case, to):
+def test_step_parity_quantized(gpu, case, to, kernel, monkeypatch):
+    """One pass on the codes against the oracle on the dequantized matrix, for
+    every variant of the correlation kernel."""
     form, m, p, n, seed = case
-    print(f"\n[quant step] {TNAME[to]} {_cid(case)}", flush=True)
+    _set_variant(kernel, monkeypatch)
+    print(f"\n[quant step] {kernel} {TNAME[to]} {_cid(case)}", flush=True)
     A32, Adeq, Ad, sc = quantized_problem(p, n, m, seed, to)
     mu = np.linspace(1.0, 0.7, m) if form >= O.BL1 else None
     X0 = fp32_round(O.init(Adeq, m)[0])
@@ -124,8 +143,10 @@ def test_solve_parity_quantized(gpu, form, m, to):
     np.testing.assert_array_equal(res.support_mask().cpu().numpy()[~ties], ref["support"][~ties])
 
 
+@pytest.mark.parametrize("kernel", ["q", "qw"])
 @pytest.mark.parametrize("to", [O.BF16, O.E4M3], ids=["bf16", "e4m3"])
-def test_path_quantized_columns_match_oracle(gpu, to):
+def test_path_quantized_columns_match_oracle(gpu, to, kernel, monkeypatch):
+    _set_variant(kernel, monkeypatch)
     p, n, K, iters = 700, 4000, 32, 8
     A32, Adeq, Ad, sc = quantized_problem(p, n, 1, 21, to)
     fr = W.gamma_fractions(K)
