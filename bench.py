@@ -82,7 +82,10 @@ def column_norm_max(A: np.ndarray) -> float:
     return best
 
 
-KERNEL_SOURCE = {"k_corr_mfma": "k_corr_mfma.hip", "k_corr": "k_pass.hip", "k_pass_m1": "k_pass.hip"}
+KERNEL_SOURCE = {"k_corr_mfma": "k_corr_mfma.hip", "k_corr_rd": "k_corr_mfma.hip",
+                 "k_corr_x3": "k_corr_mfma.hip", "k_corr_wg": "k_corr_mfma.hip",
+                 "k_corr_q": "k_quant.hip", "k_corr_qw": "k_quant.hip",
+                 "k_corr": "k_pass.hip", "k_pass_m1": "k_pass.hip"}
 
 
 def kernel_source_hash(kernel: str) -> str:

@@ -327,7 +327,13 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
         // correlation kernels below keep
         if (!(pl->use_mfma || pl->use_vx || pl->use_mv || pl->use_q)) pl->bp_thr = 2 * 1024;
     }
-    pl->mpad = pl->fused_m1 ? 1 : (int)align_up((size_t)m, (size_t)pl->corr_M);
+    // columns of the X buffers: the matrix-core kernels (corr_M = 16) read every
+    // column of their 1, 2 or 4 groups of 16 (components past m are zero)
+    pl->mpad = pl->fused_m1 ? 1
+             : pl->corr_M == 16 ? 16 * (m <= 16 ? 1 : m <= 32 ? 2 : 4)
+             : (int)align_up((size_t)m, (size_t)pl->corr_M);
+    // interleaved copies of X (FP32 row quads) for the matrix-core kernels
+    pl->xil_bytes = (pl->use_mfma || pl->use_q) ? 4 * (size_t)pl->ldx * (size_t)pl->mpad : 0;
     const int64_t ne = (int64_t)m * pl->ldx;
     const int64_t bx = cdiv(ne, 256);
     int64_t split = cdiv(2LL * ncu, bx);
@@ -379,8 +385,8 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->o_pstate = take(path ? sizeof(PathState) * M : 1);
     pl->o_list = take(sizeof(int) * (N + 64));  // frozen-support column list + its count
     const bool xil = pl->use_mfma || pl->use_q;   // interleaved copies of X for the DMA kernels
-    pl->o_xil0 = take(xil ? sizeof(float) * L * (size_t)pl->mpad : 1);
-    pl->o_xil1 = take(xil ? sizeof(float) * L * (size_t)pl->mpad : 1);
+    pl->o_xil0 = take(xil ? pl->xil_bytes : 1);
+    pl->o_xil1 = take(xil ? pl->xil_bytes : 1);
     pl->o_fsum = take(sizeof(double) * 2 * M);   // per-component objective and support sums
     pl->total = o;
 }
@@ -431,6 +437,11 @@ static size_t workspace_all(const gpspca_matrix* A, int form, int m, int max_ite
         Plan pl;
         make_plan(A, form, m, max_iter, ncu, &pl, path, 0, &t);
         mx = std::max(mx, pl.total);
+    }
+    {
+        Plan pe;  // the plan the environment or the autotuner's table selects
+        make_plan(A, form, m, max_iter, ncu, &pe, path, 0);
+        mx = std::max(mx, pe.total);
     }
     if (A->dtype == GPSPCA_F32) {
         Plan pr;  // frozen-support passes (refinement) on the same matrix
@@ -880,7 +891,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
     }
 
     if (pl.use_mfma || pl.use_q) {
-        GPSPCA_HIP(launch_fill_zero(P.xil[1], sizeof(float) * pl.ldx * pl.mpad, st));
+        GPSPCA_HIP(launch_fill_zero(P.xil[1], pl.xil_bytes, st));
         GPSPCA_HIP(launch_x_interleave(pl, P.x[0], P.xil[0], st));
     }
 
@@ -1291,7 +1302,7 @@ static int time_config(const gpspca_matrix* A, int pform, int m, double gamma, i
     }
     GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
     if (pl.use_mfma || pl.use_q) {
-        GPSPCA_HIP(launch_fill_zero(P.xil[1], sizeof(float) * pl.ldx * pl.mpad, st));
+        GPSPCA_HIP(launch_fill_zero(P.xil[1], pl.xil_bytes, st));
         GPSPCA_HIP(launch_x_interleave(pl, P.x[0], P.xil[0], st));
     }
     TimedLaunches tl;

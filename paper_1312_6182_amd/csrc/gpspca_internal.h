@@ -85,6 +85,7 @@ struct Plan {
     int gram_rows, gram_grid;
     int fused_gram;        // m <= 16: partial reduction and Gram in one kernel (64-row blocks)
     int gram_blocks;       // number of Gram partials of a pass
+    size_t xil_bytes;      // bytes of each interleaved copy of X (0: none)
     int fin_grid;
     int topm_grid;
     int vec4;              // float4 loads of A are legal
