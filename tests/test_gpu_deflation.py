@@ -9,7 +9,9 @@ projects the new iterate back onto the range of I - X_{<k} X_{<k}^T.
 Per component: the number of passes, the status and the objective trace match
 the oracle (1e-4 relative: each component's deflation carries the FP32
 rounding of the earlier ones), X to 1e-4 relative, the support exactly away
-from threshold ties; the components are orthonormal."""
+from threshold ties; the components are orthonormal.  A second test shares
+the earlier components with the oracle (it deflates by the GPU's own), which
+isolates each component's error at the FP32 tolerance of 1e-5."""
 import numpy as np
 import pytest
 
@@ -68,6 +70,35 @@ def test_deflated_components_match_oracle(gpu, case):
         ties = tie_mask(Ak, ref["X"][:, [k]], form, g, None)[:, 0]
         np.testing.assert_array_equal(sup[~ties, k], ref["support"][~ties, k])
     np.testing.assert_allclose(X.T @ X, np.eye(m), atol=1e-5)
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=_ids)
+def test_deflated_component_given_earlier_gpu_components(gpu, case):
+    """The error of each component on its own, at the FP32 tolerance: the
+    oracle solves component k on A_k = (I - Q Q^T) A with Q the GPU's own
+    components 0..k-1 (in FP64), so the earlier components' FP32 rounding is
+    shared and only component k's passes are compared -- trace, x and z within
+    1e-5, the support exactly away from ties."""
+    form, m, p, n, lda, seed = case
+    print(f"\n[deflation, given earlier] {_ids(case)}", flush=True)
+    A32, _, _ = W.planted_block(p, n, min(m, 4), seed, k=min(50, n // 8))
+    A64 = A32.astype(np.float64)
+    g = W.gamma_absolute(A64, is_l0(form), 0.01 if is_l0(form) else 0.05)
+    iters = 10
+    res = gpu.solve_deflated(to_device(A32, lda=lda), form, m, g, tol=0.0, max_iter=iters)
+    X = res.X.cpu().numpy().astype(np.float64)
+    Z = res.Z.cpu().numpy().astype(np.float64)
+    sup = res.support_mask().cpu().numpy()
+    for k in range(1, m):
+        Ak = _deflated(A64, X, k)
+        assert _top_gap(Ak) > 1e-5, k
+        ref = O.solve(Ak, form, 1, g, tol=0.0, max_iter=iters)
+        assert res.n_iter[k] == ref["n_iter"] and res.status[k] == ref["status"], k
+        np.testing.assert_allclose(res.traces[k], ref["trace"], rtol=1e-5)
+        assert rel(X[:, k], ref["X"][:, 0]) <= 1e-5, k
+        assert rel(Z[:, k], ref["Z"][:, 0]) <= 1e-5, k
+        ties = tie_mask(Ak, ref["X"], form, g, None)[:, 0]
+        np.testing.assert_array_equal(sup[~ties, k], ref["support"][~ties, 0])
 
 
 def test_deflated_first_component_is_the_plain_solve(gpu):
