@@ -92,18 +92,23 @@ __device__ __forceinline__ bool threshold_m(bool l0, double mu, double gamma, fl
 // One chunk of NT tiles of 16 columns (NT <= 4) starting at column c0: stream
 // its rows through the LDS stages, multiply on the matrix cores, threshold.
 // Columns at or past cend are clamped to cend - 1 and their results dropped.
-template <int NT, int J, int STAGES, int TMAX>
+// HX (m <= 8, J = 1): X is staged for components 0..7 only, by one DMA
+// instruction per stage instead of two; lanes of components 8..15 read the
+// same LDS line as component lj - 8, whose products land in outputs that are
+// never stored.
+template <int NT, int J, int STAGES, int TMAX, bool HX = false>
 __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int64_t cend,
                                            uint32_t lbase, const float* const* xcol,
                                            const float* __restrict__ Xil, double* f_acc,
                                            int* nnz_acc, float* __restrict__ S,
                                            uint8_t* __restrict__ act) {
     int nact_l = 0;   // active columns written by this lane
+    static_assert(!HX || J == 1, "half X staging needs one component group");
     constexpr int AStage = TMAX * 16 * kQS * 16;   // A bytes per stage: TMAX tiles x 32 rows
-    constexpr int XStageBytes = J * 2 * 1024;
+    constexpr int XStageBytes = HX ? 1024 : J * 2 * 1024;
     constexpr int StageBytes = AStage + XStageBytes;
     constexpr int ADMA = 2 * NT;           // A DMA instructions per stage (8 columns each)
-    constexpr int PER = ADMA + 2 * J;      // DMA instructions per stage
+    constexpr int PER = ADMA + (HX ? 1 : 2 * J);   // DMA instructions per stage
     const int lane = threadIdx.x;
     const int lj = lane & 15, lk = lane >> 4;
     const int p = pp.p, m = pp.m;
@@ -135,16 +140,23 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
             dma16(acol[i] + 4 * q, sb + 1024 * i);
         }
         // X: 4 row quads x 16 components per instruction, one contiguous 1 KB
-        // of the interleaved copy (rows past the full quads read the zero quad)
+        // of the interleaved copy (rows past the full quads read the zero quad);
+        // HX: 8 row quads x 8 components (lane L: quad L / 8, component L % 8)
+        if constexpr (HX) {
+            int q = q0 + (lane >> 3);
+            q = (q < nqf) ? q : nqx - 1;
+            dma16(Xil + ((size_t)q * 16 + (lane & 7)) * 4, sb + AStage);
+        } else {
 #pragma unroll
-        for (int jb = 0; jb < J; ++jb)
+            for (int jb = 0; jb < J; ++jb)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                int q = q0 + 4 * i + lk;
-                q = (q < nqf) ? q : nqx - 1;
-                dma16(Xil + ((size_t)(jb * nqx + q) * 16 + lj) * 4,
-                      sb + AStage + 1024 * (2 * jb + i));
-            }
+                for (int i = 0; i < 2; ++i) {
+                    int q = q0 + 4 * i + lk;
+                    q = (q < nqf) ? q : nqx - 1;
+                    dma16(Xil + ((size_t)(jb * nqx + q) * 16 + lj) * 4,
+                          sb + AStage + 1024 * (2 * jb + i));
+                }
+        }
     };
 
     f4m acc[NT][J];
@@ -184,8 +196,9 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                 av[h][t] = lds_read16(sb + a_slot(16 * t + lj, 4 * h + lk));
 #pragma unroll
             for (int jb = 0; jb < J; ++jb)
-                xv[h][jb] = lds_read16(sb + AStage + 2048u * jb +
-                                       16u * (uint32_t)((4 * h + lk) * 16 + lj));
+                xv[h][jb] = HX ? lds_read16(sb + AStage + 16u * (uint32_t)((4 * h + lk) * 8 + (lj & 7)))
+                               : lds_read16(sb + AStage + 2048u * jb +
+                                            16u * (uint32_t)((4 * h + lk) * 16 + lj));
             if (h == 0) {
                 // wait for the first half's reads before the second half's are issued
                 wait_lgkm0();
@@ -274,7 +287,7 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
 // J: component blocks of 16 (m <= 16 J);  STAGES: stages in flight.
 // TMAX: tiles of 16 columns per chunk (4, or 8 to stage X once per wave when
 // a wave owns up to 128 columns).
-template <int J, int STAGES, int TMAX = 4>
+template <int J, int STAGES, int TMAX = 4, bool HX = false>
 __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __restrict__ X,
                                                   const float* __restrict__ Xil,
                                                   float* __restrict__ S,
@@ -283,7 +296,7 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
                                                   int* __restrict__ nnzpart,
                                                   const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
-    constexpr int XStageBytes = J * 2 * 1024;
+    constexpr int XStageBytes = HX ? 1024 : J * 2 * 1024;
     constexpr int StageBytes = TMAX * 16 * kQS * 16 + XStageBytes;
     __shared__ __attribute__((aligned(16))) uint8_t lds[STAGES * StageBytes];
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)lds;
@@ -314,7 +327,7 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
     for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * TMAX) {
         const int64_t left = cend - c0;
         const int nt = left >= 16 * TMAX ? TMAX : (int)((left + 15) / 16);
-#define GPSPCA_CH(NT) mfma_chunk<NT, J, STAGES, TMAX>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act)
+#define GPSPCA_CH(NT) mfma_chunk<NT, J, STAGES, TMAX, HX>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act)
         if constexpr (TMAX == 8) {
             switch (nt) {
                 case 8: GPSPCA_CH(8); break;
@@ -1280,6 +1293,13 @@ hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, 
 
 // Resident workgroups per CU of the matrix-core kernel for (m, stages): what
 // LDS allows (the caller caps it).
+// Half X staging for m <= 8 (GPSPCA_MFMA_HALF_X=0 turns it off, for tests and
+// comparisons).
+static bool mfma_half_x() {
+    const char* e = std::getenv("GPSPCA_MFMA_HALF_X");
+    return !(e && e[0] == '0');
+}
+
 int corr_mfma_blocks_per_cu(int m, int stages) {
     int nb = 0;
     hipError_t e;
@@ -1305,7 +1325,9 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
                             float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                             hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(64);
-    if (pl.m <= 16 && pl.mfma_stages == 8)
+    if (pl.m <= 8 && pl.mfma_stages == 8 && mfma_half_x())
+        hipLaunchKernelGGL((k_corr_mfma<1, 2, 8, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+    else if (pl.m <= 16 && pl.mfma_stages == 8)
         hipLaunchKernelGGL((k_corr_mfma<1, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 16 && pl.mfma_stages == 4)
         hipLaunchKernelGGL((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);

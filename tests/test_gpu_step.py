@@ -98,14 +98,18 @@ def test_step_zero_gamma_dense_support(gpu, form):
     np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
 
 
-@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "rd", "rd128", "wg", "x3", "valu"])
+@pytest.mark.parametrize("kernel", ["vx", "mv", "mfma", "mfma-fullx", "rd", "rd128", "wg", "x3",
+                                    "valu"])
 @pytest.mark.parametrize("form,m", [(O.BL1, 4), (O.BL0, 8)])
 def test_every_correlation_kernel(gpu, kernel, form, m, monkeypatch):
     """Force each block correlation kernel (registers-X, matrix cores through
     registers, matrix cores through LDS DMA, FP32 split into bfloat16 parts on
     the bfloat16 matrix cores, plain vector ALU) on the same case: one step and
     a 6-pass solve against the oracle."""
-    monkeypatch.setenv("GPSPCA_CORR_KERNEL", kernel)
+    monkeypatch.setenv("GPSPCA_CORR_KERNEL", kernel.split("-")[0])
+    if kernel == "mfma-fullx":
+        # X staged for all 16 component slots (m <= 8 stages 8 of them by default)
+        monkeypatch.setenv("GPSPCA_MFMA_HALF_X", "0")
     p, n = 1003, 3001  # ragged row quad
     A32, _, _ = W.planted_block(p, n, 3, 23, k=40)
     A64 = A32.astype(np.float64)
