@@ -601,7 +601,7 @@ __global__ __launch_bounds__(256) void k_corr_wg(PassParams pp, const float* __r
     for (int jb = 0; jb < J; ++jb) xcol[jb] = X + (size_t)(16 * jb + lj) * ldx;
 
     for (int64_t r0 = tb; r0 < te; r0 += 4 * TMAX) {
-        // this round: tiles r0 .. r1-1, split evenly over the four waves
+        // tiles r0 .. r1-1 of this iteration, split evenly over the four waves
         const int64_t r1 = (r0 + 4 * TMAX < te) ? r0 + 4 * TMAX : te;
         const int64_t nt = r1 - r0;
         const int64_t w0 = r0 + nt * wv / 4, w1 = r0 + nt * (wv + 1) / 4;

@@ -24,7 +24,7 @@ def _gpu_available() -> bool:
 @pytest.fixture(scope="session")
 def gpu():
     """Skip-free guard: GPU tests must fail loudly, not skip, when the device or
-    the HIP library is missing on a GPU machine."""
+    the HIP library is missing on a machine with a GPU."""
     if not _gpu_available():
         pytest.fail("GPU test selected but torch sees no GPU")
     import paper_1312_6182_amd as g
