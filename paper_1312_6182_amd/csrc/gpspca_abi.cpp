@@ -548,6 +548,8 @@ struct Prof {
 };
 static Prof g_prof;
 
+thread_local KernelEvents g_kev;
+
 struct TimedLaunches {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     bool on = false;
@@ -555,38 +557,49 @@ struct TimedLaunches {
     int64_t seen = 0;
     bool cur = false;   // the current launch is timed
     ~TimedLaunches() {
+        g_kev = KernelEvents{};
         for (auto& e : ev) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
     }
+    // The correlation launch between begin() and end() records the pair at
+    // its own start and end (GPSPCA_LAUNCH_TIMED); an event pair recorded
+    // around it measured 9 us more than the kernel's own duration (718.8
+    // against 709.8 us on 10000 x 100000, m = 8).
     hipError_t begin(hipStream_t st) {
+        (void)st;
         cur = on && (seen++ % every) == 0;
         if (!cur) return hipSuccess;
-        // timing only: no system-scope fence at the event (the two events of a
-        // pass cost about 12 us with the default flags on 10000 x 100000, m = 8)
         hipEvent_t a, b;
         hipError_t e = hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
         if (e != hipSuccess) return e;
         e = hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
         if (e != hipSuccess) return e;
         ev.emplace_back(a, b);
-        return hipEventRecord(a, st);
+        g_kev.start = a;
+        g_kev.stop = b;
+        return hipSuccess;
     }
     hipError_t end(hipStream_t st) {
-        if (!cur) return hipSuccess;
-        return hipEventRecord(ev.back().second, st);
+        (void)st;
+        g_kev = KernelEvents{};
+        return hipSuccess;
     }
     void collect(const char* name) {
         if (!on) return;
         double tot = 0.0;
+        int64_t n = 0;
         for (auto& e : ev) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) tot += ms;
+            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+                tot += ms;
+                ++n;
+            }
         }
         std::lock_guard<std::mutex> lk(g_prof.mu);
         g_prof.total_ms += tot;
-        g_prof.launches += (int64_t)ev.size();
+        g_prof.launches += n;
         g_prof.name = name;
     }
 };

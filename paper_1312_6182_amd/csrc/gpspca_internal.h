@@ -2,6 +2,7 @@
 // kernel parameter blocks and the host-side launchers of every kernel.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -140,6 +141,25 @@ hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, 
                           uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st);
 // Xil: X in the row-quad-interleaved layout of launch_x_interleave.
+// Kernel timing: while the solve driver times a launch of the pass's
+// correlation kernel, these events are set and that launch records them at its
+// own start and end (hipExtLaunchKernelGGL puts them on the dispatch itself,
+// so no separate event packets sit around the kernel).  Null otherwise.
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local KernelEvents g_kev;
+
+// Launch of a correlation kernel that records g_kev when it is set.
+#define GPSPCA_LAUNCH_TIMED(KERNEL, GRID, BLOCK, SHM, STREAM, ...)                               \
+    do {                                                                                         \
+        if (::gpspca::g_kev.start)                                                               \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, ::gpspca::g_kev.start,       \
+                                  ::gpspca::g_kev.stop, 0, __VA_ARGS__);                        \
+        else                                                                                     \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                   \
+    } while (0)
+
 hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
                             float* S,
                             uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,

@@ -645,7 +645,7 @@ hipError_t launch_corr_wg(const Plan& pl, const PassParams& pp, const float* X, 
                           hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(256);
 #define GPSPCA_KW(JJ, SS, TT) \
-    hipLaunchKernelGGL((k_corr_wg<JJ, SS, TT>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl)
+    GPSPCA_LAUNCH_TIMED((k_corr_wg<JJ, SS, TT>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl)
     if (pl.m <= 16) {
         if (pl.mfma_stages == 4) GPSPCA_KW(1, 4, 4);
         else GPSPCA_KW(1, 2, 8);
@@ -873,7 +873,7 @@ hipError_t launch_corr_rd(const Plan& pl, const PassParams& pp, const float* X, 
     const dim3 grid(pl.corr_grid), block(64);
     const int D = pl.rd_depth;
 #define GPSPCA_RD(JJ, DD, WW) \
-    hipLaunchKernelGGL((k_corr_rd<JJ, DD, WW>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
+    GPSPCA_LAUNCH_TIMED((k_corr_rd<JJ, DD, WW>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
                        nnzpart, ctrl)
 #define GPSPCA_RDW(JJ, DD) \
     do { if (pl.rd128) GPSPCA_RD(JJ, DD, true); else GPSPCA_RD(JJ, DD, false); } while (0)
@@ -1115,7 +1115,7 @@ hipError_t launch_corr_x3(const Plan& pl, const PassParams& pp, const float* X, 
                           hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(64);
 #define GPSPCA_X3(JJ, DD) \
-    hipLaunchKernelGGL((k_corr_x3<JJ, DD>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
+    GPSPCA_LAUNCH_TIMED((k_corr_x3<JJ, DD>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
                        nnzpart, ctrl)
     const bool d3 = pl.rd_depth == 3;
     if (pl.m <= 16) {
@@ -1286,7 +1286,7 @@ __global__ __launch_bounds__(64) void k_corr_mv(PassParams pp, const float* __re
 hipError_t launch_corr_mv(const Plan& pl, const PassParams& pp, const float* X, float* S,
                           uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_corr_mv, dim3(pl.corr_grid), dim3(64), 0, st, pp, X, S, act, fpart,
+    GPSPCA_LAUNCH_TIMED(k_corr_mv, dim3(pl.corr_grid), dim3(64), 0, st, pp, X, S, act, fpart,
                        nnzpart, ctrl);
     return hipGetLastError();
 }
@@ -1326,21 +1326,21 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
                             hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(64);
     if (pl.m <= 8 && pl.mfma_stages == 8 && mfma_half_x())
-        hipLaunchKernelGGL((k_corr_mfma<1, 2, 8, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 16 && pl.mfma_stages == 8)
-        hipLaunchKernelGGL((k_corr_mfma<1, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 16 && pl.mfma_stages == 4)
-        hipLaunchKernelGGL((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 16 && pl.mfma_stages == 2)
-        hipLaunchKernelGGL((k_corr_mfma<1, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 16)
-        hipLaunchKernelGGL((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 32 && pl.mfma_stages == 8)
-        hipLaunchKernelGGL((k_corr_mfma<2, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<2, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else if (pl.m <= 32)
-        hipLaunchKernelGGL((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     else
-        hipLaunchKernelGGL((k_corr_mfma<4, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<4, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
     return hipGetLastError();
 }
 

@@ -964,7 +964,7 @@ template <int T, int KQ, bool VEC>
 static hipError_t launch_m1_t(const Plan& pl, const PassParams& pp, const float* x, float* S,
                               float* gpart, double* fpart, int* nnzpart, const Ctrl* ctrl,
                               hipStream_t st) {
-    hipLaunchKernelGGL((k_pass_m1<T, KQ, 2, VEC>), dim3(pl.m1_grid), dim3(T), 0, st, pp, x, S,
+    GPSPCA_LAUNCH_TIMED((k_pass_m1<T, KQ, 2, VEC>), dim3(pl.m1_grid), dim3(T), 0, st, pp, x, S,
                        gpart, fpart, nnzpart, ctrl);
     return hipGetLastError();
 }
@@ -1041,7 +1041,7 @@ template <int T, int KQ, int M>
 static hipError_t launch_vx_t(const Plan& pl, const PassParams& pp, const float* X, float* S,
                               uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
                               hipStream_t st) {
-    hipLaunchKernelGGL((k_corr_vx<T, KQ, M, true>), dim3(pl.corr_grid), dim3(T), 0, st, pp, X, S,
+    GPSPCA_LAUNCH_TIMED((k_corr_vx<T, KQ, M, true>), dim3(pl.corr_grid), dim3(T), 0, st, pp, X, S,
                        act, fpart, nnzpart, ctrl);
     return hipGetLastError();
 }

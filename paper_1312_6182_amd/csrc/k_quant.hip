@@ -770,10 +770,10 @@ hipError_t launch_corr_q(const Plan& pl, const PassParams& pp, const float* X, c
     const int J = q_blocks(pl.m), Sg = pl.mfma_stages;
     const dim3 grid(pl.corr_grid), block(64);
 #define GPSPCA_CQ(STT, JJ, SS) \
-    hipLaunchKernelGGL((k_corr_q<STT, JJ, SS>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
+    GPSPCA_LAUNCH_TIMED((k_corr_q<STT, JJ, SS>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
                        nnzpart, ctrl)
 #define GPSPCA_CQW(STT, JJ) \
-    hipLaunchKernelGGL((k_corr_q<STT, JJ, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
+    GPSPCA_LAUNCH_TIMED((k_corr_q<STT, JJ, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, \
                        nnzpart, ctrl)
     if (Sg == 8 && J <= 2) {
         if (pl.dtype == GPSPCA_BF16) {
@@ -811,7 +811,7 @@ hipError_t launch_corr_qw(const Plan& pl, const PassParams& pp, const float* X, 
     const int J = q_blocks(pl.m), Sg = pl.mfma_stages;
     const dim3 grid(pl.corr_grid), block(256);
 #define GPSPCA_QWL(STT, JJ, SS, TT) \
-    hipLaunchKernelGGL((k_corr_qw<STT, JJ, SS, TT>), grid, block, 0, st, pp, X, Xil, S, act, \
+    GPSPCA_LAUNCH_TIMED((k_corr_qw<STT, JJ, SS, TT>), grid, block, 0, st, pp, X, Xil, S, act, \
                        fpart, nnzpart, ctrl)
     if (pl.dtype == GPSPCA_BF16) {
         if (J == 1) {
