@@ -712,7 +712,9 @@ def main():
         return
     if not args.no_extra:
         extra = {}
-        xs = max(5, args.steps // 3)
+        # at least 33 timed passes per leg whatever --steps is, so that every
+        # leg's figure is a per-pass rate, not the one-off start of its solve
+        xs = max(33, args.steps // 3)
 
         def rec(name, Adev, fid, mm, g, mu=None):
             r2, ms2, kms2, l2, kn2 = time_gpu(G, torch, Adev, fid, mm, g, xs, 2, mu=mu)

@@ -28,6 +28,8 @@
 #include "storage.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cstdlib>
 
 namespace gpspca {
@@ -1300,7 +1302,27 @@ static bool mfma_half_x() {
     return !(e && e[0] == '0');
 }
 
+static int corr_mfma_blocks_per_cu_query(int m, int stages);
+
+// Resident workgroups per CU of the configuration (m bucket, stages): the
+// occupancy query runs once per configuration; every plan (and every
+// workspace-size query, which builds a plan per autotuner candidate) reuses it.
 int corr_mfma_blocks_per_cu(int m, int stages) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    const std::pair<int, int> key(m <= 16 ? 16 : m <= 32 ? 32 : 64, stages);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int nb = corr_mfma_blocks_per_cu_query(m, stages);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = nb;
+    return nb;
+}
+
+static int corr_mfma_blocks_per_cu_query(int m, int stages) {
     int nb = 0;
     hipError_t e;
     if (m <= 16 && stages == 8)  // wide chunks: 2 stages of 8 tiles

@@ -23,6 +23,9 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace gpspca {
 
@@ -746,7 +749,25 @@ static int occ_q() {
     return nb;
 }
 
+static int corr_q_blocks_per_cu_query(int dtype, int m, int stages);
+
+// Cached per (storage, component groups, stages), as corr_mfma_blocks_per_cu.
 int corr_q_blocks_per_cu(int dtype, int m, int stages) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, int> cache;
+    const std::tuple<int, int, int> key(dtype, q_blocks(m), stages);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int nb = corr_q_blocks_per_cu_query(dtype, m, stages);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = nb;
+    return nb;
+}
+
+static int corr_q_blocks_per_cu_query(int dtype, int m, int stages) {
     const int J = q_blocks(m);
     int nb;
     if (stages == 8 && J <= 2) {
