@@ -388,12 +388,14 @@ const char* gpspca_version(void);
 
 /*
  * Kernel timing for roofline reports.  While enabled (on >= 1), the solve path
- * brackets the launches of its dominant (A-streaming) kernel with HIP events
- * on the launch stream: the first launch of each solve and every on-th one
- * after it (on = 1: every launch; a sample keeps the events' own cost out of
- * the timed passes).  on <= 0 disables timing.  gpspca_profile_read returns
- * the summed duration (ms) of the timed launches, their count, and the name of
- * the kernel, then resets the counters.
+ * times launches of its dominant (A-streaming) correlation kernel with a pair
+ * of HIP events that the launch itself records at the kernel's start and end
+ * (hipExtLaunchKernelGGL): the first launch of each solve and every on-th one
+ * after it (on = 1: every launch).  on <= 0 disables timing.
+ * gpspca_profile_read returns the summed duration (ms) of the timed launches,
+ * their count, and the name of the kernel, then resets the counters.  Solves
+ * whose correlation runs as several launches (the vector-ALU fallback for
+ * unaligned A) report no timed launches.
  */
 int gpspca_profile_enable(int on);
 int gpspca_profile_read(double* total_ms, int64_t* launches, char* name, size_t name_len);
