@@ -7,6 +7,8 @@
 //   otherwise           k_corr (correlation + threshold, one read of A) and
 //                       k_backproj (reads only the columns in the support)
 //   then                k_reduce_partials -> k_gram -> k_stop -> k_apply
+//                       (after k_pass_m1: k_reduce_m1 -> k_stop_x1, which
+//                       writes x_{k+1} itself)
 // The stopping rule runs on the device; the host polls the control block once
 // per chunk of passes and never per pass.
 #include <hip/hip_runtime.h>
@@ -349,7 +351,9 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     // small matrices take many short column ranges: hundreds of partials are
     // summed faster by the split reduction, whose grid also spans the partials
     pl->fused_gram = (m <= 16 && !pl->fused_m1 && pl->npart <= 128) ? 1 : 0;
-    pl->gram_blocks = pl->fused_gram ? (int)cdiv(A->p, 64) : pl->gram_grid;
+    pl->gram_blocks = pl->fused_gram ? (int)cdiv(A->p, 64)
+                      : pl->fused_m1 ? (int)cdiv(A->p, kRm1Rows)
+                                     : pl->gram_grid;
     // 256 / m support words (32 columns each) per finalize workgroup
     pl->fin_grid = (int)std::max<int64_t>(1, cdiv(cdiv(A->n, 32), 256 / std::max(1, m)));
     pl->topm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(A->n, 1024)));
@@ -643,7 +647,9 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
         GPSPCA_HIP(launch_backproj(pl, pp, P.S, P.act, P.gpart, P.touched, P.ctrl, st));
     }
     const int with_x = pl.path ? 2 : (pl.m > 1 ? 1 : 0);
-    if (pl.fused_gram) {
+    if (pl.fused_m1) {
+        GPSPCA_HIP(launch_reduce_m1(pl, P.gpart, P.g64, P.gram, P.ctrl, st));
+    } else if (pl.fused_gram) {
         GPSPCA_HIP(launch_reduce_gram(pl, P.gpart, touched, Xk, with_x, P.g64, P.gram, P.ctrl, st));
     } else {
         GPSPCA_HIP(launch_reduce_partials(pl, P.gpart, touched, P.l1, P.ctrl, st));

@@ -14,6 +14,8 @@
 namespace gpspca {
 
 constexpr int kMaxM = GPSPCA_MAX_M;
+// rows per workgroup of the single-unit partial reduction (one Gram partial each)
+constexpr int kRm1Rows = 64;
 
 // Device-resident state of one solve.  Written only by single-workgroup
 // kernels (stop test / projection) and by the control reset kernel.
@@ -193,6 +195,10 @@ hipError_t launch_reduce_partials(const Plan& pl, const float* gpart, const int*
 hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float* X,
                        int with_x, double* g64, double* gram, const Ctrl* ctrl,
                        hipStream_t st);
+// m = 1 after the fused pass: g64 = the sum of the npart partials, and the
+// cdiv(p, kRm1Rows) Gram partials of ||g||^2 (entry 0 of each 3-entry block).
+hipError_t launch_reduce_m1(const Plan& pl, const float* gpart, double* g64, double* gram,
+                            const Ctrl* ctrl, hipStream_t st);
 // Xn (m = 1 only, may be NULL): write x_{k+1} = g / ||g|| from g64 as well.
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,

@@ -1020,6 +1020,8 @@ __device__ void block_coefficients(int m, double* coef, double* vprev, StopShare
 // sums of the wave partials, F, and the rule (F = 0, the relative change
 // below tol, or the last allowed pass).  Fills ss (terms, live and dead
 // components, stop) and the control block; returns the stop flag.
+// kGiven: fsum is always given (the branch that sums the partials is left out).
+template <bool kGiven = false>
 __device__ int stop_rule(int m, int nwp, const double* __restrict__ fpart,
                          const int* __restrict__ nnzpart, double* __restrict__ trace,
                          double* __restrict__ fcomp, int exact, Ctrl* __restrict__ ctrl,
@@ -1035,7 +1037,7 @@ __device__ int stop_rule(int m, int nwp, const double* __restrict__ fpart,
     // Gram-sum kernel), or here by tpc (a power of two <= 64) lanes of one
     // wave per component, each summing a strided slice, the slices combined by
     // a fixed butterfly (fixed order)
-    if (fsum) {
+    if (kGiven || fsum) {
         for (int j = t; j < m; j += nt) {
             ss.fj[j] = fsum[j];
             ss.nj[j] = (int)fsum[m + j];
@@ -1108,6 +1110,40 @@ __device__ int stop_rule(int m, int nwp, const double* __restrict__ fpart,
     return ss.stop;
 }
 
+// m = 1: ||g||^2 as the sum of the ngram Gram partials (entry 0 of each
+// 3-entry block; strided per-thread sums, a fixed butterfly in each wave, the
+// waves in order), 1/||g|| into coef, and the check that it is finite.
+// Returns 1/||g|| to every thread, or 0 when the pass failed.  red: at least
+// blockDim.x / 64 doubles of LDS.
+__device__ double unit_scale(const double* __restrict__ gram, int ngram,
+                             double* __restrict__ coef, int k, Ctrl* __restrict__ ctrl,
+                             double* red) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    double sg = 0.0;
+    for (int g = t; g < ngram; g += nt) sg += gram[(size_t)3 * g];
+    sg = wave_sum_d(sg);
+    if ((t & 63) == 0) red[t >> 6] = sg;
+    __syncthreads();
+    if (t == 0) {
+        double g2 = 0.0;
+        for (int u = 0; u < (nt + 63) / 64; ++u) g2 += red[u];
+        coef[2] = g2;
+        const double om = 1.0 / sqrt(g2);
+        coef[0] = om;
+        coef[1] = 0.0;
+        ctrl->ndead = 0;
+        const int bad = (!(g2 > 0.0) || !isfinite(om)) ? 1 : 0;
+        if (bad) {
+            ctrl->status = GPSPCA_ENONFINITE;
+            ctrl->done = 1;
+            ctrl->n_iter = k + 1;
+        }
+        red[0] = bad ? 0.0 : om;
+    }
+    __syncthreads();
+    return red[0];
+}
+
 // One workgroup: objective, trace, stopping rule, retraction coefficients.
 // m = 1: ||g||^2 is summed here from the ngram Gram partials (no k_gram_sum),
 // and with Xn given the retraction x_{k+1} = g / ||g|| is written here too
@@ -1134,32 +1170,7 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
 
     const int mm = m * m;
     if (m == 1) {
-        // ||g||^2 = sum of the partials (entry 0 of each 3-entry block): strided
-        // per-thread sums, added in thread order
-        double sg = 0.0;
-        for (int g = t; g < ngram; g += nt) sg += gram[(size_t)3 * g];
-        // a fixed butterfly within each wave, then the waves in order
-        sg = wave_sum_d(sg);
-        if ((t & 63) == 0) red[t >> 6] = sg;
-        __syncthreads();
-        if (t == 0) {
-            double g2 = 0.0;
-            for (int u = 0; u < (nt + 63) / 64; ++u) g2 += red[u];
-            coef[2] = g2;
-            const double om = 1.0 / sqrt(g2);
-            coef[0] = om;
-            coef[1] = 0.0;
-            ctrl->ndead = 0;
-            const int bad = (!(g2 > 0.0) || !isfinite(om)) ? 1 : 0;
-            if (bad) {
-                ctrl->status = GPSPCA_ENONFINITE;
-                ctrl->done = 1;
-                ctrl->n_iter = k + 1;
-            }
-            red[0] = bad ? 0.0 : om;
-        }
-        __syncthreads();
-        const double om = red[0];
+        const double om = unit_scale(gram, ngram, coef, k, ctrl, red);
         if (Xn && om != 0.0)
             for (int r = t; r < p; r += nt) Xn[r] = (float)(g64[r] * om);
     } else {
@@ -1196,6 +1207,117 @@ __global__ __launch_bounds__(1024) void k_stop(int m, int nwp, const double* __r
     }
 }
 
+// Single unit (m = 1) with the retraction written here: stopping rule, ||g||^2
+// from the Gram partials and x_{k+1} = g / ||g|| (rows < p, FP32).  Wave 0
+// sums the objective and support-size partials (lane l the partials l, l + 64,
+// ..., then a fixed butterfly) while waves 1.. load their rows of g (kX1Rows
+// each: rows u, u + nt - 64, ... for u = t - 64), so that the latency of both
+// overlaps; rows past kX1Rows * (nt - 64), if any, are read afterwards.
+constexpr int kX1Rows = 22;   // 22 * 960 >= 20480, the largest p of the fused pass
+__global__ __launch_bounds__(1024) void k_stop_x1(int nwp, const double* __restrict__ fpart,
+                                                  const int* __restrict__ nnzpart,
+                                                  double* __restrict__ trace,
+                                                  double* __restrict__ coef,
+                                                  double* __restrict__ fcomp,
+                                                  const double* __restrict__ gram, int ngram,
+                                                  int exact, const double* __restrict__ g64,
+                                                  float* __restrict__ Xn, int p,
+                                                  Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ StopShared ss;
+    __shared__ double red[16];
+    __shared__ double fs[2];
+    const int t = threadIdx.x, nt = blockDim.x, lane = t & 63;
+    const int u0 = t - 64, ust = nt - 64;
+    double gx[kX1Rows];
+    if (t < 64) {
+        double sf;
+        int sc;
+        slice_sum<8>(fpart, nnzpart, nwp, lane, 64, &sf, &sc);
+        for (int o = 32; o >= 1; o >>= 1) {
+            sf += __shfl_xor(sf, o, 64);
+            sc += __shfl_xor(sc, o, 64);
+        }
+        if (lane == 0) {
+            fs[0] = sf;
+            fs[1] = (double)sc;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kX1Rows; ++i) {
+            const int r = u0 + i * ust;
+            gx[i] = r < p ? g64[r] : 0.0;
+        }
+    }
+    __syncthreads();
+    const int k = ctrl->k;
+    if (stop_rule<true>(1, nwp, fpart, nnzpart, trace, fcomp, exact, ctrl, ss, fs)) return;
+    const double om = unit_scale(gram, ngram, coef, k, ctrl, red);
+    if (om != 0.0) {
+        if (t >= 64) {
+#pragma unroll
+            for (int i = 0; i < kX1Rows; ++i) {
+                const int r = u0 + i * ust;
+                if (r < p) Xn[r] = (float)(gx[i] * om);
+            }
+        }
+        for (int r = kX1Rows * ust + t; r < p; r += nt) Xn[r] = (float)(g64[r] * om);
+    }
+    if (t == 0 && !ctrl->done) {
+        ctrl->k = k + 1;
+        ctrl->nact = 0;
+    }
+}
+
+// m = 1 after the fused pass (one partial g per workgroup, every one written):
+// g = the sum of the partials and the Gram partials of ||g||^2 in one launch.
+// A workgroup owns kRm1Rows rows; wave sl of its kRm1Slices waves sums the
+// contiguous range sl of the partials (all loads of a batch issued together),
+// wave 0 adds the ranges in order, writes g (FP64) and the block's sum of
+// g_r^2 (a fixed butterfly) as gram[3 * block].  Rows past p re-read row
+// p - 1 and are dropped.
+constexpr int kRm1Slices = 16, kRm1Batch = 32;
+__global__ __launch_bounds__(1024) void k_reduce_m1(const float* __restrict__ gpart, int npart,
+                                                    int ldx, int p, double* __restrict__ g64,
+                                                    double* __restrict__ gram,
+                                                    const Ctrl* __restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double part[kRm1Slices][kRm1Rows];
+    const int t = threadIdx.x, rr = t & 63, sl = t >> 6;
+    const int r = blockIdx.x * kRm1Rows + rr;
+    const int rc = r < p ? r : p - 1;
+    const int c0 = (int)((int64_t)npart * sl / kRm1Slices);
+    const int c1 = (int)((int64_t)npart * (sl + 1) / kRm1Slices);
+    double s = 0.0;
+    for (int c = c0; c < c1; c += kRm1Batch) {
+        float v[kRm1Batch];
+#pragma unroll
+        for (int u = 0; u < kRm1Batch; ++u) {
+            const int cu = c + u < c1 ? c + u : c1 - 1;
+            v[u] = gpart[(size_t)cu * ldx + rc];
+        }
+#pragma unroll
+        for (int u = 0; u < kRm1Batch; ++u) s += (c + u < c1) ? (double)v[u] : 0.0;
+    }
+    part[sl][rr] = s;
+    __syncthreads();
+    if (sl == 0) {
+        double g = part[0][rr];
+#pragma unroll
+        for (int u = 1; u < kRm1Slices; ++u) g += part[u][rr];
+        if (r < p) g64[r] = g;
+        const double g2 = wave_sum_d(r < p ? g * g : 0.0);
+        if (rr == 0) gram[(size_t)3 * blockIdx.x] = g2;
+    }
+}
+
+hipError_t launch_reduce_m1(const Plan& pl, const float* gpart, double* g64, double* gram,
+                            const Ctrl* ctrl, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_m1, dim3((unsigned)((pl.p + kRm1Rows - 1) / kRm1Rows)), dim3(1024), 0, st,
+                       gpart, pl.npart, pl.ldx, (int)pl.p, g64, gram, ctrl);
+    return hipGetLastError();
+}
+
 hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                        const double* gram, double* trace, double* coef, double* fcomp,
                        double* vprev, const double* g64, float* Xn, double* fsum, Ctrl* ctrl,
@@ -1205,15 +1327,21 @@ hipError_t launch_stop(const Plan& pl, const double* fpart, const int* nnzpart,
                                        fpart, nnzpart, fsum);
         if (e != hipSuccess) return e;
     }
+    if (pl.m == 1 && Xn) {
+        hipLaunchKernelGGL(k_stop_x1, dim3(1), dim3(1024), 0, st, pl.nwave_part, fpart, nnzpart,
+                           trace, coef, fcomp, gram, pl.gram_blocks, pl.exact, g64, Xn,
+                           (int)pl.p, ctrl);
+        return hipGetLastError();
+    }
     // threads: the Jacobi steps of m = 64 have 32 x 32 blocks plus 64 x 32 rotated pairs of V;
-    // m = 1 needs no eigen-solver: one wave makes every barrier free, four write x
-    const int threads = pl.m > 1 ? jacobi_threads(pl.m) : Xn ? 256 : 64;
+    // m = 1 needs no eigen-solver: one wave makes every barrier free
+    const int threads = pl.m > 1 ? jacobi_threads(pl.m) : 64;
     const size_t shm = (pl.m > 1) ? (size_t)3 * (pl.m + (pl.m & 1)) * LDM * sizeof(double) : 0;
     static const bool lds_once = (set_lds_limit((const void*)k_stop), true);
     (void)lds_once;
     hipLaunchKernelGGL(k_stop, dim3(1), dim3(threads), shm, st, pl.m, pl.nwave_part, fpart,
                        nnzpart, vprev, trace, coef, fcomp, gram, pl.gram_blocks, pl.exact,
-                       g64, pl.m == 1 ? Xn : nullptr, (int)pl.p, fsum, ctrl);
+                       g64, nullptr, (int)pl.p, fsum, ctrl);
     return hipGetLastError();
 }
 
