@@ -122,7 +122,8 @@ size_t gpspca_workspace_bytes(const gpspca_matrix* A, int form, int m, int max_i
  *  obj_trace  host, max_iter doubles: F_0 .. F_{n_iter-1}.
  *  n_iter     host: number of passes made.
  * The iteration stops at pass k when F_k = 0, when the tolerance test holds, or
- * when k + 1 = max_iter.  Synchronizes `stream` before returning.
+ * when k + 1 = max_iter.  After an error status (< 0) the device outputs hold
+ * unspecified values.  Synchronizes `stream` before returning.
  */
 int gpspca_solve(const gpspca_matrix* A, int form, int m, double gamma, const double* mu,
                  const float* X0, double tol, int max_iter,

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -683,11 +684,32 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
 
 struct Pinned {
     Ctrl* snap = nullptr;
+    void* stage = nullptr;     // outputs read back with the control block
+    size_t stage_cap = 0;
     ~Pinned() {
         if (snap) (void)hipHostFree(snap);
+        if (stage) (void)hipHostFree(stage);
     }
 };
 static thread_local Pinned t_pinned;
+
+// Pinned host memory of at least `bytes` (64 KB at least, kept for the thread's
+// later calls, so that a solve allocates it only when it needs more).
+static int pinned_stage(size_t bytes, void** out) {
+    if (t_pinned.stage_cap < bytes) {
+        size_t cap = (size_t)64 << 10;
+        while (cap < bytes) cap *= 2;
+        if (t_pinned.stage) GPSPCA_HIP(hipHostFree(t_pinned.stage));
+        t_pinned.stage = nullptr;
+        t_pinned.stage_cap = 0;
+        void* p = nullptr;
+        GPSPCA_HIP(hipHostMalloc(&p, cap, hipHostMallocDefault));
+        t_pinned.stage = p;
+        t_pinned.stage_cap = cap;
+    }
+    *out = t_pinned.stage;
+    return GPSPCA_OK;
+}
 
 static int pinned_ctrl(Ctrl** out) {
     if (!t_pinned.snap) {
@@ -752,10 +774,13 @@ static int capture_pair(const Plan& pl, const PassParams& pp, const Ptrs& P, Pas
 // enqueued at once).  Pairs of passes go through a captured graph when the
 // solve is long enough to repay the capture (and kernel timing is off).
 // Returns the final control block in *fin.
+// tail: work enqueued after the last pass and before the control block is read
+// back (the solve's outputs), so that the host waits once.
 // noalloc: no graph (instantiation allocates), no launch timing (events), and
 // the control block is read into the caller's stack instead of pinned memory.
 static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int max_iter,
-                      double tol, hipStream_t st, Ctrl* fin, bool noalloc = false) {
+                      double tol, hipStream_t st, Ctrl* fin, bool noalloc = false,
+                      const std::function<int()>* tail = nullptr) {
     TimedLaunches tl;
     if (!noalloc) {
         std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -789,6 +814,10 @@ static int run_passes(const Plan& pl, const PassParams& pp, const Ptrs& P, int m
         GPSPCA_HIP(hipStreamSynchronize(st));
         if (snap->done) break;
         chunk = std::min(chunk * 2, 32);
+    }
+    if (tail) {
+        rc = (*tail)();
+        if (rc) return rc;
     }
     GPSPCA_HIP(hipMemcpyAsync(snap, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     GPSPCA_HIP(hipStreamSynchronize(st));
@@ -844,13 +873,30 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
     pp.nact = &P.ctrl->nact;
     const int64_t words = cdiv(A->n, 32);
 
-    GPSPCA_HIP(launch_ctrl_reset(P.ctrl, max_iter, tol, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad, st));
-    GPSPCA_HIP(launch_fill_zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad, st));
-    if (path) GPSPCA_HIP(launch_fill_zero(P.pstate, sizeof(PathState) * m, st));
+    // one launch resets the control block, clears the X buffers (their padding
+    // rows and components stay zero), their interleaved copies (written by the
+    // start's retraction and by every pass's), the path state and, for
+    // frozen-support passes, S and the activity flags, and loads X0
+    const bool il = pl.use_mfma || pl.use_q;
+    StartZero z{};
+    auto zero = [&](void* ptr, size_t bytes) {
+        z.ptr[z.n] = static_cast<uint32_t*>(ptr);
+        z.words[z.n] = bytes / 4;
+        ++z.n;
+    };
+    zero(P.x[0], sizeof(float) * pl.ldx * pl.mpad);
+    zero(P.x[1], sizeof(float) * pl.ldx * pl.mpad);
+    if (il) {
+        zero(P.xil[0], pl.xil_bytes);
+        zero(P.xil[1], pl.xil_bytes);
+    }
+    if (path) zero(P.pstate, sizeof(PathState) * m);
     if (mask) {
-        GPSPCA_HIP(launch_fill_zero(P.S, sizeof(float) * (size_t)A->n * m, st));
-        GPSPCA_HIP(launch_fill_zero(P.act, align_up((size_t)A->n, 4), st));
+        zero(P.S, sizeof(float) * (size_t)A->n * m);
+        zero(P.act, align_up((size_t)A->n, 4));
+    }
+    GPSPCA_HIP(launch_start(P.ctrl, max_iter, tol, z, m, (int)A->p, X0, (int)A->p, P.g64, st));
+    if (mask) {
         GPSPCA_HIP(launch_mask_list(mask, words, m, A->n, P.list, P.nlist, st));
         pp.list = P.list;
         pp.nlist = P.nlist;
@@ -859,8 +905,10 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
     }
 
     // start: project X0 (or the default start) onto the feasible set
+    // the retraction that ends each start writes X_0 and, for the matrix-core
+    // kernels, its interleaved copy (except the broadcast start, copied after)
+    float* xil0 = il ? P.xil[0] : nullptr;
     if (X0) {
-        GPSPCA_HIP(launch_load_g64(pl, X0, (int)A->p, P.g64, st));
         if (path) {
             // every column normalized on its own
             GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 2, P.g64, P.gram, P.ctrl, st));
@@ -869,7 +917,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
             GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
             GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
         }
-        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], xil0, P.ctrl, st));
     } else if (path && multistart) {
         // problem j starts at the column of the j-th largest norm (ties to the
         // lower index), normalized on its own
@@ -879,7 +927,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
         GPSPCA_HIP(launch_gather(pl, pp, P.idx, P.g64, st));
         GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 2, P.g64, P.gram, P.ctrl, st));
         GPSPCA_HIP(launch_project_diag(pl, P.gram, P.coef, P.ctrl, st));
-        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], xil0, P.ctrl, st));
     } else if (path) {
         // all columns start at the normalized column of largest norm
         Plan p1;
@@ -898,6 +946,7 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
         GPSPCA_HIP(launch_project(p1, P.gram, P.coef, P.ctrl, st));
         GPSPCA_HIP(launch_apply(p1, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
         GPSPCA_HIP(launch_bcast_col0(pl, P.x[0], st));
+        if (il) GPSPCA_HIP(launch_x_interleave(pl, P.x[0], P.xil[0], st));
     } else {
         // the m columns of largest norm (ties to the lower index)
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2LL * ncu, cdiv(A->n, 16)));
@@ -906,33 +955,51 @@ int solve_core(const gpspca_matrix* A, int form, int m, double gamma, const doub
         GPSPCA_HIP(launch_gather(pl, pp, P.idx, P.g64, st));
         GPSPCA_HIP(launch_gram(pl, nullptr, 0, nullptr, 0, P.g64, P.gram, P.ctrl, st));
         GPSPCA_HIP(launch_project(pl, P.gram, P.coef, P.ctrl, st));
-        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], nullptr, P.ctrl, st));
+        GPSPCA_HIP(launch_apply(pl, P.g64, P.x[1], P.coef, P.x[0], xil0, P.ctrl, st));
     }
 
-    if (pl.use_mfma || pl.use_q) {
-        GPSPCA_HIP(launch_fill_zero(P.xil[1], pl.xil_bytes, st));
-        GPSPCA_HIP(launch_x_interleave(pl, P.x[0], P.xil[0], st));
+    // outputs, enqueued behind the passes: the copy of X takes the last
+    // iterate by the pass count on the device, and the trace and path state
+    // come back into pinned memory with the control block (one wait in all)
+    const size_t trace_n = obj_trace ? (path ? (size_t)m * max_iter : (size_t)max_iter) : 0;
+    const size_t stage_bytes = sizeof(double) * trace_n + (path ? sizeof(PathState) * m : 0);
+    void* stage = nullptr;
+    if (!noalloc && stage_bytes) {
+        rc = pinned_stage(stage_bytes, &stage);
+        if (rc) return rc;
     }
-
+    char* const stage_ps = static_cast<char*>(stage) + sizeof(double) * trace_n;
+    const std::function<int()> outputs = [&]() -> int {
+        GPSPCA_HIP(launch_copy_x_last(pl, P.x[0], P.x[1], P.ctrl, X, st));
+        GPSPCA_HIP(launch_finalize(pl, P.S, P.fin, P.invn, Z, support, st));
+        if (stage && trace_n)
+            GPSPCA_HIP(hipMemcpyAsync(stage, P.trace, sizeof(double) * trace_n,
+                                      hipMemcpyDeviceToHost, st));
+        if (stage && path)
+            GPSPCA_HIP(hipMemcpyAsync(stage_ps, P.pstate, sizeof(PathState) * m,
+                                      hipMemcpyDeviceToHost, st));
+        return GPSPCA_OK;
+    };
     Ctrl fin;
-    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin, noalloc != 0);
+    rc = run_passes(pl, pp, P, max_iter, tol, st, &fin, noalloc != 0, &outputs);
     if (rc) return rc;
     if (fin.status < 0) return fail(fin.status, status_text(fin.status));
     if (fin.n_iter < 1) return fail(GPSPCA_EDEVICE, "solve ended without a pass");
 
-    const float* Xf = P.x[(fin.n_iter - 1) & 1];
-    GPSPCA_HIP(launch_copy_x(pl, Xf, X, st));
-    GPSPCA_HIP(launch_finalize(pl, P.S, P.fin, P.invn, Z, support, st));
     std::vector<PathState> ps(path ? m : 0);
-    if (path)
-        GPSPCA_HIP(hipMemcpyAsync(ps.data(), P.pstate, sizeof(PathState) * m,
-                                  hipMemcpyDeviceToHost, st));
-    if (obj_trace) {
-        const size_t cnt = path ? (size_t)m * max_iter : (size_t)fin.n_iter;
-        GPSPCA_HIP(hipMemcpyAsync(obj_trace, P.trace, sizeof(double) * cnt,
-                                  hipMemcpyDeviceToHost, st));
+    const size_t cnt = path ? (size_t)m * max_iter : (size_t)fin.n_iter;
+    if (stage) {
+        if (obj_trace) std::memcpy(obj_trace, stage, sizeof(double) * cnt);
+        if (path) std::memcpy(ps.data(), stage_ps, sizeof(PathState) * m);
+    } else if (path || obj_trace) {
+        if (path)
+            GPSPCA_HIP(hipMemcpyAsync(ps.data(), P.pstate, sizeof(PathState) * m,
+                                      hipMemcpyDeviceToHost, st));
+        if (obj_trace)
+            GPSPCA_HIP(hipMemcpyAsync(obj_trace, P.trace, sizeof(double) * cnt,
+                                      hipMemcpyDeviceToHost, st));
+        GPSPCA_HIP(hipStreamSynchronize(st));
     }
-    GPSPCA_HIP(hipStreamSynchronize(st));
     if (!path) {
         if (n_iter) *n_iter = fin.n_iter;
         if (fin.status != GPSPCA_OK)

@@ -190,6 +190,16 @@ hipError_t launch_corr_qw(const Plan& pl, const PassParams& pp, const float* X, 
 // reductions, retraction, stop test (k_reduce.hip)
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t st);
 hipError_t launch_ctrl_reset(Ctrl* ctrl, int max_iter, double tol, hipStream_t st);
+// Buffers that the start of a solve clears (whole 4-byte words).
+struct StartZero {
+    uint32_t* ptr[8];
+    size_t words[8];
+    int n;
+};
+// One launch: control block reset, the StartZero buffers cleared, and, with X0
+// given (device p x m, leading dim ldx0), g64 = X0 in FP64.
+hipError_t launch_start(Ctrl* ctrl, int max_iter, double tol, const StartZero& z, int m, int p,
+                        const float* X0, int ldx0, double* g64, hipStream_t st);
 hipError_t launch_reduce_partials(const Plan& pl, const float* gpart, const int* touched,
                                   double* l1, const Ctrl* ctrl, hipStream_t st);
 hipError_t launch_gram(const Plan& pl, const double* l1, int nsplit, const float* X,
@@ -247,6 +257,10 @@ hipError_t launch_gather(const Plan& pl, const PassParams& pp, const int64_t* id
 hipError_t launch_finalize(const Plan& pl, const float* S, double* fin, double* invn, float* Z,
                            uint32_t* support, hipStream_t st);
 hipError_t launch_copy_x(const Plan& pl, const float* Xint, float* Xout, hipStream_t st);
+// X_{n_iter - 1} (Xa when n_iter is odd, Xb when even, read from ctrl on the
+// device) -> Xout (leading dim p)
+hipError_t launch_copy_x_last(const Plan& pl, const float* Xa, const float* Xb, const Ctrl* ctrl,
+                              float* Xout, hipStream_t st);
 
 // Offsets of the coefficient block (doubles) written by the stop / projection kernels.
 inline size_t coef_omega(int m) { return 0; }

@@ -278,6 +278,28 @@ __global__ void k_copy_x(int m, int p, int ldx, const float* __restrict__ Xi, fl
     Xo[e] = Xi[(size_t)j * ldx + r];
 }
 
+// The same from the iterate of the last pass, X_{n_iter - 1}, which sits in
+// Xa (n_iter odd) or Xb (n_iter even); nothing when no pass was made.
+__global__ void k_copy_x_last(int m, int p, int ldx, const float* __restrict__ Xa,
+                              const float* __restrict__ Xb, const Ctrl* __restrict__ ctrl,
+                              float* __restrict__ Xo) {
+    const int ni = ctrl->n_iter;
+    if (ni < 1) return;
+    const float* Xi = ((ni - 1) & 1) ? Xb : Xa;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)m * p) return;
+    const int j = (int)(e / p), r = (int)(e % p);
+    Xo[e] = Xi[(size_t)j * ldx + r];
+}
+
+hipError_t launch_copy_x_last(const Plan& pl, const float* Xa, const float* Xb, const Ctrl* ctrl,
+                              float* Xout, hipStream_t st) {
+    const int64_t ne = (int64_t)pl.m * pl.p;
+    hipLaunchKernelGGL(k_copy_x_last, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pl.m,
+                       (int)pl.p, pl.ldx, Xa, Xb, ctrl, Xout);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy_x(const Plan& pl, const float* Xint, float* Xout, hipStream_t st) {
     const int64_t ne = (int64_t)pl.m * pl.p;
     hipLaunchKernelGGL(k_copy_x, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, pl.m,

@@ -46,6 +46,52 @@ hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t st) {
     return hipGetLastError();
 }
 
+__device__ __forceinline__ void ctrl_reset_fields(Ctrl* ctrl, int max_iter, double tol) {
+    ctrl->k = 0;
+    ctrl->done = 0;
+    ctrl->status = GPSPCA_OK;
+    ctrl->n_iter = 0;
+    ctrl->ndead = 0;
+    ctrl->degenerate_seen = 0;
+    ctrl->max_iter = max_iter;
+    ctrl->warm = 0;
+    ctrl->nact = 0;
+    ctrl->tol = tol;
+    ctrl->last_F = 0.0;
+}
+
+// Start of a solve in one launch: the control block reset (thread 0 of
+// workgroup 0), the listed buffers cleared, and g64[j p + r] = X0[j ldx0 + r]
+// in FP64 for j < m (m = 0: no X0).
+__global__ __launch_bounds__(256) void k_start(Ctrl* ctrl, int max_iter, double tol, StartZero z,
+                                               int m, int p, const float* __restrict__ X0,
+                                               int ldx0, double* __restrict__ g64) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset_fields(ctrl, max_iter, tol);
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t step = (size_t)gridDim.x * blockDim.x;
+    for (int b = 0; b < z.n; ++b) {
+        uint32_t* ptr = z.ptr[b];
+        const size_t w = z.words[b];
+        for (size_t i = i0; i < w; i += step) ptr[i] = 0u;
+    }
+    const size_t ne = (size_t)m * p;
+    for (size_t e = i0; e < ne; e += step) {
+        const size_t j = e / p, r = e % p;
+        g64[e] = (double)X0[j * ldx0 + r];
+    }
+}
+
+hipError_t launch_start(Ctrl* ctrl, int max_iter, double tol, const StartZero& z, int m, int p,
+                        const float* X0, int ldx0, double* g64, hipStream_t st) {
+    size_t most = X0 ? (size_t)m * p : 0;
+    for (int i = 0; i < z.n; ++i) most = z.words[i] > most ? z.words[i] : most;
+    size_t blocks = (most + 255) / 256;
+    blocks = blocks < 1 ? 1 : blocks > 4096 ? 4096 : blocks;
+    hipLaunchKernelGGL(k_start, dim3((unsigned)blocks), dim3(256), 0, st, ctrl, max_iter, tol, z,
+                       X0 ? m : 0, p, X0, ldx0, g64);
+    return hipGetLastError();
+}
+
 __global__ void k_ctrl_reset(Ctrl* ctrl, int max_iter, double tol) {
     if (threadIdx.x == 0) {
         ctrl->k = 0;
