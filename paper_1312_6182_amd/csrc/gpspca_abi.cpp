@@ -46,6 +46,13 @@ int fail(int code, const std::string& msg) {
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// GPSPCA_MFMA_BALANCE=0 turns the balanced partition of the matrix-core
+// correlation off (every wave then takes whole tiles only).
+static bool mfma_balance_enabled() {
+    const char* e = std::getenv("GPSPCA_MFMA_BALANCE");
+    return !(e && e[0] == '0');
+}
+
 // ---------------------------------------------------------------- device info
 static int device_cus(int* out) {
     static std::mutex mu;
@@ -359,6 +366,23 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->fin_grid = (int)std::max<int64_t>(1, cdiv(cdiv(A->n, 32), 256 / std::max(1, m)));
     pl->topm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(A->n, 1024)));
 
+    // balanced partition of the FP32 matrix-core correlation (2 stages of 8
+    // tiles, one component group): when the waves do not divide the tiles,
+    // each takes q whole tiles and an equal row share of the leftover ones
+    pl->bal = pl->bal_q = pl->bal_rem = 0;
+    if (pl->use_mfma && !pl->use_rd && !pl->use_x3 && !pl->use_wg && !pl->use_mv &&
+        !pl->use_q && !pl->use_qw && !pl->use_vx && !pl->fused_m1 && !pl->restricted &&
+        m <= 16 && pl->mfma_stages == 8 && A->p >= 64 && mfma_balance_enabled()) {
+        const int64_t ntile = cdiv(A->n, 16), W = pl->corr_grid;
+        const int64_t q = ntile / W, rem = ntile % W;
+        if (rem > 0 && q >= 1 && q + 1 <= 8) {
+            pl->bal = 1;
+            pl->bal_q = (int)q;
+            pl->bal_rem = (int)rem;
+            pl->nwave_part = (int)(W + rem);
+        }
+    }
+
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -393,6 +417,7 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->o_xil0 = take(xil ? pl->xil_bytes : 1);
     pl->o_xil1 = take(xil ? pl->xil_bytes : 1);
     pl->o_fsum = take(sizeof(double) * 2 * M);   // per-component objective and support sums
+    pl->o_xpart = take(pl->bal ? sizeof(float) * 512 * (size_t)pl->corr_grid : 1);
     pl->total = o;
 }
 
@@ -457,6 +482,7 @@ static size_t workspace_all(const gpspca_matrix* A, int form, int m, int max_ite
 }
 
 struct Ptrs {
+    float* xpart;
     Ctrl* ctrl;
     double* trace;
     float* x[2];
@@ -514,6 +540,7 @@ static Ptrs carve(const Plan& pl, void* ws) {
     P.xil[0] = reinterpret_cast<float*>(b + pl.o_xil0);
     P.xil[1] = reinterpret_cast<float*>(b + pl.o_xil1);
     P.fsum = reinterpret_cast<double*>(b + pl.o_fsum);
+    P.xpart = reinterpret_cast<float*>(b + pl.o_xpart);
     return P;
 }
 
@@ -641,7 +668,7 @@ static int enqueue_pass(const Plan& pl, const PassParams& pp, const Ptrs& P, int
                                       P.ctrl, st));
         else if (pl.use_mfma)
             GPSPCA_HIP(launch_corr_mfma(pl, pp, Xk, P.xil[k & 1], P.S, P.act, P.fpart, P.nnzpart,
-                                        P.ctrl, st));
+                                        P.xpart, P.ctrl, st));
         else
             GPSPCA_HIP(launch_corr(pl, pp, Xk, P.S, P.act, P.fpart, P.nnzpart, P.ctrl, st));
         GPSPCA_HIP(tl.end(st));

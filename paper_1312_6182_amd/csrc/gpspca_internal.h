@@ -59,6 +59,15 @@ struct PassParams {
     int* nact;             // &Ctrl::nact: active-column count of the pass
 };
 
+// Balanced partition of the FP32 matrix-core correlation: every wave owns q
+// whole tiles of 16 columns, and the rem leftover tiles are split by rows over
+// all waves; xpart holds the partial sums of those splits (2 x 256 floats per
+// wave), and the objective partials have nwp = waves + rem slots per component.
+struct BalArgs {
+    float* xpart;
+    int q, rem, nwp;
+};
+
 // A configuration of the correlation kernel: the autotuner's unit of choice.
 enum TuneKernel { kTuneDefault = 0, kTuneMfma = 1, kTuneVx = 2, kTuneValu = 3, kTuneRd = 4,
                   kTuneWg = 5, kTuneRd128 = 6, kTuneX3 = 7, kTuneQw = 8 };
@@ -97,6 +106,8 @@ struct Plan {
     int use_qw;            // ... by four-wave workgroups that share each X stage
     int restricted;        // frozen-support passes over a column list (VALU correlation)
     int use_mfma;          // block correlation on the matrix cores (LDS DMA staging)
+    int bal, bal_q, bal_rem; // ... balanced partition: q whole tiles per wave, rem leftover
+                           // tiles split by rows (k_corr_bal_fix finishes them)
     int mfma_stages;       // stages in flight of the matrix-core kernels (FP32 and 16/8-bit)
     int waves_per_cu;      // resident matrix-core workgroups per CU
     int use_rd;            // matrix-core correlation with register-direct operand loads
@@ -114,7 +125,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t o_ctrl, o_trace, o_x0, o_x1, o_s, o_act, o_gpart, o_touched, o_fpart, o_nnzpart,
         o_l1, o_g64, o_gram, o_coef, o_norms, o_cand_v, o_cand_i, o_idx, o_fin, o_invn, o_fcomp,
-        o_pstate, o_list, o_xil0, o_xil1, o_fsum;
+        o_pstate, o_list, o_xil0, o_xil1, o_fsum, o_xpart;
     size_t total;
 };
 
@@ -163,9 +174,8 @@ extern thread_local KernelEvents g_kev;
     } while (0)
 
 hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
-                            float* S,
-                            uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
-                            hipStream_t st);
+                            float* S, uint8_t* act, double* fpart, int* nnzpart, float* xpart,
+                            const Ctrl* ctrl, hipStream_t st);
 hipError_t launch_backproj(const Plan& pl, const PassParams& pp, const float* S,
                            const uint8_t* act, float* gpart, int* touched, const Ctrl* ctrl,
                            hipStream_t st);

@@ -89,6 +89,14 @@ __device__ __forceinline__ bool threshold_m(bool l0, double mu, double gamma, fl
     return false;
 }
 
+// Balanced partition: a wave's row-split share of a leftover tile, the 16
+// columns from col over the stages s0 .. s1 - 1.  A wave has at most two, and
+// their stage ranges are disjoint.
+struct XPiece {
+    int64_t col;
+    int s0, s1;
+};
+
 }  // namespace
 
 // One chunk of NT tiles of 16 columns (NT <= 4) starting at column c0: stream
@@ -98,12 +106,20 @@ __device__ __forceinline__ bool threshold_m(bool l0, double mu, double gamma, fl
 // instruction per stage instead of two; lanes of components 8..15 read the
 // same LDS line as component lj - 8, whose products land in outputs that are
 // never stored.
-template <int NT, int J, int STAGES, int TMAX, bool HX = false>
+// BAL (balanced partition, 2 stages, J = 1): the chunk also streams the wave's
+// pieces of leftover tiles (xp[0 .. nxp-1]) as tile NT of the stages in their
+// ranges, and writes their partial sums (the accumulator layout, 1 KB each) to
+// xout[256 e ..].
+template <int NT, int J, int STAGES, int TMAX, bool HX = false, bool BAL_ = false>
 __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int64_t cend,
                                            uint32_t lbase, const float* const* xcol,
                                            const float* __restrict__ Xil, double* f_acc,
                                            int* nnz_acc, float* __restrict__ S,
-                                           uint8_t* __restrict__ act) {
+                                           uint8_t* __restrict__ act,
+                                           const XPiece* xp = nullptr, int nxp = 0,
+                                           float* __restrict__ xout = nullptr) {
+    constexpr bool BAL = BAL_ && NT < TMAX;   // a full chunk never carries pieces
+    static_assert(!BAL_ || (STAGES == 2 && J == 1), "pieces need 2 stages and one group");
     int nact_l = 0;   // active columns written by this lane
     static_assert(!HX || J == 1, "half X staging needs one component group");
     constexpr int AStage = TMAX * 16 * kQS * 16;   // A bytes per stage: TMAX tiles x 32 rows
@@ -132,6 +148,33 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
         col = (col < cend) ? col : cend - 1;
         acol[i] = pp.A + col * pp.lda;
     }
+    // pieces: DMA sources laid out as a tile of this chunk (instructions 0, 1
+    // of a tile have the swizzled quads aq[0], aq[1]); stage ranges
+    // (scalars, not arrays, so that nothing of this lands in scratch or LDS)
+    const float *xa00 = pp.A, *xa01 = pp.A, *xa10 = pp.A, *xa11 = pp.A;
+    int64_t xc0 = 0, xc1 = 0;
+    int xs00 = 0, xs10 = 0, xs01 = 0, xs11 = 0;   // stage range [xs0e, xs1e) of piece e
+    if constexpr (BAL) {
+        if (nxp > 0) { xc0 = xp[0].col; xs00 = xp[0].s0; xs10 = xp[0].s1; }
+        if (nxp > 1) { xc1 = xp[1].col; xs01 = xp[1].s0; xs11 = xp[1].s1; }
+        auto src = [&](int64_t base, int ii) {
+            int64_t col = base + (64 * ii + lane) / kQS;
+            col = (col < pp.n) ? col : pp.n - 1;
+            return pp.A + col * pp.lda;
+        };
+        xa00 = src(xc0, 0);
+        xa01 = src(xc0, 1);
+        xa10 = src(xc1, 0);
+        xa11 = src(xc1, 1);
+    }
+    // the piece streamed in stage st: 0, 1, or -1 (none)
+    auto xpiece = [&](int st) -> int {
+        if constexpr (BAL) {
+            if (st >= xs00 && st < xs10) return 0;
+            if (st >= xs01 && st < xs11) return 1;
+        }
+        return -1;
+    };
     auto issue = [&](int st) {
         const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
         const int q0 = kQS * st;
@@ -140,6 +183,16 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
             int q = q0 + aq[i];
             q = (q < nqf) ? q : nqf - 1;
             dma16(acol[i] + 4 * q, sb + 1024 * i);
+        }
+        if constexpr (BAL) {
+            const int e = xpiece(st);
+            if (e >= 0) {
+                int qa = q0 + aq[0], qb = q0 + aq[1];
+                qa = (qa < nqf) ? qa : nqf - 1;
+                qb = (qb < nqf) ? qb : nqf - 1;
+                dma16((e == 0 ? xa00 : xa10) + 4 * qa, sb + 1024 * (2 * NT));
+                dma16((e == 0 ? xa01 : xa11) + 4 * qb, sb + 1024 * (2 * NT + 1));
+            }
         }
         // X: 4 row quads x 16 components per instruction, one contiguous 1 KB
         // of the interleaved copy (rows past the full quads read the zero quad);
@@ -166,6 +219,7 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4m{0.f, 0.f, 0.f, 0.f};
+    f4m accx0 = f4m{0.f, 0.f, 0.f, 0.f}, accx1 = f4m{0.f, 0.f, 0.f, 0.f};
 
 #pragma unroll
     for (int s = 0; s < STAGES - 1; ++s)
@@ -184,18 +238,30 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
             else if (ahead == 1) wait_vmcnt<PER>();
             else wait_vmcnt<0>();
         } else {
-            if (ahead >= 1) wait_vmcnt<PER>();
-            else wait_vmcnt<0>();
+            // the next stage's instructions may stay in flight (two more when
+            // it streams a piece)
+            if (ahead >= 1) {
+                if (BAL && xpiece(st + 1) >= 0) wait_vmcnt<PER + 2>();
+                else wait_vmcnt<PER>();
+            } else {
+                wait_vmcnt<0>();
+            }
         }
         const uint32_t sb = lbase + (uint32_t)((st % STAGES) * StageBytes);
+        const int xe = xpiece(st);
         // both halves of the stage are read before the first multiplies, so the
         // second half's LDS latency hides behind the first half's MFMAs
-        f4m av[2][NT], xv[2][J];
+        f4m av[2][NT], xv[2][J], avx0, avx1;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
 #pragma unroll
             for (int t = 0; t < NT; ++t)
                 av[h][t] = lds_read16(sb + a_slot(16 * t + lj, 4 * h + lk));
+            if (BAL && xe >= 0) {
+                const f4m r = lds_read16(sb + a_slot(16 * NT + lj, 4 * h + lk));
+                if (h == 0) avx0 = r;
+                else avx1 = r;
+            }
 #pragma unroll
             for (int jb = 0; jb < J; ++jb)
                 xv[h][jb] = HX ? lds_read16(sb + AStage + 16u * (uint32_t)((4 * h + lk) * 8 + (lj & 7)))
@@ -208,6 +274,7 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                 for (int t = 0; t < NT; ++t) after_wait(av[0][t]);
 #pragma unroll
                 for (int jb = 0; jb < J; ++jb) after_wait(xv[0][jb]);
+                if (BAL && xe >= 0) after_wait(avx0);
             }
         }
         __builtin_amdgcn_sched_barrier(0);  // keep the second half's reads ahead of the MFMAs
@@ -219,12 +286,22 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                 for (int jb = 0; jb < J; ++jb)
                     acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                         av[0][t][tm], xv[0][jb][tm], acc[t][jb], 0, 0, 0);
+        if (BAL && xe == 0) {
+#pragma unroll
+            for (int tm = 0; tm < 4; ++tm)
+                accx0 = __builtin_amdgcn_mfma_f32_16x16x4f32(avx0[tm], xv[0][0][tm], accx0, 0, 0, 0);
+        } else if (BAL && xe == 1) {
+#pragma unroll
+            for (int tm = 0; tm < 4; ++tm)
+                accx1 = __builtin_amdgcn_mfma_f32_16x16x4f32(avx0[tm], xv[0][0][tm], accx1, 0, 0, 0);
+        }
         __builtin_amdgcn_sched_barrier(0);  // the first half's MFMAs stay before the wait
         wait_lgkm0();
 #pragma unroll
         for (int t = 0; t < NT; ++t) after_wait(av[1][t]);
 #pragma unroll
         for (int jb = 0; jb < J; ++jb) after_wait(xv[1][jb]);
+        if (BAL && xe >= 0) after_wait(avx1);
 #pragma unroll
         for (int tm = 0; tm < 4; ++tm)
 #pragma unroll
@@ -233,6 +310,15 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                 for (int jb = 0; jb < J; ++jb)
                     acc[t][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                         av[1][t][tm], xv[1][jb][tm], acc[t][jb], 0, 0, 0);
+        if (BAL && xe == 0) {
+#pragma unroll
+            for (int tm = 0; tm < 4; ++tm)
+                accx0 = __builtin_amdgcn_mfma_f32_16x16x4f32(avx1[tm], xv[1][0][tm], accx0, 0, 0, 0);
+        } else if (BAL && xe == 1) {
+#pragma unroll
+            for (int tm = 0; tm < 4; ++tm)
+                accx1 = __builtin_amdgcn_mfma_f32_16x16x4f32(avx1[tm], xv[1][0][tm], accx1, 0, 0, 0);
+        }
     }
 
     // ragged tail rows 4*nqf .. p-1 (p % 4 of them)
@@ -251,6 +337,27 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                         acc[t][jb][v] = __builtin_fmaf(a, xcol[jb][r], acc[t][jb][v]);
                 }
             }
+        // the piece whose range ends at the last stage takes the ragged rows
+        if constexpr (BAL) {
+            // (at most one piece ends at the last stage: the ranges are disjoint)
+            const int eo = (nxp > 0 && xs10 == nst) ? 0 : (nxp > 1 && xs11 == nst) ? 1 : -1;
+            if (eo >= 0) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int64_t col = (eo == 0 ? xc0 : xc1) + 4 * lk + v;
+                    col = (col < pp.n) ? col : pp.n - 1;
+                    const float* ac = pp.A + col * pp.lda;
+                    float sv = eo == 0 ? accx0[v] : accx1[v];
+                    for (int r = 4 * nqf; r < p; ++r) sv = __builtin_fmaf(ac[r], xcol[0][r], sv);
+                    if (eo == 0) accx0[v] = sv;
+                    else accx1[v] = sv;
+                }
+            }
+        }
+    }
+    if constexpr (BAL) {
+        if (nxp > 0) *reinterpret_cast<f4m*>(xout + 4 * lane) = accx0;
+        if (nxp > 1) *reinterpret_cast<f4m*>(xout + 256 + 4 * lane) = accx1;
     }
 
     // threshold, S, activity flags
@@ -289,14 +396,23 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
 // J: component blocks of 16 (m <= 16 J);  STAGES: stages in flight.
 // TMAX: tiles of 16 columns per chunk (4, or 8 to stage X once per wave when
 // a wave owns up to 128 columns).
-template <int J, int STAGES, int TMAX = 4, bool HX = false>
+// BAL: balanced partition (J = 1, 2 stages; bal.q + 1 <= TMAX).  Wave w owns
+// the whole tiles q w .. q (w + 1) - 1, and the rem = ntile - q W leftover
+// tiles at the end of A are split by row stages over all waves: their
+// rem x nst (tile, stage) pairs, tile-major, are cut into W near-equal
+// contiguous ranges, so every wave streams the same amount of A up to one
+// stage of one tile.  A wave's range covers at most two leftover tiles; their
+// partial sums go to bal.xpart[(2 w + piece) * 256 ..], and k_corr_bal_fix
+// finishes those tiles.  Without it, W not dividing ntile leaves some waves a
+// whole tile more than others, and they stream it at the end, alone.
+template <int J, int STAGES, int TMAX = 4, bool HX = false, bool BAL = false>
 __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __restrict__ X,
                                                   const float* __restrict__ Xil,
                                                   float* __restrict__ S,
                                                   uint8_t* __restrict__ act,
                                                   double* __restrict__ fpart,
                                                   int* __restrict__ nnzpart,
-                                                  const Ctrl* __restrict__ ctrl) {
+                                                  const Ctrl* __restrict__ ctrl, BalArgs bal) {
     if (ctrl->done) return;
     constexpr int XStageBytes = HX ? 1024 : J * 2 * 1024;
     constexpr int StageBytes = TMAX * 16 * kQS * 16 + XStageBytes;
@@ -311,8 +427,31 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
     // of tiles (+-1) and issues DMA and matrix-core work only for those, so no
     // wave streams clamped duplicate columns except in the last tile of A
     const int64_t ntile = (n + 15) / 16;
-    const int64_t cbeg = 16 * (ntile * w / W);
-    const int64_t cend = std::min<int64_t>(n, 16 * (ntile * (w + 1) / W));
+    int64_t cbeg = 16 * (ntile * w / W);
+    int64_t cend = std::min<int64_t>(n, 16 * (ntile * (w + 1) / W));
+    XPiece xp[2];
+    int nxp = 0;
+    if constexpr (BAL) {
+        cbeg = 16 * (int64_t)bal.q * w;
+        cend = std::min<int64_t>(n, 16 * (int64_t)bal.q * (w + 1));
+        const int64_t nst = ((pp.p >> 2) + kQS - 1) / kQS;
+        const int64_t R = (int64_t)bal.rem * nst;
+        const int64_t a = R * w / W, b = R * (w + 1) / W;
+        if (a < b) {
+            const int64_t ua = a / nst, t0 = (int64_t)bal.q * W;
+            xp[0].col = 16 * (t0 + ua);
+            xp[0].s0 = (int)(a - ua * nst);
+            xp[0].s1 = (int)std::min<int64_t>(b - ua * nst, nst);
+            nxp = 1;
+            if (b - ua * nst > nst) {
+                xp[1].col = 16 * (t0 + ua + 1);
+                xp[1].s0 = 0;
+                xp[1].s1 = (int)(b - (ua + 1) * nst);
+                nxp = 2;
+            }
+        }
+    }
+    const int64_t NW = BAL ? bal.nwp : W;   // objective partial slots per component
 
     const int lj = lane & 15;
 
@@ -329,7 +468,7 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
     for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * TMAX) {
         const int64_t left = cend - c0;
         const int nt = left >= 16 * TMAX ? TMAX : (int)((left + 15) / 16);
-#define GPSPCA_CH(NT) mfma_chunk<NT, J, STAGES, TMAX, HX>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act)
+#define GPSPCA_CH(NT) mfma_chunk<NT, J, STAGES, TMAX, HX, BAL>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act, xp, nxp, bal.xpart + (size_t)w * 512)
         if constexpr (TMAX == 8) {
             switch (nt) {
                 case 8: GPSPCA_CH(8); break;
@@ -363,10 +502,94 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
         c += __shfl_xor(c, 32, 64);
         const int comp = 16 * jb + lj;
         if (lane < 16 && comp < m) {
-            fpart[(int64_t)comp * W + w] = f;
-            nnzpart[(int64_t)comp * W + w] = c;
+            fpart[(int64_t)comp * NW + w] = f;
+            nnzpart[(int64_t)comp * NW + w] = c;
         }
     }
+}
+
+// Leftover tile u of the balanced partition (one wave per tile): the partial
+// sums of its row ranges, in the order of the ranges (ascending wave), then the
+// threshold, S, the activity flags and the objective partials at slot W + u,
+// as k_corr_mfma does for its own tiles (lane l: component l % 16, columns
+// 4 (l / 16) .. + 3 of the tile).
+__global__ __launch_bounds__(64) void k_corr_bal_fix(PassParams pp, BalArgs bal, int W,
+                                                     float* __restrict__ S,
+                                                     uint8_t* __restrict__ act,
+                                                     double* __restrict__ fpart,
+                                                     int* __restrict__ nnzpart,
+                                                     const Ctrl* __restrict__ ctrl) {
+    // the flag is read together with the partial sums (reading stale sums is
+    // harmless) and checked before anything is written
+    const int done = ctrl->done;
+    const int lane = threadIdx.x, lj = lane & 15, lk = lane >> 4;
+    const int64_t u = blockIdx.x;
+    const int64_t nst = ((pp.p >> 2) + kQS - 1) / kQS;
+    const int64_t R = (int64_t)bal.rem * nst;
+    const int64_t x0 = u * nst, x1 = x0 + nst;
+    // first range holding stage-tile x0: the largest w with R w / W <= x0
+    int64_t w = x0 * W / R;
+    while (w + 1 < W && R * (w + 1) / W <= x0) ++w;
+    while (w > 0 && R * w / W > x0) --w;
+    // 16 ranges per round: lane k % 16 works out where range w + k is stored
+    // (its loads of all 16 are then issued together and added in range order;
+    // ranges past the tile, or empty, re-read range 0 and are not added)
+    f4m acc = f4m{0.f, 0.f, 0.f, 0.f};
+    for (; w < W && R * w / W < x1; w += 16) {
+        const int64_t wk = w + lj;
+        const int64_t a = R * wk / W, b = R * (wk + 1) / W;
+        const int in_k = (wk < W && a < x1 && a < b) ? 1 : 0;
+        const int e_k = (a / nst == u) ? 0 : 1;   // 1: the range began in tile u - 1
+        const int at_k = in_k ? (int)((wk * 2 + e_k) * 64) : 0;   // in f4m units
+        f4m v[16];
+        int in[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            in[k] = __shfl(in_k, k, 64);
+            const int at = __shfl(at_k, k, 64);
+            v[k] = reinterpret_cast<const f4m*>(bal.xpart)[at + lane];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (in[k]) acc += v[k];
+    }
+    if (done) return;
+    const int64_t n = pp.n, c0 = 16 * ((int64_t)bal.q * W + u);
+    const int m = pp.m;
+    const bool l0 = pp.l0 != 0;
+    double f = 0.0;
+    int cnt = 0, nact_l = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t col = c0 + 4 * lk + v;
+        const bool cvalid = col < n;
+        bool any = false;
+        if (cvalid && lj < m) {
+            float sv;
+            double fv;
+            if (threshold_m(l0, pp.mu[lj], pp.gam[lj], acc[v], sv, fv)) {
+                f += fv;
+                cnt += 1;
+                any = true;
+            }
+            S[col * m + lj] = sv;
+        }
+        const uint64_t bal_bits = __ballot(any);
+        if (cvalid && lj == 0) {
+            const int fl = ((bal_bits >> (16 * lk)) & 0xFFFFull) ? 1 : 0;
+            act[col] = fl;
+            nact_l += fl;
+        }
+    }
+    f += __shfl_xor(f, 16, 64);
+    cnt += __shfl_xor(cnt, 16, 64);
+    f += __shfl_xor(f, 32, 64);
+    cnt += __shfl_xor(cnt, 32, 64);
+    if (lane < 16 && lj < m) {
+        fpart[(int64_t)lj * bal.nwp + W + u] = f;
+        nnzpart[(int64_t)lj * bal.nwp + W + u] = cnt;
+    }
+    add_active_count(nact_l, pp.nact);
 }
 
 // ---------------------------------------------------------------------------
@@ -1344,25 +1567,37 @@ static int corr_mfma_blocks_per_cu_query(int m, int stages) {
 }
 
 hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X, const float* Xil,
-                            float* S, uint8_t* act, double* fpart, int* nnzpart, const Ctrl* ctrl,
-                            hipStream_t st) {
+                            float* S, uint8_t* act, double* fpart, int* nnzpart, float* xpart,
+                            const Ctrl* ctrl, hipStream_t st) {
     const dim3 grid(pl.corr_grid), block(64);
-    if (pl.m <= 8 && pl.mfma_stages == 8 && mfma_half_x())
-        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+    BalArgs bal{xpart, pl.bal_q, pl.bal_rem, pl.nwave_part};
+    const bool hx = pl.m <= 8 && mfma_half_x();
+    if (pl.bal && hx && pl.mfma_stages == 8)
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8, true, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
+    else if (pl.bal && pl.m <= 16 && pl.mfma_stages == 8)
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8, false, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
+    else if (hx && pl.mfma_stages == 8)
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (pl.m <= 16 && pl.mfma_stages == 8)
-        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (pl.m <= 16 && pl.mfma_stages == 4)
-        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 4>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (pl.m <= 16 && pl.mfma_stages == 2)
-        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (pl.m <= 16)
-        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (pl.m <= 32 && pl.mfma_stages == 8)
-        GPSPCA_LAUNCH_TIMED((k_corr_mfma<2, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<2, 2, 8>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (pl.m <= 32)
-        GPSPCA_LAUNCH_TIMED((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<2, 3>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else
-        GPSPCA_LAUNCH_TIMED((k_corr_mfma<4, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl);
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<4, 2>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
+    if (pl.bal) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_corr_bal_fix, dim3(pl.bal_rem), dim3(64), 0, st, pp, bal,
+                           pl.corr_grid, S, act, fpart, nnzpart, ctrl);
+    }
     return hipGetLastError();
 }
 

@@ -183,3 +183,58 @@ def test_matrix_core_two_groups_stage_variants(gpu, stages, m, p, n, monkeypatch
     np.testing.assert_array_equal((S != 0)[~ties], (ref["S"] != 0)[~ties])
     assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
     np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
+
+
+# (form, m, p, n, waves per CU, lda extra): more tiles of 16 columns than
+# waves, so the matrix-core correlation takes q whole tiles per wave and splits
+# the leftover tiles by rows over all waves.  Covers q = 1, 2 and 7, components
+# in one half stage (m <= 8) and a full group (m = 16), ragged row quads, a
+# ragged last tile among the leftover ones, and matrices of 2 row stages.
+BAL_CASES = [
+    (O.BL1, 8, 300, 20000, 4, 0),
+    (O.BL0, 5, 301, 20000, 4, 3),
+    (O.BL1, 8, 67, 5000, 1, 1),
+    (O.BL1, 16, 1000, 9000, 2, 0),
+    (O.BL0, 3, 2000, 40003, 4, 0),
+    (O.BL1, 8, 129, 30277, 1, 3),
+]
+
+
+@pytest.mark.parametrize("balance", ["1", "0"])
+@pytest.mark.parametrize("case", BAL_CASES, ids=lambda c: f"{FORM_NAMES[c[0]]}-m{c[1]}-p{c[2]}-n{c[3]}-w{c[4]}")
+def test_matrix_core_balanced_partition(gpu, case, balance, monkeypatch):
+    """Leftover tiles split by rows over the waves (and, for comparison, the
+    partition in whole tiles only): one step and a 4-pass solve against the
+    oracle."""
+    import torch
+    form, m, p, n, wpc, extra = case
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    ntile = (n + 15) // 16
+    q, rem = divmod(ntile, ncu * wpc)
+    assert q >= 1 and rem > 0 and q + 1 <= 8   # the case exercises the split
+    monkeypatch.setenv("GPSPCA_CORR_KERNEL", "mfma")
+    monkeypatch.setenv("GPSPCA_MFMA_WAVES_PER_CU", str(wpc))
+    monkeypatch.setenv("GPSPCA_MFMA_BALANCE", balance)
+    print(f"\n[corr balanced={balance}] m={m} p={p} n={n} waves={ncu * wpc} q={q} rem={rem}",
+          flush=True)
+    A32, _, _ = W.planted_block(p, n, min(m, 4), 140 + m, k=40)
+    A64 = A32.astype(np.float64)
+    mu = np.linspace(1.0, 0.7, m)
+    X0 = fp32_round(O.init(A64, m)[0])
+    g0 = W.gamma_absolute(A64, is_l0(form), 0.02 if is_l0(form) else 0.05)
+    gamma = pick_gamma(A64, form, m, mu, X0, g0, iters=4)
+    Ad = to_device(A32, lda=(p + extra + 3) // 4 * 4)
+    ref = O.step(A64, form, X0, gamma, mu=mu)
+    out = gpu.step(Ad, form, x_to_device(X0), gamma, mu=list(mu))
+    ties = tie_mask(A64, X0, form, gamma, mu)
+    S = out.S.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal((S != 0)[~ties], (ref["S"] != 0)[~ties])
+    eb = corr_band(A64, X0) * mu[None, :]
+    assert np.all(np.abs(S - ref["S"]) <= eb + 1e-7 * np.abs(ref["S"]))
+    assert rel(out.G.cpu().numpy(), ref["G"]) <= 1e-5
+    np.testing.assert_allclose(out.f, ref["f"], rtol=1e-5)
+    assert list(out.nnz) == list(ref["nnz"]) or ties.any()
+    rs = O.solve(A64, form, m, gamma, mu=mu, X0=X0, tol=0.0, max_iter=4)
+    res = gpu.solve(Ad, form, m, gamma, mu=list(mu), X0=x_to_device(X0), tol=0.0, max_iter=4)
+    assert rel(res.X.cpu().numpy(), rs["X"]) <= 1e-5
+    np.testing.assert_allclose(res.trace, rs["trace"], rtol=1e-5)
