@@ -367,12 +367,12 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->topm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(A->n, 1024)));
 
     // balanced partition of the FP32 matrix-core correlation (2 stages of 8
-    // tiles, one component group): when the waves do not divide the tiles,
+    // tiles, one or two component groups): when the waves do not divide the tiles,
     // each takes q whole tiles and an equal row share of the leftover ones
     pl->bal = pl->bal_q = pl->bal_rem = 0;
     if (pl->use_mfma && !pl->use_rd && !pl->use_x3 && !pl->use_wg && !pl->use_mv &&
         !pl->use_q && !pl->use_qw && !pl->use_vx && !pl->fused_m1 && !pl->restricted &&
-        m <= 16 && pl->mfma_stages == 8 && A->p >= 64 && mfma_balance_enabled()) {
+        m <= 32 && pl->mfma_stages == 8 && A->p >= 64 && mfma_balance_enabled()) {
         const int64_t ntile = cdiv(A->n, 16), W = pl->corr_grid;
         const int64_t q = ntile / W, rem = ntile % W;
         if (rem > 0 && q >= 1 && q + 1 <= 8) {
@@ -417,7 +417,7 @@ static void make_plan(const gpspca_matrix* A, int form, int m, int max_iter, int
     pl->o_xil0 = take(xil ? pl->xil_bytes : 1);
     pl->o_xil1 = take(xil ? pl->xil_bytes : 1);
     pl->o_fsum = take(sizeof(double) * 2 * M);   // per-component objective and support sums
-    pl->o_xpart = take(pl->bal ? sizeof(float) * 512 * (size_t)pl->corr_grid : 1);
+    pl->o_xpart = take(pl->bal ? sizeof(float) * 512 * (size_t)(m <= 16 ? 1 : 2) * pl->corr_grid : 1);
     pl->total = o;
 }
 

@@ -62,7 +62,8 @@ struct PassParams {
 // Balanced partition of the FP32 matrix-core correlation: every wave owns q
 // whole tiles of 16 columns, and the rem leftover tiles are split by rows over
 // all waves; xpart holds the partial sums of those splits (2 x 256 floats per
-// wave), and the objective partials have nwp = waves + rem slots per component.
+// wave and component group), and the objective partials have nwp = waves + rem
+// slots per component.
 struct BalArgs {
     float* xpart;
     int q, rem, nwp;

@@ -106,10 +106,10 @@ struct XPiece {
 // instruction per stage instead of two; lanes of components 8..15 read the
 // same LDS line as component lj - 8, whose products land in outputs that are
 // never stored.
-// BAL (balanced partition, 2 stages, J = 1): the chunk also streams the wave's
-// pieces of leftover tiles (xp[0 .. nxp-1]) as tile NT of the stages in their
-// ranges, and writes their partial sums (the accumulator layout, 1 KB each) to
-// xout[256 e ..].
+// BAL (balanced partition, 2 stages): the chunk also streams the wave's pieces
+// of leftover tiles (xp[0 .. nxp-1]) as tile NT of the stages in their ranges,
+// and writes their partial sums (the accumulator layout, 1 KB per piece and
+// component group) to xout[256 (J e + jb) ..].
 template <int NT, int J, int STAGES, int TMAX, bool HX = false, bool BAL_ = false>
 __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int64_t cend,
                                            uint32_t lbase, const float* const* xcol,
@@ -119,7 +119,7 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                                            const XPiece* xp = nullptr, int nxp = 0,
                                            float* __restrict__ xout = nullptr) {
     constexpr bool BAL = BAL_ && NT < TMAX;   // a full chunk never carries pieces
-    static_assert(!BAL_ || (STAGES == 2 && J == 1), "pieces need 2 stages and one group");
+    static_assert(!BAL_ || STAGES == 2, "pieces need 2 stages");
     int nact_l = 0;   // active columns written by this lane
     static_assert(!HX || J == 1, "half X staging needs one component group");
     constexpr int AStage = TMAX * 16 * kQS * 16;   // A bytes per stage: TMAX tiles x 32 rows
@@ -219,7 +219,9 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int jb = 0; jb < J; ++jb) acc[t][jb] = f4m{0.f, 0.f, 0.f, 0.f};
-    f4m accx0 = f4m{0.f, 0.f, 0.f, 0.f}, accx1 = f4m{0.f, 0.f, 0.f, 0.f};
+    f4m accx0[J], accx1[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) accx0[jb] = accx1[jb] = f4m{0.f, 0.f, 0.f, 0.f};
 
 #pragma unroll
     for (int s = 0; s < STAGES - 1; ++s)
@@ -289,11 +291,15 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
         if (BAL && xe == 0) {
 #pragma unroll
             for (int tm = 0; tm < 4; ++tm)
-                accx0 = __builtin_amdgcn_mfma_f32_16x16x4f32(avx0[tm], xv[0][0][tm], accx0, 0, 0, 0);
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    accx0[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avx0[tm], xv[0][jb][tm], accx0[jb], 0, 0, 0);
         } else if (BAL && xe == 1) {
 #pragma unroll
             for (int tm = 0; tm < 4; ++tm)
-                accx1 = __builtin_amdgcn_mfma_f32_16x16x4f32(avx0[tm], xv[0][0][tm], accx1, 0, 0, 0);
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    accx1[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avx0[tm], xv[0][jb][tm], accx1[jb], 0, 0, 0);
         }
         __builtin_amdgcn_sched_barrier(0);  // the first half's MFMAs stay before the wait
         wait_lgkm0();
@@ -313,11 +319,15 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
         if (BAL && xe == 0) {
 #pragma unroll
             for (int tm = 0; tm < 4; ++tm)
-                accx0 = __builtin_amdgcn_mfma_f32_16x16x4f32(avx1[tm], xv[1][0][tm], accx0, 0, 0, 0);
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    accx0[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avx1[tm], xv[1][jb][tm], accx0[jb], 0, 0, 0);
         } else if (BAL && xe == 1) {
 #pragma unroll
             for (int tm = 0; tm < 4; ++tm)
-                accx1 = __builtin_amdgcn_mfma_f32_16x16x4f32(avx1[tm], xv[1][0][tm], accx1, 0, 0, 0);
+#pragma unroll
+                for (int jb = 0; jb < J; ++jb)
+                    accx1[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avx1[tm], xv[1][jb][tm], accx1[jb], 0, 0, 0);
         }
     }
 
@@ -347,17 +357,23 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
                     int64_t col = (eo == 0 ? xc0 : xc1) + 4 * lk + v;
                     col = (col < pp.n) ? col : pp.n - 1;
                     const float* ac = pp.A + col * pp.lda;
-                    float sv = eo == 0 ? accx0[v] : accx1[v];
-                    for (int r = 4 * nqf; r < p; ++r) sv = __builtin_fmaf(ac[r], xcol[0][r], sv);
-                    if (eo == 0) accx0[v] = sv;
-                    else accx1[v] = sv;
+#pragma unroll
+                    for (int jb = 0; jb < J; ++jb) {
+                        float sv = eo == 0 ? accx0[jb][v] : accx1[jb][v];
+                        for (int r = 4 * nqf; r < p; ++r) sv = __builtin_fmaf(ac[r], xcol[jb][r], sv);
+                        if (eo == 0) accx0[jb][v] = sv;
+                        else accx1[jb][v] = sv;
+                    }
                 }
             }
         }
     }
     if constexpr (BAL) {
-        if (nxp > 0) *reinterpret_cast<f4m*>(xout + 4 * lane) = accx0;
-        if (nxp > 1) *reinterpret_cast<f4m*>(xout + 256 + 4 * lane) = accx1;
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) {
+            if (nxp > 0) *reinterpret_cast<f4m*>(xout + 256 * jb + 4 * lane) = accx0[jb];
+            if (nxp > 1) *reinterpret_cast<f4m*>(xout + 256 * (J + jb) + 4 * lane) = accx1[jb];
+        }
     }
 
     // threshold, S, activity flags
@@ -402,7 +418,7 @@ __device__ __forceinline__ void mfma_chunk(const PassParams& pp, int64_t c0, int
 // rem x nst (tile, stage) pairs, tile-major, are cut into W near-equal
 // contiguous ranges, so every wave streams the same amount of A up to one
 // stage of one tile.  A wave's range covers at most two leftover tiles; their
-// partial sums go to bal.xpart[(2 w + piece) * 256 ..], and k_corr_bal_fix
+// partial sums go to bal.xpart[((2 w + piece) J + group) * 256 ..], and k_corr_bal_fix
 // finishes those tiles.  Without it, W not dividing ntile leaves some waves a
 // whole tile more than others, and they stream it at the end, alone.
 template <int J, int STAGES, int TMAX = 4, bool HX = false, bool BAL = false>
@@ -468,7 +484,7 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
     for (int64_t c0 = cbeg; c0 < cend; c0 += 16 * TMAX) {
         const int64_t left = cend - c0;
         const int nt = left >= 16 * TMAX ? TMAX : (int)((left + 15) / 16);
-#define GPSPCA_CH(NT) mfma_chunk<NT, J, STAGES, TMAX, HX, BAL>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act, xp, nxp, bal.xpart + (size_t)w * 512)
+#define GPSPCA_CH(NT) mfma_chunk<NT, J, STAGES, TMAX, HX, BAL>(pp, c0, cend, lbase, xcol, Xil, f_acc, nnz_acc, S, act, xp, nxp, bal.xpart + (size_t)w * 512 * J)
         if constexpr (TMAX == 8) {
             switch (nt) {
                 case 8: GPSPCA_CH(8); break;
@@ -511,8 +527,9 @@ __global__ __launch_bounds__(64) void k_corr_mfma(PassParams pp, const float* __
 // Leftover tile u of the balanced partition (one wave per tile): the partial
 // sums of its row ranges, in the order of the ranges (ascending wave), then the
 // threshold, S, the activity flags and the objective partials at slot W + u,
-// as k_corr_mfma does for its own tiles (lane l: component l % 16, columns
-// 4 (l / 16) .. + 3 of the tile).
+// as k_corr_mfma does for its own tiles (lane l: component 16 jb + l % 16 of
+// group jb < J, columns 4 (l / 16) .. + 3 of the tile).
+template <int J>
 __global__ __launch_bounds__(64) void k_corr_bal_fix(PassParams pp, BalArgs bal, int W,
                                                      float* __restrict__ S,
                                                      uint8_t* __restrict__ act,
@@ -534,45 +551,57 @@ __global__ __launch_bounds__(64) void k_corr_bal_fix(PassParams pp, BalArgs bal,
     // 16 ranges per round: lane k % 16 works out where range w + k is stored
     // (its loads of all 16 are then issued together and added in range order;
     // ranges past the tile, or empty, re-read range 0 and are not added)
-    f4m acc = f4m{0.f, 0.f, 0.f, 0.f};
+    f4m acc[J];
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) acc[jb] = f4m{0.f, 0.f, 0.f, 0.f};
     for (; w < W && R * w / W < x1; w += 16) {
         const int64_t wk = w + lj;
         const int64_t a = R * wk / W, b = R * (wk + 1) / W;
         const int in_k = (wk < W && a < x1 && a < b) ? 1 : 0;
         const int e_k = (a / nst == u) ? 0 : 1;   // 1: the range began in tile u - 1
-        const int at_k = in_k ? (int)((wk * 2 + e_k) * 64) : 0;   // in f4m units
-        f4m v[16];
+        const int at_k = in_k ? (int)((wk * 2 + e_k) * J * 64) : 0;   // in f4m units
+        f4m v[16][J];
         int in[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             in[k] = __shfl(in_k, k, 64);
             const int at = __shfl(at_k, k, 64);
-            v[k] = reinterpret_cast<const f4m*>(bal.xpart)[at + lane];
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+                v[k][jb] = reinterpret_cast<const f4m*>(bal.xpart)[at + 64 * jb + lane];
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-            if (in[k]) acc += v[k];
+#pragma unroll
+            for (int jb = 0; jb < J; ++jb)
+                if (in[k]) acc[jb] += v[k][jb];
     }
     if (done) return;
     const int64_t n = pp.n, c0 = 16 * ((int64_t)bal.q * W + u);
     const int m = pp.m;
     const bool l0 = pp.l0 != 0;
-    double f = 0.0;
-    int cnt = 0, nact_l = 0;
+    double f[J];
+    int cnt[J], nact_l = 0;
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) { f[jb] = 0.0; cnt[jb] = 0; }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int64_t col = c0 + 4 * lk + v;
         const bool cvalid = col < n;
         bool any = false;
-        if (cvalid && lj < m) {
-            float sv;
-            double fv;
-            if (threshold_m(l0, pp.mu[lj], pp.gam[lj], acc[v], sv, fv)) {
-                f += fv;
-                cnt += 1;
-                any = true;
+#pragma unroll
+        for (int jb = 0; jb < J; ++jb) {
+            const int comp = 16 * jb + lj;
+            if (cvalid && comp < m) {
+                float sv;
+                double fv;
+                if (threshold_m(l0, pp.mu[comp], pp.gam[comp], acc[jb][v], sv, fv)) {
+                    f[jb] += fv;
+                    cnt[jb] += 1;
+                    any = true;
+                }
+                S[col * m + comp] = sv;
             }
-            S[col * m + lj] = sv;
         }
         const uint64_t bal_bits = __ballot(any);
         if (cvalid && lj == 0) {
@@ -581,13 +610,19 @@ __global__ __launch_bounds__(64) void k_corr_bal_fix(PassParams pp, BalArgs bal,
             nact_l += fl;
         }
     }
-    f += __shfl_xor(f, 16, 64);
-    cnt += __shfl_xor(cnt, 16, 64);
-    f += __shfl_xor(f, 32, 64);
-    cnt += __shfl_xor(cnt, 32, 64);
-    if (lane < 16 && lj < m) {
-        fpart[(int64_t)lj * bal.nwp + W + u] = f;
-        nnzpart[(int64_t)lj * bal.nwp + W + u] = cnt;
+#pragma unroll
+    for (int jb = 0; jb < J; ++jb) {
+        double fj = f[jb];
+        int cj = cnt[jb];
+        fj += __shfl_xor(fj, 16, 64);
+        cj += __shfl_xor(cj, 16, 64);
+        fj += __shfl_xor(fj, 32, 64);
+        cj += __shfl_xor(cj, 32, 64);
+        const int comp = 16 * jb + lj;
+        if (lane < 16 && comp < m) {
+            fpart[(int64_t)comp * bal.nwp + W + u] = fj;
+            nnzpart[(int64_t)comp * bal.nwp + W + u] = cj;
+        }
     }
     add_active_count(nact_l, pp.nact);
 }
@@ -1576,6 +1611,8 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
         GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8, true, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (pl.bal && pl.m <= 16 && pl.mfma_stages == 8)
         GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8, false, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
+    else if (pl.bal && pl.m <= 32 && pl.mfma_stages == 8)
+        GPSPCA_LAUNCH_TIMED((k_corr_mfma<2, 2, 8, false, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (hx && pl.mfma_stages == 8)
         GPSPCA_LAUNCH_TIMED((k_corr_mfma<1, 2, 8, true>), grid, block, 0, st, pp, X, Xil, S, act, fpart, nnzpart, ctrl, bal);
     else if (pl.m <= 16 && pl.mfma_stages == 8)
@@ -1595,8 +1632,12 @@ hipError_t launch_corr_mfma(const Plan& pl, const PassParams& pp, const float* X
     if (pl.bal) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_corr_bal_fix, dim3(pl.bal_rem), dim3(64), 0, st, pp, bal,
-                           pl.corr_grid, S, act, fpart, nnzpart, ctrl);
+        if (pl.m <= 16)
+            hipLaunchKernelGGL(k_corr_bal_fix<1>, dim3(pl.bal_rem), dim3(64), 0, st, pp, bal,
+                               pl.corr_grid, S, act, fpart, nnzpart, ctrl);
+        else
+            hipLaunchKernelGGL(k_corr_bal_fix<2>, dim3(pl.bal_rem), dim3(64), 0, st, pp, bal,
+                               pl.corr_grid, S, act, fpart, nnzpart, ctrl);
     }
     return hipGetLastError();
 }

@@ -19,6 +19,9 @@ pytestmark = pytest.mark.gpu
     (O.SL0, 8, 600, 4000, 0),
     (O.SL1, 32, 1001, 3000, 3),
     (O.SL0, 5, 257, 2000, 1),
+    # more tiles of 16 columns than matrix-core waves: the leftover tiles are
+    # split by rows (two component groups)
+    (O.SL1, 32, 300, 20000, 0),
 ])
 def test_path_columns_match_single_solves(gpu, form, K, p, n, lda_extra):
     print(f"\n[path] form={form} K={K} p={p} n={n}", flush=True)

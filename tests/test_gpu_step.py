@@ -189,7 +189,8 @@ def test_matrix_core_two_groups_stage_variants(gpu, stages, m, p, n, monkeypatch
 # waves, so the matrix-core correlation takes q whole tiles per wave and splits
 # the leftover tiles by rows over all waves.  Covers q = 1, 2 and 7, components
 # in one half stage (m <= 8) and a full group (m = 16), ragged row quads, a
-# ragged last tile among the leftover ones, and matrices of 2 row stages.
+# ragged last tile among the leftover ones, matrices of 2 row stages, and two
+# component groups (m = 20, 32).
 BAL_CASES = [
     (O.BL1, 8, 300, 20000, 4, 0),
     (O.BL0, 5, 301, 20000, 4, 3),
@@ -197,6 +198,8 @@ BAL_CASES = [
     (O.BL1, 16, 1000, 9000, 2, 0),
     (O.BL0, 3, 2000, 40003, 4, 0),
     (O.BL1, 8, 129, 30277, 1, 3),
+    (O.BL1, 20, 300, 20000, 4, 0),
+    (O.BL0, 32, 257, 9000, 2, 3),
 ]
 
 
