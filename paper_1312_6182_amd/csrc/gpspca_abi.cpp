@@ -582,19 +582,27 @@ static Prof g_prof;
 
 thread_local KernelEvents g_kev;
 
-struct TimedLaunches {
+// Event pairs of the timed launches, kept for the thread's later solves: a
+// pair is created once, not per solve, so that the first pass of a solve does
+// not wait for the host to create its events.
+struct EventPool {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-    bool on = false;
-    int every = 1;
-    int64_t seen = 0;
-    bool cur = false;   // the current launch is timed
-    ~TimedLaunches() {
-        g_kev = KernelEvents{};
+    ~EventPool() {
         for (auto& e : ev) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
     }
+};
+static thread_local EventPool t_events;
+
+struct TimedLaunches {
+    size_t used = 0;    // pairs of t_events taken by this solve
+    bool on = false;
+    int every = 1;
+    int64_t seen = 0;
+    bool cur = false;   // the current launch is timed
+    ~TimedLaunches() { g_kev = KernelEvents{}; }
     // The correlation launch between begin() and end() records the pair at
     // its own start and end (GPSPCA_LAUNCH_TIMED); an event pair recorded
     // around it measured 9 us more than the kernel's own duration (718.8
@@ -603,14 +611,20 @@ struct TimedLaunches {
         (void)st;
         cur = on && (seen++ % every) == 0;
         if (!cur) return hipSuccess;
-        hipEvent_t a, b;
-        hipError_t e = hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
-        if (e != hipSuccess) return e;
-        e = hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
-        if (e != hipSuccess) return e;
-        ev.emplace_back(a, b);
-        g_kev.start = a;
-        g_kev.stop = b;
+        if (used == t_events.ev.size()) {
+            hipEvent_t a, b;
+            hipError_t e = hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
+            if (e != hipSuccess) return e;
+            e = hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return e;
+            }
+            t_events.ev.emplace_back(a, b);
+        }
+        const auto& pr = t_events.ev[used++];
+        g_kev.start = pr.first;
+        g_kev.stop = pr.second;
         return hipSuccess;
     }
     hipError_t end(hipStream_t st) {
@@ -622,7 +636,8 @@ struct TimedLaunches {
         if (!on) return;
         double tot = 0.0;
         int64_t n = 0;
-        for (auto& e : ev) {
+        for (size_t i = 0; i < used; ++i) {
+            const auto& e = t_events.ev[i];
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
                 tot += ms;
