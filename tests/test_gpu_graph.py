@@ -2,7 +2,8 @@
 same passes enqueued one by one (GPSPCA_GRAPH=0): fixed pass counts and
 tolerance-stopped solves (several replays, with the host's polls of the device
 stop flag in between), on the fused single-unit pass, the matrix-core block
-pass, a gamma path and bfloat16 storage."""
+pass (also with leftover tiles split by rows), a gamma path and bfloat16
+storage."""
 import numpy as np
 import pytest
 import torch
@@ -19,15 +20,20 @@ def _run(gpu, monkeypatch, graph, fn):
     return fn()
 
 
-@pytest.mark.parametrize("case", ["m1", "block", "path", "bf16"])
+@pytest.mark.parametrize("case", ["m1", "block", "block-bal", "path", "bf16"])
 @pytest.mark.parametrize("tol,iters", [(0.0, 21), (1e-6, 400)])
 def test_graph_replay_equals_eager(gpu, monkeypatch, case, tol, iters):
-    A32, _, _ = W.planted_block(900, 7000, 4, 77, k=40)
+    if case == "block-bal":
+        # more tiles of 16 columns than correlation waves: the leftover tiles
+        # are split by rows and finished by a second kernel in every pass
+        A32, _, _ = W.planted_block(300, 20000, 4, 78, k=40)
+    else:
+        A32, _, _ = W.planted_block(900, 7000, 4, 77, k=40)
     Ad = to_device(A32)
     g = W.gamma_absolute(A32.astype(np.float64), False, 0.05)
     if case == "m1":
         fn = lambda: gpu.solve(Ad, 0, 1, g, tol=tol, max_iter=iters)
-    elif case == "block":
+    elif case in ("block", "block-bal"):
         fn = lambda: gpu.solve(Ad, 2, 8, g, tol=tol, max_iter=iters)
     elif case == "path":
         gs = [g * f for f in (0.5, 1.0, 1.5, 2.0, 3.0)]
