@@ -637,9 +637,10 @@ hipError_t launch_reduce_gram(const Plan& pl, const float* gpart, const int* tou
 constexpr int kItems = 3;
 
 // Threads for an m x m Jacobi step: m > 32: 1024 (at most 32 x 33 / 2 blocks
-// of A + 64 x 32 rows of V = 2576 items); m > 16: 512 (at most 648); else 256
-// (at most 164).
-static int jacobi_threads(int m) { return m > 32 ? 1024 : m > 16 ? 512 : 256; }
+// of A + 64 x 32 rows of V = 2576 items); m > 16: 512 (at most 648); m > 8: 256
+// (at most 164); else one wave (at most 42 items and 16 entries of a product,
+// and a barrier of a single wave costs almost nothing).
+static int jacobi_threads(int m) { return m > 32 ? 1024 : m > 16 ? 512 : m > 8 ? 256 : 64; }
 
 __device__ __forceinline__ int jac_pidx(int s, int mm) { return s < mm / 2 ? s : mm - 1 - s; }
 
