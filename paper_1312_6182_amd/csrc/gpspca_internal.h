@@ -15,7 +15,7 @@ namespace gpspca {
 
 constexpr int kMaxM = GPSPCA_MAX_M;
 // rows per workgroup of the single-unit partial reduction (one Gram partial each)
-constexpr int kRm1Rows = 64;
+constexpr int kRm1Rows = 32;
 
 // Device-resident state of one solve.  Written only by single-workgroup
 // kernels (stop test / projection) and by the control reset kernel.

@@ -1318,19 +1318,19 @@ __global__ __launch_bounds__(1024) void k_stop_x1(int nwp, const double* __restr
 
 // m = 1 after the fused pass (one partial g per workgroup, every one written):
 // g = the sum of the partials and the Gram partials of ||g||^2 in one launch.
-// A workgroup owns kRm1Rows rows; wave sl of its kRm1Slices waves sums the
-// contiguous range sl of the partials (all loads of a batch issued together),
-// wave 0 adds the ranges in order, writes g (FP64) and the block's sum of
-// g_r^2 (a fixed butterfly) as gram[3 * block].  Rows past p re-read row
+// A workgroup owns kRm1Rows rows; slice sl (threads sl kRm1Rows .. + kRm1Rows
+// - 1) of its kRm1Slices sums the contiguous range sl of the partials (all
+// loads of a batch issued together), wave 0 adds the ranges in order, writes g
+// (FP64) and the block's sum of g_r^2 (a fixed butterfly) as gram[3 * block].  Rows past p re-read row
 // p - 1 and are dropped.
-constexpr int kRm1Slices = 16, kRm1Batch = 32;
+constexpr int kRm1Slices = 1024 / kRm1Rows, kRm1Batch = 16;
 __global__ __launch_bounds__(1024) void k_reduce_m1(const float* __restrict__ gpart, int npart,
                                                     int ldx, int p, double* __restrict__ g64,
                                                     double* __restrict__ gram,
                                                     const Ctrl* __restrict__ ctrl) {
     if (ctrl->done) return;
     __shared__ double part[kRm1Slices][kRm1Rows];
-    const int t = threadIdx.x, rr = t & 63, sl = t >> 6;
+    const int t = threadIdx.x, rr = t % kRm1Rows, sl = t / kRm1Rows;
     const int r = blockIdx.x * kRm1Rows + rr;
     const int rc = r < p ? r : p - 1;
     const int c0 = (int)((int64_t)npart * sl / kRm1Slices);
@@ -1348,13 +1348,17 @@ __global__ __launch_bounds__(1024) void k_reduce_m1(const float* __restrict__ gp
     }
     part[sl][rr] = s;
     __syncthreads();
-    if (sl == 0) {
-        double g = part[0][rr];
+    if (t < 64) {   // wave 0: lanes t < kRm1Rows finish the rows, the rest add 0
+        const bool own = t < kRm1Rows && r < p;
+        double g = 0.0;
+        if (t < kRm1Rows) {
+            g = part[0][rr];
 #pragma unroll
-        for (int u = 1; u < kRm1Slices; ++u) g += part[u][rr];
-        if (r < p) g64[r] = g;
-        const double g2 = wave_sum_d(r < p ? g * g : 0.0);
-        if (rr == 0) gram[(size_t)3 * blockIdx.x] = g2;
+            for (int u = 1; u < kRm1Slices; ++u) g += part[u][rr];
+        }
+        if (own) g64[r] = g;
+        const double g2 = wave_sum_d(own ? g * g : 0.0);
+        if (t == 0) gram[(size_t)3 * blockIdx.x] = g2;
     }
 }
 
